@@ -1,0 +1,266 @@
+"""CPU oracle for the streaming taches convolution.  TEST INFRASTRUCTURE ONLY.
+
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
+import this module.  It shares no code with the HIP path; the only common
+module is the seeded input generator (``paper_2401_01607_amd.workloads``),
+which holds none of the method's arithmetic.
+
+Four forms of the same computation:
+
+* ``OracleStream`` (O1 FP64, O2 FP32): the paper's buffer algorithm
+  (Section 4.2, TachesAlgorithm), index-corrected, in C (``taches_oracle.c``).
+* ``vector_form`` (O3): the paper's vector algorithm (Section 4.1,
+  TachesAlgorithmVect): a residue array that receives e(n) * h, emits its
+  first element and shifts left with a zero fill, then flushes the temporal
+  overflow.  numpy, FP64.  Small inputs only.
+* ``brute_force`` (O4): Eq. (4) evaluated one output at a time, with exact
+  Python integers / fractions.  Tiny inputs only.
+* ``sampled_outputs``: Eq. (4) for chosen output indices in FP64 with numpy
+  dot products (a library primitive), for full-size parity at sampled points.
+
+Block-IR semantics everywhere: the IR used for the tache of input sample m is
+the one active for the block that holds m (the last one set before that
+block); taches keep the IR that produced them.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from concurrent.futures import ThreadPoolExecutor
+from fractions import Fraction
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+SRC_PATH = os.path.join(HERE, "taches_oracle.c")
+
+OR_FP64, OR_FP32_FMA, OR_FP32_MULADD = 0, 1, 2
+OR_OK, OR_EINVAL, OR_ENOIR, OR_ENOMEM = 0, -1, -2, -3
+
+BUILD_CMD = ["gcc", "-O2", "-fPIC", "-shared", "-ffp-contract=off", "-std=c99",
+             "-o", LIB_PATH, SRC_PATH, "-lm"]
+
+
+def build() -> None:
+    """Compile the C oracle (a checker, built beside the product)."""
+    subprocess.run(BUILD_CMD, check=True)
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_long
+        L.or_open.restype = vp
+        L.or_open.argtypes = [i32, i32, i32, i32]
+        L.or_close.restype = None
+        L.or_close.argtypes = [vp]
+        L.or_set_ir.restype = i32
+        L.or_set_ir.argtypes = [vp, vp, i32]
+        L.or_process.restype = i32
+        L.or_process.argtypes = [vp, vp, vp]
+        L.or_get_residue.restype = i32
+        L.or_get_residue.argtypes = [vp, i32, vp]
+        L.or_run_channel.restype = i32
+        L.or_run_channel.argtypes = [i32, i32, i32, vp, i64, i32, vp, vp, vp, vp]
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+class OracleStream:
+    """Block-by-block oracle stream (O1 / O2).  Mirrors the library's calls:
+    open(B, Lmax, C), set_ir(h), process(x[C][B]) -> y[C][B] (float64)."""
+
+    def __init__(self, block: int, max_ir_len: int, channels: int = 1, prec: int = OR_FP64):
+        self.B, self.Lmax, self.C, self.prec = block, max_ir_len, channels, prec
+        self._h = lib().or_open(block, max_ir_len, channels, prec)
+        if not self._h:
+            raise ValueError("or_open failed")
+
+    def set_ir(self, h: np.ndarray) -> int:
+        h = np.ascontiguousarray(h, dtype=np.float32)
+        return lib().or_set_ir(self._h, _ptr(h), int(h.size))
+
+    def process(self, x: np.ndarray):
+        x = np.ascontiguousarray(np.asarray(x, dtype=np.float32).reshape(self.C, self.B))
+        y = np.zeros((self.C, self.B), dtype=np.float64)
+        rc = lib().or_process(self._h, _ptr(x), _ptr(y))
+        return rc, y
+
+    def residue(self, c: int = 0) -> np.ndarray:
+        out = np.zeros(self.Lmax, dtype=np.float64)
+        lib().or_get_residue(self._h, c, _ptr(out))
+        return out
+
+    def close(self):
+        if self._h:
+            lib().or_close(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _schedule_array(n_blocks: int, schedule) -> np.ndarray:
+    """ir_of_block[b] = IR index set before block b, -1 = no change."""
+    a = np.full(n_blocks, -1, dtype=np.int32)
+    for b, k in schedule:
+        if 0 <= b < n_blocks:
+            a[b] = k
+    return a
+
+
+def run_channel(x: np.ndarray, irs, schedule, block: int, max_ir_len: int,
+                n_blocks: int | None = None, prec: int = OR_FP64) -> np.ndarray:
+    """Whole-signal oracle for one channel: ``n_blocks`` blocks (default: enough
+    for the input plus its temporal overflow), zero input beyond ``x``."""
+    x = np.ascontiguousarray(x, dtype=np.float32).ravel()
+    Lmax_used = max(len(h) for h in irs)
+    if n_blocks is None:
+        n_blocks = -(-(x.size + Lmax_used - 1) // block)
+    irs32 = [np.ascontiguousarray(h, dtype=np.float32) for h in irs]
+    ptrs = (ctypes.c_void_p * len(irs32))(*[h.ctypes.data for h in irs32])
+    lens = np.array([h.size for h in irs32], dtype=np.int32)
+    sched = _schedule_array(n_blocks, schedule)
+    y = np.zeros(n_blocks * block, dtype=np.float64)
+    rc = lib().or_run_channel(block, max_ir_len, prec, _ptr(x), x.size, n_blocks,
+                              ctypes.cast(ptrs, ctypes.c_void_p), _ptr(lens), _ptr(sched), _ptr(y))
+    if rc != OR_OK:
+        raise RuntimeError(f"oracle rc={rc}")
+    return y
+
+
+def run_channels(xs, irs, schedule, block: int, max_ir_len: int, n_blocks=None,
+                 prec: int = OR_FP64, threads: int | None = None):
+    """Run independent channels/streams on host threads (the C calls release
+    the GIL).  ``xs``: list of 1-D signals sharing (irs, schedule)."""
+    threads = threads or min(len(xs), os.cpu_count() or 1)
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        futs = [ex.submit(run_channel, x, irs, schedule, block, max_ir_len, n_blocks, prec) for x in xs]
+        return [f.result() for f in futs]
+
+
+# ---------------------------------------------------------------------------
+# O3: vector form (Section 4.1), FP64, small inputs.
+# ---------------------------------------------------------------------------
+
+def vector_form(e: np.ndarray, h_of_sample) -> np.ndarray:
+    """TachesAlgorithmVect with a per-sample IR.
+
+    ``h_of_sample(n)`` returns the IR for input sample n (the block's IR).
+    The residue has ``Nh`` = longest IR slots.  For each sample: add
+    e(n) * h to the residue, append its first element to the output, shift
+    it left with a zero fill.  After the loop append the first Nh-1 residue
+    elements (the temporal overflow).  Output length Ne + Nh - 1.
+    """
+    e = np.asarray(e, dtype=np.float32)
+    Ne = e.size
+    hs = [np.asarray(h_of_sample(n), dtype=np.float32) for n in range(Ne)]
+    Nh = max(h.size for h in hs)
+    r = np.zeros(Nh, dtype=np.float64)
+    s = []
+    for n in range(Ne):
+        h = hs[n].astype(np.float64)
+        r[: h.size] = r[: h.size] + np.float64(e[n]) * h
+        s.append(r[0])
+        r = np.concatenate([r[1:], [0.0]])
+    s.extend(r[: Nh - 1].tolist())
+    return np.array(s, dtype=np.float64)
+
+
+# ---------------------------------------------------------------------------
+# O4: brute force of Eq. (4), exact arithmetic, tiny inputs.
+# ---------------------------------------------------------------------------
+
+def _exact(v):
+    f = float(v)
+    return int(f) if f.is_integer() else Fraction(f)
+
+
+def brute_force(x: np.ndarray, irs, schedule, block: int, n_out: int):
+    """y[n] = sum over m <= n of x[m] * h_{b(m)}[n - m], exactly.
+
+    ``schedule``: list of (block, ir_index) pairs, as for the streaming calls.
+    Returns a list of exact numbers (int or Fraction)."""
+    x = [_exact(v) for v in np.asarray(x, dtype=np.float32)]
+    irs_e = [[_exact(v) for v in np.asarray(h, dtype=np.float32)] for h in irs]
+    n_blocks = -(-max(n_out, len(x)) // block)
+    act = []
+    cur = None
+    sched = dict(schedule)
+    for b in range(n_blocks):
+        if b in sched:
+            cur = sched[b]
+        act.append(cur)
+    y = []
+    for n in range(n_out):
+        acc = 0
+        for m in range(0, min(n, len(x) - 1) + 1):
+            k = act[m // block]
+            if k is None:
+                continue
+            h = irs_e[k]
+            j = n - m
+            if j < len(h):
+                acc += x[m] * h[j]
+        y.append(acc)
+    return y
+
+
+# ---------------------------------------------------------------------------
+# Sampled outputs of Eq. (4) in FP64 for full-size parity.
+# ---------------------------------------------------------------------------
+
+def sampled_outputs(x: np.ndarray, irs, schedule, block: int, idx) -> np.ndarray:
+    """FP64 values of y[n] for the output indices ``idx`` (one dot product of
+    the input window with the reversed IR per active-IR segment)."""
+    x = np.asarray(x, dtype=np.float32).astype(np.float64)
+    irs64 = [np.asarray(h, dtype=np.float32).astype(np.float64) for h in irs]
+    n_blocks = -(-x.size // block)
+    sched = _schedule_array(n_blocks, schedule)
+    act = np.empty(n_blocks, dtype=np.int64)
+    cur = -1
+    for b in range(n_blocks):
+        if sched[b] >= 0:
+            cur = sched[b]
+        act[b] = cur
+    out = np.zeros(len(idx), dtype=np.float64)
+    for t, n in enumerate(idx):
+        n = int(n)
+        lo = max(0, n - max(h.size for h in irs64) + 1)
+        hi = min(n, x.size - 1)
+        if hi < lo:
+            continue
+        m = np.arange(lo, hi + 1)
+        ks = act[m // block]
+        acc = 0.0
+        for k in np.unique(ks):
+            if k < 0:
+                continue
+            sel = m[ks == k]
+            j = n - sel
+            ok = j < irs64[k].size
+            acc += float(np.dot(x[sel[ok]], irs64[k][j[ok]]))
+        out[t] = acc
+    return out
+
+
+def abs_bound_weights(x: np.ndarray, irs, schedule, block: int, max_ir_len: int, n_blocks=None):
+    """sum_k |h_k| |x_{n-k}| per output (the magnitude the rounding bounds
+    scale with): the same oracle run on absolute values."""
+    return run_channel(np.abs(np.asarray(x, dtype=np.float32)), [np.abs(np.asarray(h, np.float32)) for h in irs],
+                       schedule, block, max_ir_len, n_blocks, OR_FP64)

@@ -1,0 +1,393 @@
+"""Pins for the CPU oracle, checked against what the paper and mathematics fix.
+
+Every pin is written as a function of an implementation
+``impl(x, irs, schedule, B, Lmax, n_out) -> float64[n_out]`` so that the same
+pins run on the buffer-form oracle (O1/O2, C), on the vector-form oracle (O3)
+and on deliberately broken variants of the vector form, which must each fail
+at least one pin.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2401_01607_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------------------
+# implementations under test
+# ---------------------------------------------------------------------------
+
+def impl_o1(x, irs, schedule, B, Lmax, n_out, prec=O.OR_FP64):
+    nb = -(-n_out // B)
+    return O.run_channel(x, irs, schedule, B, Lmax, n_blocks=nb, prec=prec)[:n_out]
+
+
+def impl_o2(x, irs, schedule, B, Lmax, n_out):
+    return impl_o1(x, irs, schedule, B, Lmax, n_out, prec=O.OR_FP32_FMA)
+
+
+def _active_of_sample(schedule, B, n):
+    act = {}
+    cur = None
+    sched = dict(schedule)
+    for b in range(-(-n // B) + 1):
+        if b in sched:
+            cur = sched[b]
+        act[b] = cur
+    return act
+
+
+def impl_o3(x, irs, schedule, B, Lmax, n_out):
+    xx = np.zeros(n_out, dtype=np.float32)
+    xx[: min(len(x), n_out)] = np.asarray(x, np.float32)[:n_out]
+    act = _active_of_sample(schedule, B, n_out)
+    zero = np.zeros(1, np.float32)
+
+    def h_of(n):
+        k = act[n // B]
+        return zero if k is None else irs[k]
+    return O.vector_form(xx, h_of)[:n_out]
+
+
+# Broken variants of the vector form: each is a plausible coding mistake.
+def _vector_mutant(kind):
+    def impl(x, irs, schedule, B, Lmax, n_out):
+        xx = np.zeros(n_out, dtype=np.float32)
+        xx[: min(len(x), n_out)] = np.asarray(x, np.float32)[:n_out]
+        act = _active_of_sample(schedule, B, n_out)
+        if kind == "swap_late":          # IR taken from the previous block
+            act = {b: act.get(b - 1, act[0]) if b > 0 else act[0] for b in act}
+        if kind == "swap_early":         # IR taken from the next block
+            act = {b: act.get(b + 1, act[b]) for b in act}
+        Nh = max(len(h) for h in irs)
+        r = np.zeros(Nh + 1, np.float64)
+        s = []
+        for n in range(n_out):
+            k = act[n // B]
+            h = np.zeros(1) if k is None else np.asarray(irs[k], np.float64)
+            if kind == "drop_last_tap":
+                h = h[:-1]
+            if kind == "sign":
+                r[: h.size] -= np.float64(xx[n]) * h
+            elif kind == "rotated":      # literal index of the printed listing
+                hr = np.roll(h, 1)
+                r[: hr.size] += np.float64(xx[n]) * hr
+            elif kind == "reversed_ir":  # operand read backwards
+                r[: h.size] += np.float64(xx[n]) * h[::-1]
+            else:
+                r[: h.size] += np.float64(xx[n]) * h
+            if kind == "emit_after_shift":
+                r = np.concatenate([r[1:], [0.0]])
+                s.append(r[0])
+            elif kind == "shift_right":
+                s.append(r[0])
+                r = np.concatenate([[0.0], r[:-1]])
+            else:
+                s.append(r[0])
+                r = np.concatenate([r[1:], [0.0]])
+        return np.array(s)
+    return impl
+
+
+MUTANTS = ["swap_late", "swap_early", "drop_last_tap", "sign", "rotated", "reversed_ir",
+           "emit_after_shift", "shift_right"]
+
+
+# ---------------------------------------------------------------------------
+# pins: each returns True when the implementation satisfies it
+# ---------------------------------------------------------------------------
+
+def _read_golden(name):
+    out = {}
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            k, v = line.split(":", 1)
+            out[k.strip()] = v.split()
+    return out
+
+
+def pin_golden_fig5(impl):
+    """Hand-derived worked example of the Fig. 4-6 shape, every block size."""
+    g = _read_golden("fig5_taches_6x3.txt")
+    x = np.array(g["x"], np.float32)
+    h = np.array(g["h"], np.float32)
+    y = np.array(g["y"], np.float64)
+    return all(np.array_equal(impl(x, [h], [(0, 0)], B, 3, 8), y) for B in (1, 2, 3, 4, 6, 8))
+
+
+def pin_golden_swap(impl):
+    """Hand-derived IR swap at the next block."""
+    g = _read_golden("ir_swap_next_block.txt")
+    B = int(g["block"][0])
+    x = np.array(g["x"], np.float32)
+    hA = np.array(g["h_A"], np.float32)
+    hB = np.array(g["h_B"], np.float32)
+    y = np.array(g["y"], np.float64)
+    return np.array_equal(impl(x, [hA, hB], [(0, 0), (1, 1)], B, 2, len(y)), y)
+
+
+def _int_case(seed, n, L1, L2, B, swaps):
+    x = W.signal_int(n, seed)
+    h1 = W.signal_int(L1, seed + 1)
+    h2 = W.signal_int(L2, seed + 2)
+    sched = [(0, 0)] + [(b, (i + 1) % 2) for i, b in enumerate(swaps)]
+    return x, [h1, h2], sched
+
+
+def pin_brute_force(impl):
+    """Exact equality with Eq. (4) summed with Python integers, with swaps,
+    B > L, L = 1, B = 1 and IRs of different lengths."""
+    cases = [(11, 37, 5, 9, 4, [3, 5]), (12, 20, 1, 1, 1, [7]), (13, 25, 3, 3, 8, [1]),
+             (14, 30, 7, 2, 3, [2, 4, 6]), (15, 16, 16, 4, 5, [])]
+    for seed, n, L1, L2, B, swaps in cases:
+        x, irs, sched = _int_case(seed, n, L1, L2, B, swaps)
+        Lmax = max(L1, L2)
+        n_out = n + Lmax + B
+        ref = np.array([float(v) for v in O.brute_force(x, irs, sched, B, n_out)])
+        if not np.array_equal(impl(x, irs, sched, B, Lmax, n_out), ref):
+            return False
+    return True
+
+
+def pin_impulse(impl):
+    """An impulse at d returns h exactly at d .. d+L-1 and zero elsewhere."""
+    L, B = 13, 5
+    h = W.impulse_response(L, 7)
+    for d in (0, B - 1, B, 3 * B + 3):
+        x = np.zeros(d + 1, np.float32)
+        x[d] = 1.0
+        n_out = d + L + 2 * B
+        y = impl(x, [h], [(0, 0)], B, L, n_out)
+        want = np.zeros(n_out)
+        want[d:d + L] = h.astype(np.float64)
+        if not np.array_equal(y, want):
+            return False
+    return True
+
+
+def pin_overflow(impl):
+    """Output is Ne + L - 1 long: exactly zero after that (Section 4.1), and
+    the overflow samples equal numpy.convolve's tail."""
+    x = W.signal_int(23, 3)
+    h = W.signal_int(6, 4)
+    n_out = 23 + 6 - 1 + 9
+    y = impl(x, [h], [(0, 0)], 4, 6, n_out)
+    full = np.convolve(x.astype(np.float64), h.astype(np.float64))
+    return np.array_equal(y[:28], full) and not np.any(y[28:])
+
+
+def pin_swap_decomposition(impl):
+    """y = conv(x*1[m<s], h_old) + conv(x*1[m>=s], h_new) for a swap before
+    block s/B, exactly (integers); moving the swap by one block changes y."""
+    B, n = 4, 24
+    x = W.signal_int(n, 21)
+    ha, hb = W.signal_int(5, 22), W.signal_int(5, 23)
+    s_blk = 3
+    s = s_blk * B
+    n_out = n + 5 - 1
+    y = impl(x, [ha, hb], [(0, 0), (s_blk, 1)], B, 5, n_out)
+    x1 = x.astype(np.float64).copy()
+    x1[s:] = 0
+    x2 = x.astype(np.float64) - x1
+    want = np.convolve(x1, ha.astype(np.float64)) + np.convolve(x2, hb.astype(np.float64))
+    if not np.array_equal(y, want):
+        return False
+    for other in (s_blk - 1, s_blk + 1):
+        if np.array_equal(impl(x, [ha, hb], [(0, 0), (other, 1)], B, 5, n_out), want):
+            return False
+    return True
+
+
+def pin_linearity_shift(impl):
+    """Linearity and time-shift invariance (LTI, Section 3.2), exact with
+    integers: y(a*x1 + b*x2) = a*y(x1) + b*y(x2); y(x delayed by d) = y
+    delayed by d for any d without swaps."""
+    B, L, n = 3, 7, 20
+    h = W.signal_int(L, 31)
+    x1, x2 = W.signal_int(n, 32, amp=10), W.signal_int(n, 33, amp=10)
+    n_out = n + L + 8
+    y1 = impl(x1, [h], [(0, 0)], B, L, n_out)
+    y2 = impl(x2, [h], [(0, 0)], B, L, n_out)
+    y12 = impl((3 * x1 - 2 * x2).astype(np.float32), [h], [(0, 0)], B, L, n_out)
+    if not np.array_equal(y12, 3 * y1 - 2 * y2):
+        return False
+    for d in (1, 2, 5):
+        xd = np.concatenate([np.zeros(d, np.float32), x1])
+        yd = impl(xd, [h], [(0, 0)], B, L, n_out)
+        if not (np.array_equal(yd[d:], y1[: n_out - d]) and not np.any(yd[:d])):
+            return False
+    return True
+
+
+def pin_commutativity(impl):
+    """Exchanging the roles of input and IR gives the same output (Section
+    3.2, Fig. 6), exactly with integers."""
+    x = W.signal_int(6, 41)
+    h = W.signal_int(3, 42)
+    a = impl(x, [h], [(0, 0)], 2, 3, 8)
+    b = impl(h, [x], [(0, 0)], 2, 6, 8)
+    return np.array_equal(a, b)
+
+
+PINS = [pin_golden_fig5, pin_golden_swap, pin_brute_force, pin_impulse, pin_overflow,
+        pin_swap_decomposition, pin_linearity_shift, pin_commutativity]
+
+
+@pytest.mark.parametrize("pin", PINS, ids=lambda p: p.__name__)
+@pytest.mark.parametrize("impl", [impl_o1, impl_o2, impl_o3], ids=["O1_fp64", "O2_fp32", "O3_vector"])
+def test_pin_holds(impl, pin):
+    assert pin(impl)
+
+
+@pytest.mark.parametrize("kind", MUTANTS)
+def test_mutant_is_caught(kind):
+    impl = _vector_mutant(kind)
+    failed = [p.__name__ for p in PINS if not p(impl)]
+    assert failed, f"no pin catches mutant {kind}"
+
+
+def test_unmutated_variant_passes():
+    impl = _vector_mutant("none")
+    assert all(p(impl) for p in PINS)
+
+
+# ---------------------------------------------------------------------------
+# further pins on float inputs
+# ---------------------------------------------------------------------------
+
+def test_o1_matches_numpy_convolve():
+    """Without swaps the method is the direct convolution (Eq. 1), the
+    library routine numpy.convolve, up to FP64 rounding order."""
+    x = W.signal_uniform(3000, 5)
+    h = W.impulse_response(257, 6)
+    y = impl_o1(x, [h], [(0, 0)], 64, 257, 3000 + 256)
+    ref = np.convolve(x.astype(np.float64), h.astype(np.float64))
+    mag = O.abs_bound_weights(x, [h], [(0, 0)], 64, 257)[: ref.size]
+    assert np.all(np.abs(y - ref) <= 2 * 257 * 2.0**-53 * mag + 1e-300)
+
+
+def test_vector_form_bitwise_equals_buffer_form():
+    """Both pseudo-code forms add each output's taches in input order, so in
+    FP64 they agree bit for bit (Sections 4.1 and 4.2)."""
+    x = W.signal_gauss(500, 8)
+    ha, hb = W.impulse_response(40, 9), W.impulse_response(25, 10)
+    sched = [(0, 0), (7, 1), (20, 0)]
+    a = impl_o1(x, [ha, hb], sched, 16, 40, 560)
+    b = impl_o3(x, [ha, hb], sched, 16, 40, 560)
+    assert np.array_equal(a, b)
+
+
+def test_block_size_invariance_bitwise():
+    """Without swaps the block size changes only timing, not the output
+    (Section 5.2, Table 2): each slot receives its taches in input order
+    whatever B is, so FP64 results are bit-identical."""
+    x = W.signal_gauss(2000, 11)
+    h = W.impulse_response(300, 12)
+    ys = [impl_o1(x, [h], [(0, 0)], B, 300, 2400) for B in (1, 7, 64, 256, 2400)]
+    for y in ys[1:]:
+        assert np.array_equal(y, ys[0])
+
+
+def test_zero_block_generates_no_tache():
+    """A zero input adds nothing (Section 3.2): after a zero block the
+    residue equals the previous residue advanced by B, bit for bit."""
+    B, L = 8, 50
+    s = O.OracleStream(B, L, 1)
+    s.set_ir(W.impulse_response(L, 13))
+    s.process(W.signal_gauss(B, 14))
+    before = s.residue()
+    rc, y = s.process(np.zeros(B, np.float32))
+    after = s.residue()
+    assert rc == 0
+    assert np.array_equal(y[0], before[:B])
+    assert np.array_equal(after[: L - B], before[B:])
+    assert not np.any(after[L - B:])
+
+
+def test_process_before_ir_is_enoir():
+    s = O.OracleStream(4, 8, 1)
+    rc, _ = s.process(np.ones(4, np.float32))
+    assert rc == O.OR_ENOIR
+    assert s.set_ir(np.ones(9, np.float32)) == O.OR_EINVAL
+    assert s.set_ir(np.ones(8, np.float32)) == 0
+
+
+def test_last_set_ir_wins():
+    B = 4
+    x = W.signal_int(12, 51)
+    h1, h2 = W.signal_int(3, 52), W.signal_int(3, 53)
+    s = O.OracleStream(B, 3, 1)
+    s.set_ir(h1)
+    s.set_ir(h2)
+    ys = [s.process(x[i:i + B])[1][0] for i in range(0, 12, B)]
+    y = np.concatenate(ys)
+    assert np.array_equal(y, np.convolve(x.astype(np.float64), h2.astype(np.float64))[:12])
+
+
+def test_multichannel_equals_single_channels():
+    B, L, C = 16, 33, 3
+    h = W.impulse_response(L, 61)
+    xs = [W.signal_gauss(64, 62 + c) for c in range(C)]
+    s = O.OracleStream(B, L, C)
+    s.set_ir(h)
+    ys = []
+    for b in range(4):
+        ys.append(s.process(np.stack([xc[b * B:(b + 1) * B] for xc in xs]))[1])
+    y = np.concatenate(ys, axis=1)
+    for c in range(C):
+        assert np.array_equal(y[c], impl_o1(xs[c], [h], [(0, 0)], B, L, 64))
+
+
+def test_printed_listing_literal_index_rotates_ir():
+    """Reading of the buffer listing's index (Section 4.2): taken literally,
+    h(1) lands one slot after the emitted one and an impulse returns the IR
+    rotated by one, [h(Nh), h(1), ...].  The oracle's corrected index returns h."""
+    h = np.array([1.0, 2.0, 3.0, 4.0])
+    Nh = 4
+    r = [0.0] * (Nh + 1)            # 1-based residue
+    r_index = 1
+    out = []
+    for e0 in [1.0, 0.0, 0.0, 0.0]:
+        for i in range(r_index + 1, Nh + 1):
+            r[i] += e0 * h[i - r_index - 1]
+        for i in range(1, r_index + 1):
+            r[i] += e0 * h[Nh - r_index + i - 1]
+        out.append(r[r_index])
+        r[r_index] = 0.0
+        r_index = r_index + 1 if r_index < Nh else 1
+    assert out == [4.0, 1.0, 2.0, 3.0]
+    y = impl_o1(np.array([1, 0, 0, 0], np.float32), [h.astype(np.float32)], [(0, 0)], 1, 4, 4)
+    assert y.tolist() == [1.0, 2.0, 3.0, 4.0]
+
+
+def test_fp32_oracle_within_rounding_bound():
+    """O2 rounds once per multiply-accumulate (Section 5.5's per-MAC
+    requantization).  A chain of k fused MACs is within gamma_k * sum|x h|
+    of the exact sum (gamma_k = k u / (1 - k u), u = 2^-24); O1 is exact up
+    to 2^-53 relative, far below."""
+    x = W.signal_gauss(4000, 71)
+    h = W.impulse_response(2048, 72)
+    n_out = 4000 + 2047
+    y64 = impl_o1(x, [h], [(0, 0)], 128, 2048, n_out)
+    y32 = impl_o2(x, [h], [(0, 0)], 128, 2048, n_out)
+    mag = O.abs_bound_weights(x, [h], [(0, 0)], 128, 2048)[:n_out]
+    u = 2.0**-24
+    gam = 2048 * u / (1 - 2048 * u)
+    assert np.all(np.abs(y32 - y64) <= gam * mag * (1 + 1e-9) + 1e-30)
+    assert np.any(y32 != y64)  # it really is a different precision
+
+
+def test_sampled_outputs_match_full_oracle():
+    spec = W.config2(n=6000, L=3000, block=256, period=1000)
+    y = impl_o1(spec.x[0], spec.irs, spec.schedule, 256, 3000, 6000 + 2999)
+    idx = np.array([0, 1, 255, 256, 999, 1000, 1024, 2999, 3000, 5999, 6000, 8998])
+    s = O.sampled_outputs(spec.x[0], spec.irs, spec.schedule, 256, idx)
+    mag = O.abs_bound_weights(spec.x[0], spec.irs, spec.schedule, 256, 3000)
+    assert np.all(np.abs(s - y[idx]) <= 1e-12 * mag[idx] + 1e-300)
