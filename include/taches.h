@@ -1,0 +1,182 @@
+/*
+ * taches.h — C-ABI of the streaming taches convolution library (libtaches.so)
+ * for AMD MI355X (gfx950).
+ *
+ * The method (Millot & Pelé, AES 2008, Section 3.2, Eq. 4): every input
+ * sample x[m] adds its "tache" x[m] * h[n - m], a scaled and delayed copy of
+ * the impulse response h, to the output; the output is the sum of all
+ * taches.  The buffer form (Section 4.2, algorithm TachesAlgorithm) consumes
+ * the input block by block and keeps the not-yet-emitted part of the sum in
+ * a circular residue, so each output sample is ready as soon as its own
+ * input sample has been consumed.  The impulse response may be replaced
+ * while running; the new one is used for the next samples (Abstract;
+ * Section 6).  Outputs continue for L-1 samples after the last input
+ * (temporal overflow, Section 4.1): drain them by processing zero blocks or
+ * by passing x = NULL to taches_process_blocks.
+ *
+ * Semantics implemented (exactly, up to floating-point summation order):
+ *   y[c][n] = sum over m <= n of x[c][m] * h_{b(m)}[n - m]
+ * where b(m) is the block that holds input sample m and h_b is the IR that
+ * was active for block b (the last one set before that block; taps outside
+ * [0, L_b) are zero).  Taches already started keep the IR that made them.
+ *
+ * Conventions for every call:
+ *   - Sizes are counts of float samples.  Multichannel buffers are planar:
+ *     x[c * B + i] for channel c, sample i of the block (c < channels).
+ *   - "host" pointers are ordinary CPU memory owned by the caller; "device"
+ *     pointers are GPU memory (e.g. from PyTorch) owned by the caller, on the
+ *     stream's device.  The library owns all device memory it allocates (the
+ *     circular tail, IR slots, staging); taches_close frees it.
+ *   - Return value: TACHES_OK (0) or a negative status.  On error nothing is
+ *     written to the caller's output and taches_last_error() returns a
+ *     message (thread-local, valid until the next failing call on the same
+ *     thread).  No call throws across the ABI.
+ *   - A handle is not thread-safe; distinct handles may be used from
+ *     distinct threads.  All device work of a handle is ordered on one HIP
+ *     stream (its own, or the one given with taches_set_hip_stream).
+ */
+#ifndef TACHES_H
+#define TACHES_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define TACHES_OK 0
+#define TACHES_EINVAL (-1)  /* bad size, NULL pointer, bad slot or config   */
+#define TACHES_ENOIR (-2)   /* process before any IR was set                */
+#define TACHES_ENOMEM (-3)  /* device/host allocation or HBM budget failure */
+#define TACHES_EDEVICE (-4) /* a HIP call failed                            */
+#define TACHES_EBUSY (-5)   /* pool: stream attached elsewhere / slots full */
+
+/* ---- precision of the contraction -------------------------------------- */
+#define TACHES_PREC_FP32 0       /* FP32 multiply-add on the vector ALUs      */
+#define TACHES_PREC_SPLIT_BF16 1 /* hi+lo BF16 on MFMA, FP32 accumulation     */
+
+/* ---- type of the circular tail accumulator ----------------------------- */
+#define TACHES_TAIL_AUTO 0 /* FP64 when L >= 2^18 or L/min(B,256) > 4096 */
+#define TACHES_TAIL_FP32 1
+#define TACHES_TAIL_FP64 2
+
+typedef struct taches_stream taches_stream;
+typedef struct taches_pool taches_pool;
+
+typedef struct taches_config {
+  int32_t block_size;          /* B >= 1: samples per channel per block      */
+  int32_t max_ir_len;          /* Lmax >= 1: longest IR this stream accepts  */
+  int32_t channels;            /* C >= 1: channels sharing the IR            */
+  int32_t max_blocks_per_call; /* >= 1: largest n_blocks of process_blocks   */
+  int32_t precision;           /* TACHES_PREC_*                              */
+  int32_t tail;                /* TACHES_TAIL_*                              */
+  int32_t ir_slots;            /* >= 2: device IR slots (for IR schedules)   */
+  int32_t device;              /* HIP device ordinal                         */
+} taches_config;
+
+/* Fill *cfg with defaults: channels 1, one block per call, FP32, AUTO tail,
+ * 2 IR slots, device 0. */
+void taches_config_default(taches_config* cfg, int32_t block_size, int32_t max_ir_len);
+
+/* ---- stream lifetime --------------------------------------------------- */
+
+/* Open a mono FP32 stream (the paper's TachesAlgorithm(pe, h, Nb) with Nb =
+ * block_size, Section 4.2).  Allocates the circular tail of
+ * >= max_ir_len - 1 + block_size slots on device 0 and clears it.
+ * Returns NULL on failure (see taches_last_error). */
+taches_stream* taches_open(int32_t block_size, int32_t max_ir_len);
+
+/* Same with every option.  The tail holds max_ir_len - 1 +
+ * block_size * max_blocks_per_call slots per channel (FP32 or FP64). */
+taches_stream* taches_open_ex(const taches_config* cfg);
+
+/* Wait for the handle's work, free all its device and host memory.  NULL is
+ * a no-op.  Returns TACHES_EBUSY if the stream is attached to a pool. */
+int taches_close(taches_stream* s);
+
+/* Message of the last failure on this thread ("" if none). */
+const char* taches_last_error(void);
+
+/* Order all later device work of this handle on `hip_stream` (a
+ * hipStream_t, e.g. torch.cuda.current_stream().cuda_stream; NULL = the
+ * handle's own stream).  Work already enqueued is first waited for. */
+int taches_set_hip_stream(taches_stream* s, void* hip_stream);
+
+/* Block the host until all device work of the handle is done. */
+int taches_synchronize(taches_stream* s);
+
+/* ---- a1: impulse response staging -------------------------------------- */
+
+/* Queue h[0..L) (host, FP32) as the IR for the next block (Abstract,
+ * Section 6): it becomes active at the first block of the next process
+ * call; blocks already processed keep their taches.  Several calls before
+ * one block: the last wins.  1 <= L <= max_ir_len, else TACHES_EINVAL.
+ * h is copied before return; the caller may reuse it at once. */
+int taches_set_ir(taches_stream* s, const float* h, int32_t L);
+
+/* Same with h on the device (stream-ordered copy; keep h alive until the
+ * handle's stream has passed this point). */
+int taches_set_ir_device(taches_stream* s, const float* h_dev, int32_t L);
+
+/* Load h[0..L) into IR slot `slot` (0 <= slot < ir_slots) for use by an IR
+ * schedule of taches_process_blocks.  h_on_device selects host or device
+ * memory for h.  Loading the active slot is allowed: the copy is ordered
+ * after the work already enqueued, so earlier blocks keep the old IR. */
+int taches_load_ir_slot(taches_stream* s, int32_t slot, const float* h, int32_t L,
+                        int32_t h_on_device);
+
+/* ---- a2..a4: process blocks -------------------------------------------- */
+
+/* One block, host buffers, blocking: x[C*B] in, y[C*B] out.  y[c*B+i] is
+ * the output for the same sample time as x[c*B+i] and already holds that
+ * sample's own tache (zero algorithmic latency, Sections 4.1-4.2). */
+int taches_process(taches_stream* s, const float* x, float* y);
+
+/* One block, device buffers, asynchronous on the handle's stream. */
+int taches_process_async(taches_stream* s, const float* x_dev, float* y_dev);
+
+/* n_blocks consecutive blocks in one launch, device buffers, asynchronous.
+ * x_dev: [C][n_blocks*B] planar (channel stride n_blocks*B), or NULL for
+ * zero input (drains the temporal overflow); y_dev: same shape.
+ * ir_slot_of_block: host array of n_blocks entries or NULL; entry b >= 0
+ * makes that IR slot active from block b on, -1 keeps the current IR.  A
+ * pending taches_set_ir applies before block 0.  The result equals n_blocks
+ * calls of taches_process_async bit for bit. */
+int taches_process_blocks(taches_stream* s, const float* x_dev, float* y_dev, int32_t n_blocks,
+                          const int32_t* ir_slot_of_block);
+
+/* ---- state ------------------------------------------------------------- */
+
+typedef struct taches_info {
+  int32_t block_size, max_ir_len, channels, max_blocks_per_call;
+  int32_t precision;
+  int32_t tail_fp64;     /* 1 if the tail accumulator is FP64 */
+  int32_t ring_slots;    /* circular tail length per channel */
+  int32_t head;          /* slot of the next output sample */
+  int32_t live;          /* slots after head that may hold pending sums */
+  int32_t active_len;    /* length of the active IR, 0 = none */
+  int64_t blocks_done;   /* blocks processed since open */
+  int64_t device_bytes;  /* device memory owned by the handle */
+  int32_t tile_r, tile_w;/* last gather tile config used */
+} taches_info;
+
+int taches_get_info(const taches_stream* s, taches_info* out);
+
+/* Device bytes a stream with this config would own (for HBM admission). */
+int64_t taches_bytes_for(const taches_config* cfg);
+
+/* Copy the pending sums for the next n output samples of channel c into
+ * out[0..n) (host, FP64).  Synchronizes the handle.  Slot k is what the
+ * tail holds for output head+k: the residue of Section 4.2 in output order. */
+int taches_read_tail(taches_stream* s, int32_t channel, double* out, int32_t n);
+
+/* Force the gather tile shape (R outputs per lane in {4, 8, 16}, W waves
+ * per output tile in {1, 2, 4}); 0, 0 = automatic choice per call. */
+int taches_set_tile(taches_stream* s, int32_t r, int32_t w);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TACHES_H */

@@ -1,0 +1,77 @@
+// Internal declarations shared by the runtime and the kernels of libtaches.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "taches.h"
+
+namespace taches {
+
+// Longest run of input samples whose products are summed in FP32 before the
+// sum is added to the tail accumulator.  Each block is cut into
+// ceil(B / CHUNK_MAX) chunks of near-equal length; chunk boundaries depend
+// only on B, so a block gives the same partial sums whether it is processed
+// alone or inside a multi-block call.
+constexpr int CHUNK_MAX = 256;
+
+// IR of one block: device pointer to L FP32 taps (plus BF16 hi/lo copies for
+// the split path).
+struct BlockIR {
+  const float* h;
+  const uint16_t* h_hi;
+  const uint16_t* h_lo;
+  int32_t L;
+  int32_t pad_;
+};
+
+// One stream-call of the gather kernels: n_blocks blocks of one stream.
+//  Outputs n in [0, n_out) are computed relative to the slot at `head`:
+//    acc(n) = tail(n) [if n < live_in] + the partial sums of every chunk of
+//             this call that reaches n, added in chunk order;
+//  n < S:  y[n] = acc(n) (rounded to FP32) and the slot is cleared;
+//  n >= S: the slot keeps acc(n) for later calls.
+struct GatherCall {
+  const float* x;        // [C][x_cstride] planar input, nullptr = all zero
+  float* y;              // [C][y_cstride] planar output
+  void* ring;            // [C][ring_cstride] tail (float or double)
+  const BlockIR* irs;    // per-block IR table (device), nullptr = ir0 for all
+  BlockIR ir0;
+  int64_t x_cstride, y_cstride, ring_cstride;
+  int32_t S;             // input samples of the call = n_blocks * B
+  int32_t B;             // block size
+  int32_t n_blocks;
+  int32_t cpb;           // chunks per block
+  int32_t Rcap;          // ring slots
+  int32_t head;          // ring slot of output n = 0
+  int32_t live_in;       // slots (from head) holding pending sums
+  int32_t n_out;         // outputs to produce (>= S)
+  int32_t Lmax_call;     // longest IR used by the call's blocks
+  int32_t channels;
+};
+
+// One unit of batched work: an output tile of one channel of one call.
+struct WorkItem {
+  int32_t call;    // index into the GatherCall table
+  int32_t channel;
+  int32_t tile;    // output tile index (tile size fixed by the kernel's R)
+  int32_t pad_;
+};
+
+// Kernel launchers (k_gather.hip).  r in {4, 8, 16}, w in {1, 2, 4}.
+hipError_t launch_gather(const GatherCall& call, bool tail_fp64, int r, int w, hipStream_t st);
+hipError_t launch_gather_batched(const GatherCall* calls_dev, const WorkItem* items_dev,
+                                 const int32_t* wg_begin_dev, const int32_t* call_fp64_dev, int n_wg,
+                                 int r, hipStream_t st);
+
+inline int tile_outputs(int r) { return 64 * r; }
+
+// IR staging for the split-BF16 path (k_toeplitz.hip): hi = RN_bf16(h),
+// lo = RN_bf16(h - hi), bit patterns stored as uint16.
+hipError_t launch_split_bf16(const float* h, uint16_t* hi, uint16_t* lo, int L, hipStream_t st);
+
+// Multichannel split-BF16 Toeplitz-block MFMA with FP64 tail (k_toeplitz.hip).
+hipError_t launch_toeplitz(const GatherCall& call, hipStream_t st);
+bool split_supported(const taches_config& cfg);
+
+}  // namespace taches

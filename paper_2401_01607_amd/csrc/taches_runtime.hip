@@ -1,0 +1,525 @@
+// Host runtime and C-ABI of libtaches: stream handles, IR slots, the
+// circular tail, call planning and kernel launches.
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "taches.h"
+#include "taches_internal.h"
+
+using taches::BlockIR;
+using taches::GatherCall;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                        \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess) return fail(TACHES_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+// Tail accumulator type: FP64 when the IR is long (L >= 2^18) or when one
+// output would receive more than 4096 chunk additions in FP32.
+bool want_fp64(const taches_config& c) {
+  if (c.tail == TACHES_TAIL_FP64) return true;
+  if (c.tail == TACHES_TAIL_FP32) return false;
+  const int64_t chunk = std::min<int64_t>(c.block_size, taches::CHUNK_MAX);
+  return c.max_ir_len >= (1 << 18) || (int64_t)c.max_ir_len > 4096 * chunk;
+}
+
+int64_t ring_slots_for(const taches_config& c) {
+  return round_up((int64_t)c.max_ir_len - 1 + (int64_t)c.block_size * c.max_blocks_per_call, 64);
+}
+
+int validate(const taches_config* c) {
+  if (!c) return fail(TACHES_EINVAL, "config is NULL");
+  if (c->block_size < 1 || c->max_ir_len < 1 || c->channels < 1 || c->max_blocks_per_call < 1)
+    return fail(TACHES_EINVAL, "block_size, max_ir_len, channels and max_blocks_per_call must be >= 1");
+  if (c->precision != TACHES_PREC_FP32 && c->precision != TACHES_PREC_SPLIT_BF16)
+    return fail(TACHES_EINVAL, "unknown precision %d", c->precision);
+  if (c->tail < TACHES_TAIL_AUTO || c->tail > TACHES_TAIL_FP64) return fail(TACHES_EINVAL, "unknown tail %d", c->tail);
+  if (c->ir_slots < 2 || c->ir_slots > 64) return fail(TACHES_EINVAL, "ir_slots must be in [2, 64]");
+  const int64_t S = (int64_t)c->block_size * c->max_blocks_per_call;
+  if (S + c->max_ir_len >= (int64_t)1 << 30) return fail(TACHES_EINVAL, "block_size * max_blocks_per_call + max_ir_len too large");
+  if ((int64_t)c->channels * ring_slots_for(*c) >= (int64_t)1 << 34) return fail(TACHES_EINVAL, "tail too large");
+  return TACHES_OK;
+}
+
+struct IrSlot {
+  float* h = nullptr;       // device, Lmax taps
+  uint16_t* hi = nullptr;   // device BF16 hi copy (split precision)
+  uint16_t* lo = nullptr;   // device BF16 lo copy
+  int L = 0;
+  float* staging = nullptr; // pinned host copy source
+  hipEvent_t ev = nullptr;  // completes when the last copy out of staging is done
+  bool ev_pending = false;
+};
+
+}  // namespace
+
+struct taches_stream {
+  taches_config cfg{};
+  bool tail_fp64 = false;
+  int Rcap = 0;
+  void* ring = nullptr;
+  std::vector<IrSlot> slots;
+  int active = -1, pending = -1;
+  int head = 0, live = 0;
+  int64_t blocks_done = 0;
+  hipStream_t own = nullptr, stream = nullptr;
+  float *x_pin = nullptr, *y_pin = nullptr, *x_dev = nullptr, *y_dev = nullptr;
+  BlockIR *irtab_dev = nullptr, *irtab_pin = nullptr;
+  hipEvent_t irtab_ev = nullptr;
+  bool irtab_pending = false;
+  int force_r = 0, force_w = 0, last_r = 0, last_w = 0;
+  int64_t device_bytes = 0;
+  taches_pool* pool = nullptr;
+};
+
+namespace {
+
+void free_stream(taches_stream* s) {
+  if (!s) return;
+  if (s->stream) (void)hipStreamSynchronize(s->stream);
+  (void)hipFree(s->ring);
+  for (auto& sl : s->slots) {
+    (void)hipFree(sl.h);
+    (void)hipFree(sl.hi);
+    (void)hipFree(sl.lo);
+    (void)hipHostFree(sl.staging);
+    if (sl.ev) (void)hipEventDestroy(sl.ev);
+  }
+  (void)hipFree(s->x_dev);
+  (void)hipFree(s->y_dev);
+  (void)hipHostFree(s->x_pin);
+  (void)hipHostFree(s->y_pin);
+  (void)hipFree(s->irtab_dev);
+  (void)hipHostFree(s->irtab_pin);
+  if (s->irtab_ev) (void)hipEventDestroy(s->irtab_ev);
+  if (s->own) (void)hipStreamDestroy(s->own);
+  delete s;
+}
+
+template <typename T>
+int dev_alloc(taches_stream* s, T** p, size_t bytes) {
+  hipError_t e = hipMalloc((void**)p, bytes);
+  if (e != hipSuccess) return fail(TACHES_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+  s->device_bytes += (int64_t)bytes;
+  return TACHES_OK;
+}
+
+template <typename T>
+int host_alloc(T** p, size_t bytes) {
+  hipError_t e = hipHostMalloc((void**)p, bytes, hipHostMallocDefault);
+  if (e != hipSuccess) return fail(TACHES_ENOMEM, "hipHostMalloc(%zu): %s", bytes, hipGetErrorString(e));
+  return TACHES_OK;
+}
+
+int stream_init(taches_stream* s) {
+  const taches_config& c = s->cfg;
+  HIPCHK(hipSetDevice(c.device));
+  HIPCHK(hipStreamCreateWithFlags(&s->own, hipStreamNonBlocking));
+  s->stream = s->own;
+  s->tail_fp64 = want_fp64(c);
+  s->Rcap = (int)ring_slots_for(c);
+  const size_t esz = s->tail_fp64 ? 8 : 4;
+  const size_t ring_bytes = (size_t)c.channels * s->Rcap * esz;
+  int rc;
+  if ((rc = dev_alloc(s, &s->ring, ring_bytes))) return rc;
+  HIPCHK(hipMemsetAsync(s->ring, 0, ring_bytes, s->stream));
+  s->slots.resize(c.ir_slots);
+  for (auto& sl : s->slots) {
+    if ((rc = dev_alloc(s, &sl.h, (size_t)c.max_ir_len * 4))) return rc;
+    if (c.precision == TACHES_PREC_SPLIT_BF16) {
+      if ((rc = dev_alloc(s, &sl.hi, (size_t)c.max_ir_len * 2))) return rc;
+      if ((rc = dev_alloc(s, &sl.lo, (size_t)c.max_ir_len * 2))) return rc;
+    }
+    if ((rc = host_alloc(&sl.staging, (size_t)c.max_ir_len * 4))) return rc;
+    HIPCHK(hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming));
+  }
+  const size_t blk = (size_t)c.channels * c.block_size * 4;
+  if ((rc = dev_alloc(s, &s->x_dev, blk))) return rc;
+  if ((rc = dev_alloc(s, &s->y_dev, blk))) return rc;
+  if ((rc = host_alloc(&s->x_pin, blk))) return rc;
+  if ((rc = host_alloc(&s->y_pin, blk))) return rc;
+  const size_t tab = (size_t)c.max_blocks_per_call * sizeof(BlockIR);
+  if ((rc = dev_alloc(s, &s->irtab_dev, tab))) return rc;
+  if ((rc = host_alloc(&s->irtab_pin, tab))) return rc;
+  HIPCHK(hipEventCreateWithFlags(&s->irtab_ev, hipEventDisableTiming));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  return TACHES_OK;
+}
+
+int load_slot(taches_stream* s, int slot, const float* h, int L, bool on_device) {
+  IrSlot& sl = s->slots[slot];
+  if (on_device) {
+    HIPCHK(hipMemcpyAsync(sl.h, h, (size_t)L * 4, hipMemcpyDeviceToDevice, s->stream));
+  } else {
+    if (sl.ev_pending) {
+      HIPCHK(hipEventSynchronize(sl.ev));
+      sl.ev_pending = false;
+    }
+    std::memcpy(sl.staging, h, (size_t)L * 4);
+    HIPCHK(hipMemcpyAsync(sl.h, sl.staging, (size_t)L * 4, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipEventRecord(sl.ev, s->stream));
+    sl.ev_pending = true;
+  }
+  if (s->cfg.precision == TACHES_PREC_SPLIT_BF16) {
+    hipError_t e = taches::launch_split_bf16(sl.h, sl.hi, sl.lo, L, s->stream);
+    if (e != hipSuccess) return fail(TACHES_EDEVICE, "IR split: %s", hipGetErrorString(e));
+  }
+  sl.L = L;
+  return TACHES_OK;
+}
+
+// Tile shape: prefer long per-lane tiles (fewer LDS reads per FMA) and
+// split the chunks of a tile over several waves only when the call has too
+// few tiles to give every SIMD two waves.
+void pick_tile(const taches_stream* s, int n_out, int chunks_per_tile, int* r, int* w) {
+  if (s->force_r) {
+    *r = s->force_r;
+    *w = s->force_w ? s->force_w : 1;
+    return;
+  }
+  const int64_t target = 2048;
+  static const int cand[9][2] = {{16, 1}, {16, 2}, {16, 4}, {8, 1}, {8, 2}, {8, 4}, {4, 1}, {4, 2}, {4, 4}};
+  for (auto& cw : cand) {
+    const int64_t tiles = (int64_t)s->cfg.channels * ((n_out + 64 * cw[0] - 1) / (64 * cw[0]));
+    if (cw[1] > 1 && chunks_per_tile < 2 * cw[1]) continue;
+    if (tiles * cw[1] >= target) {
+      *r = cw[0];
+      *w = cw[1];
+      return;
+    }
+  }
+  *r = 4;
+  *w = 1;
+}
+
+int process_common(taches_stream* s, const float* x_dev, float* y_dev, int n_blocks, const int32_t* sched) {
+  const taches_config& c = s->cfg;
+  if (n_blocks < 1 || n_blocks > c.max_blocks_per_call)
+    return fail(TACHES_EINVAL, "n_blocks %d outside [1, %d]", n_blocks, c.max_blocks_per_call);
+  if (!y_dev) return fail(TACHES_EINVAL, "y is NULL");
+  if (s->pool) return fail(TACHES_EBUSY, "stream is attached to a pool");
+  // resolve the IR of every block: a pending set_ir applies first, then the schedule
+  int act = s->pending >= 0 ? s->pending : s->active;
+  if (sched) {
+    for (int b = 0; b < n_blocks; ++b) {
+      const int k = sched[b];
+      if (k < -1 || k >= c.ir_slots) return fail(TACHES_EINVAL, "schedule entry %d: slot %d", b, k);
+      if (k >= 0 && s->slots[k].L == 0) return fail(TACHES_ENOIR, "schedule entry %d: slot %d holds no IR", b, k);
+    }
+  }
+  if (x_dev && act < 0 && !(sched && sched[0] >= 0)) return fail(TACHES_ENOIR, "no impulse response set");
+  const int B = c.block_size;
+  const int64_t S = (int64_t)n_blocks * B;
+  bool uniform = true;
+  int first_slot = -1;
+  int Lmax_call = 0;
+  int64_t ext = 0;
+  int cur = act;
+  for (int b = 0; b < n_blocks; ++b) {
+    if (sched && sched[b] >= 0) cur = sched[b];
+    if (b == 0) first_slot = cur;
+    else if (cur != first_slot) uniform = false;
+    if (x_dev && cur >= 0) {
+      const int L = s->slots[cur].L;
+      Lmax_call = std::max(Lmax_call, L);
+      ext = std::max<int64_t>(ext, (int64_t)b * B + B + L - 1);
+    }
+  }
+  if (x_dev && cur < 0) return fail(TACHES_ENOIR, "no impulse response set");
+  const int64_t n_out = std::max<int64_t>(std::max<int64_t>(S, s->live), ext);
+  if (n_out > s->Rcap) return fail(TACHES_EINVAL, "call needs %lld tail slots, ring has %d", (long long)n_out, s->Rcap);
+
+  GatherCall g{};
+  g.x = x_dev;
+  g.y = y_dev;
+  g.ring = s->ring;
+  g.x_cstride = S;
+  g.y_cstride = S;
+  g.ring_cstride = s->Rcap;
+  g.S = (int32_t)S;
+  g.B = B;
+  g.n_blocks = n_blocks;
+  g.cpb = (B + taches::CHUNK_MAX - 1) / taches::CHUNK_MAX;
+  g.Rcap = s->Rcap;
+  g.head = s->head;
+  g.live_in = s->live;
+  g.n_out = (int32_t)n_out;
+  g.Lmax_call = std::max(Lmax_call, 1);
+  g.channels = c.channels;
+  auto ir_of = [&](int k) {
+    BlockIR ir{};
+    if (k >= 0) {
+      ir.h = s->slots[k].h;
+      ir.h_hi = s->slots[k].hi;
+      ir.h_lo = s->slots[k].lo;
+      ir.L = s->slots[k].L;
+    }
+    return ir;
+  };
+  if (!x_dev || uniform) {
+    g.irs = nullptr;
+    g.ir0 = ir_of(first_slot);
+  } else {
+    if (s->irtab_pending) {
+      HIPCHK(hipEventSynchronize(s->irtab_ev));
+      s->irtab_pending = false;
+    }
+    int k = act;
+    for (int b = 0; b < n_blocks; ++b) {
+      if (sched[b] >= 0) k = sched[b];
+      s->irtab_pin[b] = ir_of(k);
+    }
+    HIPCHK(hipMemcpyAsync(s->irtab_dev, s->irtab_pin, (size_t)n_blocks * sizeof(BlockIR), hipMemcpyHostToDevice,
+                          s->stream));
+    HIPCHK(hipEventRecord(s->irtab_ev, s->stream));
+    s->irtab_pending = true;
+    g.irs = s->irtab_dev;
+  }
+
+  if (c.precision == TACHES_PREC_SPLIT_BF16) {
+    hipError_t e = taches::launch_toeplitz(g, s->stream);
+    if (e != hipSuccess) return fail(TACHES_EDEVICE, "toeplitz launch: %s", hipGetErrorString(e));
+    s->last_r = 0;
+    s->last_w = 0;
+  } else {
+    const int span_blocks = (int)std::min<int64_t>(n_blocks, (64 * 16 + g.Lmax_call - 1 + B - 1) / B + 1);
+    int r, w;
+    pick_tile(s, (int)n_out, x_dev ? span_blocks * g.cpb : 0, &r, &w);
+    hipError_t e = taches::launch_gather(g, s->tail_fp64, r, w, s->stream);
+    if (e != hipSuccess) return fail(TACHES_EDEVICE, "gather launch: %s", hipGetErrorString(e));
+    s->last_r = r;
+    s->last_w = w;
+  }
+  // commit the new stream state
+  s->active = cur >= 0 ? cur : act;
+  s->pending = -1;
+  s->head = (int)((s->head + S) % s->Rcap);
+  s->live = (int)(n_out - S);
+  s->blocks_done += n_blocks;
+  return TACHES_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void taches_config_default(taches_config* cfg, int32_t block_size, int32_t max_ir_len) {
+  if (!cfg) return;
+  std::memset(cfg, 0, sizeof *cfg);
+  cfg->block_size = block_size;
+  cfg->max_ir_len = max_ir_len;
+  cfg->channels = 1;
+  cfg->max_blocks_per_call = 1;
+  cfg->precision = TACHES_PREC_FP32;
+  cfg->tail = TACHES_TAIL_AUTO;
+  cfg->ir_slots = 2;
+  cfg->device = 0;
+}
+
+const char* taches_last_error(void) { return g_err.c_str(); }
+
+taches_stream* taches_open_ex(const taches_config* cfg) {
+  if (validate(cfg) != TACHES_OK) return nullptr;
+  if (cfg->precision == TACHES_PREC_SPLIT_BF16 && !taches::split_supported(*cfg)) {
+    fail(TACHES_EINVAL, "split-BF16 path needs channels in [1, 64]");
+    return nullptr;
+  }
+  taches_stream* s = new (std::nothrow) taches_stream();
+  if (!s) {
+    fail(TACHES_ENOMEM, "out of host memory");
+    return nullptr;
+  }
+  s->cfg = *cfg;
+  if (stream_init(s) != TACHES_OK) {
+    std::string keep = g_err;
+    free_stream(s);
+    g_err = keep;
+    return nullptr;
+  }
+  return s;
+}
+
+taches_stream* taches_open(int32_t block_size, int32_t max_ir_len) {
+  taches_config c;
+  taches_config_default(&c, block_size, max_ir_len);
+  return taches_open_ex(&c);
+}
+
+int taches_close(taches_stream* s) {
+  if (!s) return TACHES_OK;
+  if (s->pool) return fail(TACHES_EBUSY, "stream is attached to a pool");
+  free_stream(s);
+  return TACHES_OK;
+}
+
+int taches_set_hip_stream(taches_stream* s, void* hip_stream) {
+  if (!s) return fail(TACHES_EINVAL, "stream is NULL");
+  hipStream_t next = hip_stream ? (hipStream_t)hip_stream : s->own;
+  if (next != s->stream) {
+    HIPCHK(hipStreamSynchronize(s->stream));
+    s->stream = next;
+  }
+  return TACHES_OK;
+}
+
+int taches_synchronize(taches_stream* s) {
+  if (!s) return fail(TACHES_EINVAL, "stream is NULL");
+  HIPCHK(hipStreamSynchronize(s->stream));
+  return TACHES_OK;
+}
+
+static int set_ir_common(taches_stream* s, const float* h, int32_t L, bool on_device) {
+  if (!s) return fail(TACHES_EINVAL, "stream is NULL");
+  if (!h) return fail(TACHES_EINVAL, "h is NULL");
+  if (L < 1 || L > s->cfg.max_ir_len) return fail(TACHES_EINVAL, "L=%d outside [1, %d]", L, s->cfg.max_ir_len);
+  if (s->pool) return fail(TACHES_EBUSY, "stream is attached to a pool; use the pool's IR call");
+  int slot = s->pending;
+  if (slot < 0) {
+    for (int k = 0; k < (int)s->slots.size(); ++k)
+      if (k != s->active) {
+        slot = k;
+        break;
+      }
+  }
+  int rc = load_slot(s, slot, h, L, on_device);
+  if (rc != TACHES_OK) return rc;
+  s->pending = slot;
+  return TACHES_OK;
+}
+
+int taches_set_ir(taches_stream* s, const float* h, int32_t L) { return set_ir_common(s, h, L, false); }
+
+int taches_set_ir_device(taches_stream* s, const float* h_dev, int32_t L) { return set_ir_common(s, h_dev, L, true); }
+
+int taches_load_ir_slot(taches_stream* s, int32_t slot, const float* h, int32_t L, int32_t h_on_device) {
+  if (!s) return fail(TACHES_EINVAL, "stream is NULL");
+  if (slot < 0 || slot >= (int)s->slots.size()) return fail(TACHES_EINVAL, "slot %d outside [0, %zu)", slot, s->slots.size());
+  if (!h) return fail(TACHES_EINVAL, "h is NULL");
+  if (L < 1 || L > s->cfg.max_ir_len) return fail(TACHES_EINVAL, "L=%d outside [1, %d]", L, s->cfg.max_ir_len);
+  if (s->pool) return fail(TACHES_EBUSY, "stream is attached to a pool");
+  if (slot == s->pending) s->pending = -1;
+  return load_slot(s, slot, h, L, h_on_device != 0);
+}
+
+int taches_process(taches_stream* s, const float* x, float* y) {
+  if (!s) return fail(TACHES_EINVAL, "stream is NULL");
+  if (!x || !y) return fail(TACHES_EINVAL, "x or y is NULL");
+  const size_t n = (size_t)s->cfg.channels * s->cfg.block_size;
+  std::memcpy(s->x_pin, x, n * 4);
+  HIPCHK(hipMemcpyAsync(s->x_dev, s->x_pin, n * 4, hipMemcpyHostToDevice, s->stream));
+  int rc = process_common(s, s->x_dev, s->y_dev, 1, nullptr);
+  if (rc != TACHES_OK) {
+    (void)hipStreamSynchronize(s->stream);
+    return rc;
+  }
+  HIPCHK(hipMemcpyAsync(s->y_pin, s->y_dev, n * 4, hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  std::memcpy(y, s->y_pin, n * 4);
+  return TACHES_OK;
+}
+
+int taches_process_async(taches_stream* s, const float* x_dev, float* y_dev) {
+  if (!s) return fail(TACHES_EINVAL, "stream is NULL");
+  if (!x_dev) return fail(TACHES_EINVAL, "x is NULL");
+  return process_common(s, x_dev, y_dev, 1, nullptr);
+}
+
+int taches_process_blocks(taches_stream* s, const float* x_dev, float* y_dev, int32_t n_blocks,
+                          const int32_t* ir_slot_of_block) {
+  if (!s) return fail(TACHES_EINVAL, "stream is NULL");
+  return process_common(s, x_dev, y_dev, n_blocks, ir_slot_of_block);
+}
+
+int taches_get_info(const taches_stream* s, taches_info* out) {
+  if (!s || !out) return fail(TACHES_EINVAL, "NULL argument");
+  std::memset(out, 0, sizeof *out);
+  out->block_size = s->cfg.block_size;
+  out->max_ir_len = s->cfg.max_ir_len;
+  out->channels = s->cfg.channels;
+  out->max_blocks_per_call = s->cfg.max_blocks_per_call;
+  out->precision = s->cfg.precision;
+  out->tail_fp64 = s->tail_fp64 ? 1 : 0;
+  out->ring_slots = s->Rcap;
+  out->head = s->head;
+  out->live = s->live;
+  out->active_len = s->active >= 0 ? s->slots[s->active].L : 0;
+  out->blocks_done = s->blocks_done;
+  out->device_bytes = s->device_bytes;
+  out->tile_r = s->last_r;
+  out->tile_w = s->last_w;
+  return TACHES_OK;
+}
+
+int64_t taches_bytes_for(const taches_config* cfg) {
+  if (validate(cfg) != TACHES_OK) return -1;
+  const int64_t esz = want_fp64(*cfg) ? 8 : 4;
+  int64_t b = (int64_t)cfg->channels * ring_slots_for(*cfg) * esz;
+  b += (int64_t)cfg->ir_slots * cfg->max_ir_len * (cfg->precision == TACHES_PREC_SPLIT_BF16 ? 8 : 4);
+  b += 2 * (int64_t)cfg->channels * cfg->block_size * 4;
+  b += (int64_t)cfg->max_blocks_per_call * (int64_t)sizeof(BlockIR);
+  return b;
+}
+
+int taches_read_tail(taches_stream* s, int32_t channel, double* out, int32_t n) {
+  if (!s || !out) return fail(TACHES_EINVAL, "NULL argument");
+  if (channel < 0 || channel >= s->cfg.channels) return fail(TACHES_EINVAL, "channel %d out of range", channel);
+  if (n < 0 || n > s->Rcap) return fail(TACHES_EINVAL, "n=%d outside [0, %d]", n, s->Rcap);
+  HIPCHK(hipStreamSynchronize(s->stream));
+  const size_t esz = s->tail_fp64 ? 8 : 4;
+  std::vector<unsigned char> buf((size_t)n * esz);
+  const int first = std::min(n, s->Rcap - s->head);
+  const unsigned char* base = (const unsigned char*)s->ring;
+  const int64_t coff = (int64_t)channel * s->Rcap;
+  if (first > 0)
+    HIPCHK(hipMemcpy(buf.data(), base + (coff + s->head) * esz, (size_t)first * esz, hipMemcpyDeviceToHost));
+  if (n > first)
+    HIPCHK(hipMemcpy(buf.data() + (size_t)first * esz, base + coff * esz, (size_t)(n - first) * esz, hipMemcpyDeviceToHost));
+  for (int k = 0; k < n; ++k) {
+    if (s->tail_fp64) {
+      double v;
+      std::memcpy(&v, buf.data() + (size_t)k * 8, 8);
+      out[k] = v;
+    } else {
+      float v;
+      std::memcpy(&v, buf.data() + (size_t)k * 4, 4);
+      out[k] = v;
+    }
+  }
+  return TACHES_OK;
+}
+
+int taches_set_tile(taches_stream* s, int32_t r, int32_t w) {
+  if (!s) return fail(TACHES_EINVAL, "stream is NULL");
+  if (r == 0 && w == 0) {
+    s->force_r = s->force_w = 0;
+    return TACHES_OK;
+  }
+  if ((r != 4 && r != 8 && r != 16) || (w != 1 && w != 2 && w != 4))
+    return fail(TACHES_EINVAL, "tile (%d, %d) not in {4,8,16} x {1,2,4}", r, w);
+  s->force_r = r;
+  s->force_w = w;
+  return TACHES_OK;
+}
+
+}  // extern "C"

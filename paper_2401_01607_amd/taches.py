@@ -1,0 +1,277 @@
+"""Thin Python binding of libtaches (ctypes).  Argument marshalling only:
+every step of the convolution runs in the library's HIP kernels.  PyTorch
+supplies device memory (tensor.data_ptr()) and streams
+(torch.cuda.current_stream().cuda_stream).
+
+The functions keep the C names (taches_open, taches_set_ir, ...); ``Stream``
+wraps a handle for convenience.  Importing this module fails loudly if the
+library has not been built: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch  # loads the HIP runtime first, so the library shares it
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libtaches.so")
+
+TACHES_OK, TACHES_EINVAL, TACHES_ENOIR, TACHES_ENOMEM, TACHES_EDEVICE, TACHES_EBUSY = 0, -1, -2, -3, -4, -5
+TACHES_PREC_FP32, TACHES_PREC_SPLIT_BF16 = 0, 1
+TACHES_TAIL_AUTO, TACHES_TAIL_FP32, TACHES_TAIL_FP64 = 0, 1, 2
+
+STATUS_NAMES = {0: "TACHES_OK", -1: "TACHES_EINVAL", -2: "TACHES_ENOIR", -3: "TACHES_ENOMEM",
+                -4: "TACHES_EDEVICE", -5: "TACHES_EBUSY"}
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                      "(or python -m paper_2401_01607_amd.build)")
+
+lib = ctypes.CDLL(LIB_PATH)
+
+
+class taches_config(ctypes.Structure):
+    _fields_ = [("block_size", ctypes.c_int32), ("max_ir_len", ctypes.c_int32),
+                ("channels", ctypes.c_int32), ("max_blocks_per_call", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("tail", ctypes.c_int32),
+                ("ir_slots", ctypes.c_int32), ("device", ctypes.c_int32)]
+
+
+class taches_info(ctypes.Structure):
+    _fields_ = [("block_size", ctypes.c_int32), ("max_ir_len", ctypes.c_int32),
+                ("channels", ctypes.c_int32), ("max_blocks_per_call", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("tail_fp64", ctypes.c_int32),
+                ("ring_slots", ctypes.c_int32), ("head", ctypes.c_int32), ("live", ctypes.c_int32),
+                ("active_len", ctypes.c_int32), ("blocks_done", ctypes.c_int64),
+                ("device_bytes", ctypes.c_int64), ("tile_r", ctypes.c_int32), ("tile_w", ctypes.c_int32)]
+
+
+_vp, _i32, _i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+_P = ctypes.POINTER
+_SIGS = {
+    "taches_config_default": (None, [_P(taches_config), _i32, _i32]),
+    "taches_open": (_vp, [_i32, _i32]),
+    "taches_open_ex": (_vp, [_P(taches_config)]),
+    "taches_close": (ctypes.c_int, [_vp]),
+    "taches_last_error": (ctypes.c_char_p, []),
+    "taches_set_hip_stream": (ctypes.c_int, [_vp, _vp]),
+    "taches_synchronize": (ctypes.c_int, [_vp]),
+    "taches_set_ir": (ctypes.c_int, [_vp, _vp, _i32]),
+    "taches_set_ir_device": (ctypes.c_int, [_vp, _vp, _i32]),
+    "taches_load_ir_slot": (ctypes.c_int, [_vp, _i32, _vp, _i32, _i32]),
+    "taches_process": (ctypes.c_int, [_vp, _vp, _vp]),
+    "taches_process_async": (ctypes.c_int, [_vp, _vp, _vp]),
+    "taches_process_blocks": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp]),
+    "taches_get_info": (ctypes.c_int, [_vp, _P(taches_info)]),
+    "taches_bytes_for": (_i64, [_P(taches_config)]),
+    "taches_read_tail": (ctypes.c_int, [_vp, _i32, _vp, _i32]),
+    "taches_set_tile": (ctypes.c_int, [_vp, _i32, _i32]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+class TachesError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = lib.taches_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {msg}")
+
+
+def _check(rc: int, where: str) -> int:
+    if rc != TACHES_OK:
+        raise TachesError(rc, where)
+    return rc
+
+
+def _host_ptr(a: np.ndarray):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def _dev_ptr(t):
+    if t is None:
+        return None
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise TypeError("expected a contiguous float32 CUDA tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+# ---- same-name wrappers -----------------------------------------------------
+
+def taches_config_default(block_size: int, max_ir_len: int) -> taches_config:
+    c = taches_config()
+    lib.taches_config_default(ctypes.byref(c), block_size, max_ir_len)
+    return c
+
+
+def taches_open(block_size: int, max_ir_len: int):
+    h = lib.taches_open(block_size, max_ir_len)
+    if not h:
+        raise TachesError(TACHES_EINVAL, "taches_open")
+    return h
+
+
+def taches_open_ex(cfg: taches_config):
+    h = lib.taches_open_ex(ctypes.byref(cfg))
+    if not h:
+        raise TachesError(TACHES_EINVAL, "taches_open_ex")
+    return h
+
+
+def taches_close(s) -> int:
+    return lib.taches_close(s)
+
+
+def taches_set_ir(s, h: np.ndarray) -> int:
+    h = np.ascontiguousarray(h, dtype=np.float32)
+    return lib.taches_set_ir(s, _host_ptr(h), int(h.size))
+
+
+def taches_set_ir_device(s, h_dev) -> int:
+    return lib.taches_set_ir_device(s, _dev_ptr(h_dev), int(h_dev.numel()))
+
+
+def taches_load_ir_slot(s, slot: int, h) -> int:
+    if isinstance(h, torch.Tensor):
+        return lib.taches_load_ir_slot(s, slot, _dev_ptr(h), int(h.numel()), 1)
+    h = np.ascontiguousarray(h, dtype=np.float32)
+    return lib.taches_load_ir_slot(s, slot, _host_ptr(h), int(h.size), 0)
+
+
+def taches_process(s, x: np.ndarray, y: np.ndarray) -> int:
+    return lib.taches_process(s, _host_ptr(x), _host_ptr(y))
+
+
+def taches_process_async(s, x_dev, y_dev) -> int:
+    return lib.taches_process_async(s, _dev_ptr(x_dev), _dev_ptr(y_dev))
+
+
+def taches_process_blocks(s, x_dev, y_dev, n_blocks: int, ir_slot_of_block=None) -> int:
+    sched = None
+    if ir_slot_of_block is not None:
+        sched = np.ascontiguousarray(ir_slot_of_block, dtype=np.int32)
+        if sched.size != n_blocks:
+            raise ValueError("ir_slot_of_block must have n_blocks entries")
+    return lib.taches_process_blocks(s, _dev_ptr(x_dev), _dev_ptr(y_dev), n_blocks,
+                                     None if sched is None else _host_ptr(sched))
+
+
+def taches_get_info(s) -> taches_info:
+    info = taches_info()
+    _check(lib.taches_get_info(s, ctypes.byref(info)), "taches_get_info")
+    return info
+
+
+def taches_bytes_for(cfg: taches_config) -> int:
+    return int(lib.taches_bytes_for(ctypes.byref(cfg)))
+
+
+def taches_read_tail(s, channel: int, n: int) -> np.ndarray:
+    out = np.zeros(n, dtype=np.float64)
+    _check(lib.taches_read_tail(s, channel, _host_ptr(out), n), "taches_read_tail")
+    return out
+
+
+def taches_set_tile(s, r: int, w: int) -> int:
+    return lib.taches_set_tile(s, r, w)
+
+
+def taches_set_hip_stream(s, stream=None) -> int:
+    ptr = None if stream is None else ctypes.c_void_p(stream)
+    return lib.taches_set_hip_stream(s, ptr)
+
+
+def taches_synchronize(s) -> int:
+    return lib.taches_synchronize(s)
+
+
+def taches_last_error() -> str:
+    return lib.taches_last_error().decode(errors="replace")
+
+
+# ---- convenience wrapper ------------------------------------------------------
+
+class Stream:
+    """One taches stream (a handle).  Raises TachesError on any failure."""
+
+    def __init__(self, block_size: int, max_ir_len: int, channels: int = 1, max_blocks_per_call: int = 1,
+                 precision: int = TACHES_PREC_FP32, tail: int = TACHES_TAIL_AUTO, ir_slots: int = 2,
+                 device: int = 0, torch_stream: bool = True):
+        cfg = taches_config_default(block_size, max_ir_len)
+        cfg.channels = channels
+        cfg.max_blocks_per_call = max_blocks_per_call
+        cfg.precision = precision
+        cfg.tail = tail
+        cfg.ir_slots = ir_slots
+        cfg.device = device
+        self.cfg = cfg
+        self.h = taches_open_ex(cfg)
+        if torch_stream:
+            _check(taches_set_hip_stream(self.h, torch.cuda.current_stream(device).cuda_stream),
+                   "taches_set_hip_stream")
+
+    @property
+    def B(self) -> int:
+        return self.cfg.block_size
+
+    @property
+    def C(self) -> int:
+        return self.cfg.channels
+
+    def set_ir(self, h) -> None:
+        if isinstance(h, torch.Tensor):
+            _check(taches_set_ir_device(self.h, h), "taches_set_ir_device")
+        else:
+            _check(taches_set_ir(self.h, h), "taches_set_ir")
+
+    def load_ir_slot(self, slot: int, h) -> None:
+        _check(taches_load_ir_slot(self.h, slot, h), "taches_load_ir_slot")
+
+    def process(self, x: np.ndarray) -> np.ndarray:
+        x = np.ascontiguousarray(x, dtype=np.float32).reshape(self.C, self.B)
+        y = np.zeros_like(x)
+        _check(taches_process(self.h, x, y), "taches_process")
+        return y
+
+    def process_async(self, x_dev, y_dev) -> None:
+        _check(taches_process_async(self.h, x_dev, y_dev), "taches_process_async")
+
+    def process_blocks(self, x_dev, y_dev, n_blocks: int, ir_slot_of_block=None) -> None:
+        _check(taches_process_blocks(self.h, x_dev, y_dev, n_blocks, ir_slot_of_block), "taches_process_blocks")
+
+    def info(self) -> taches_info:
+        return taches_get_info(self.h)
+
+    def read_tail(self, channel: int = 0, n: int | None = None) -> np.ndarray:
+        if n is None:
+            n = self.info().ring_slots
+        return taches_read_tail(self.h, channel, n)
+
+    def set_tile(self, r: int, w: int) -> None:
+        _check(taches_set_tile(self.h, r, w), "taches_set_tile")
+
+    def synchronize(self) -> None:
+        _check(taches_synchronize(self.h), "taches_synchronize")
+
+    def close(self) -> None:
+        if self.h:
+            _check(taches_close(self.h), "taches_close")
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            if self.h:
+                lib.taches_close(self.h)
+                self.h = None
+        except Exception:
+            pass

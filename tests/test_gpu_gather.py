@@ -1,0 +1,199 @@
+"""Parity of the FP32 gather path (K1, and K1d with the FP64 tail) with the
+CPU oracle, through the C-ABI.  Tolerance for float inputs:
+max |y_gpu - y_fp64_oracle| <= 1e-5 * RMS(y_fp64_oracle); integer-valued
+inputs (every partial sum exact) must match bit for bit."""
+import numpy as np
+import pytest
+
+from paper_2401_01607_amd import workloads as W
+from tests.gpu_harness import gpu_multi_block, gpu_per_block, oracle_run, rel_err
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+INT_CASES = [
+    # B, L1, L2, n, swap blocks
+    (1, 1, 1, 20, [5]),
+    (2, 3, 5, 50, [3, 10]),
+    (3, 7, 2, 40, [4]),
+    (5, 16, 16, 100, []),
+    (8, 100, 37, 500, [10, 20, 30]),
+    (64, 10, 10, 300, [1]),          # B > L
+    (64, 1000, 500, 5000, [7, 40]),
+    (300, 700, 1200, 4000, [3, 5]),  # B not a power of two, two chunks per block
+    (513, 2000, 64, 6000, [2]),      # three chunks per block
+]
+
+
+def _int_case(B, L1, L2, n, swaps, seed=1):
+    amp = 31 if max(L1, L2) > 1000 else 100
+    x = W.signal_int(n, seed, amp)
+    irs = [W.signal_int(L1, seed + 1, amp), W.signal_int(L2, seed + 2, amp)]
+    sched = [(0, 0)] + [(b, (i + 1) % 2) for i, b in enumerate(swaps)]
+    Lmax = max(L1, L2)
+    n_blocks = -(-(n + Lmax) // B) + 1
+    return x, irs, sched, Lmax, n_blocks
+
+
+@pytest.mark.parametrize("case", INT_CASES, ids=[f"B{c[0]}_L{c[1]}-{c[2]}" for c in INT_CASES])
+def test_integer_inputs_bitwise(case):
+    x, irs, sched, Lmax, nb = _int_case(*case)
+    B = case[0]
+    ref = oracle_run(x, irs, sched, B, Lmax, nb)
+    y1, _ = gpu_per_block(x, irs, sched, B, Lmax, nb)
+    assert np.array_equal(y1, ref)
+    y2, _ = gpu_multi_block(x, irs, sched, B, Lmax, nb)
+    assert np.array_equal(y2, ref)
+    y3, _ = gpu_multi_block(x, irs, sched, B, Lmax, nb, tail=2)  # FP64 tail
+    assert np.array_equal(y3, ref)
+
+
+def test_host_blocking_path_bitwise():
+    x, irs, sched, Lmax, nb = _int_case(*INT_CASES[6])
+    ref = oracle_run(x, irs, sched, 64, Lmax, nb)
+    y, _ = gpu_per_block(x, irs, sched, 64, Lmax, nb, host_io=True)
+    assert np.array_equal(y, ref)
+
+
+def test_config1_parity_and_modes_agree():
+    """Plain taches, 48 000 uniform samples, L = 1024, B = 64 (plus drain)."""
+    spec = W.config1()
+    B, L = spec.block, spec.max_ir_len
+    nb = -(-(spec.n_samples + L - 1) // B)
+    ref = oracle_run(spec.x, spec.irs, spec.schedule, B, L, nb)
+    y1, i1 = gpu_per_block(spec.x, spec.irs, spec.schedule, B, L, nb)
+    assert rel_err(y1, ref) <= TOL
+    y2, _ = gpu_multi_block(spec.x, spec.irs, spec.schedule, B, L, nb)
+    assert np.array_equal(y1, y2), "per-block and multi-block calls must agree bit for bit"
+    y3, _ = gpu_multi_block(spec.x, spec.irs, spec.schedule, B, L, nb, calls=7)
+    assert np.array_equal(y1, y3)
+    assert i1.tail_fp64 == 0
+
+
+@pytest.mark.parametrize("tile", [(4, 1), (4, 2), (4, 4), (8, 1), (8, 2), (8, 4), (16, 1), (16, 2), (16, 4)])
+def test_every_tile_shape_gives_the_same_bits(tile):
+    spec = W.config2(n=20_000, L=5000, block=256, period=4800)
+    nb = -(-(spec.n_samples + 4999) // 256)
+    base, _ = gpu_multi_block(spec.x, spec.irs, spec.schedule, 256, 5000, nb, tile=(16, 1))
+    y, info = gpu_multi_block(spec.x, spec.irs, spec.schedule, 256, 5000, nb, tile=tile)
+    assert (info.tile_r, info.tile_w) == tile
+    assert np.array_equal(y, base)
+
+
+def test_config2_reduced_parity_with_swaps():
+    """Config-2 shape (L = 65 536, B = 256, IR swapped every 4800 samples)
+    on the first second of input, plus the full temporal overflow."""
+    spec = W.config2(n=48_000)
+    B, L = 256, 65_536
+    nb = -(-(spec.n_samples + L - 1) // B)
+    ref = oracle_run(spec.x, spec.irs, spec.schedule, B, L, nb)
+    y, info = gpu_multi_block(spec.x, spec.irs, spec.schedule, B, L, nb)
+    assert rel_err(y, ref) <= TOL
+    yb, _ = gpu_per_block(spec.x, spec.irs, spec.schedule, B, L, nb)
+    assert np.array_equal(y, yb)
+    # the FP64 tail is at least as accurate
+    y64, _ = gpu_multi_block(spec.x, spec.irs, spec.schedule, B, L, nb, tail=2)
+    assert rel_err(y64, ref) <= rel_err(y, ref) + 1e-9
+
+
+def test_swap_one_block_off_differs():
+    spec = W.config2(n=12_000, L=2000, block=256, period=4800)
+    nb = -(-(12_000 + 1999) // 256)
+    y, _ = gpu_multi_block(spec.x, spec.irs, spec.schedule, 256, 2000, nb)
+    shifted = [(b + 1 if b > 0 else 0, k) for b, k in spec.schedule]
+    ref_shift = oracle_run(spec.x, spec.irs, shifted, 256, 2000, nb)
+    assert rel_err(y, ref_shift) > 1e-2
+
+
+def test_impulse_returns_h_exactly():
+    h = W.impulse_response(3000, 5)
+    for d in (0, 255, 256, 3 * 256 + 3):
+        x = np.zeros(d + 1, np.float32)
+        x[d] = 1.0
+        nb = -(-(d + 3000) // 256) + 1
+        y, _ = gpu_multi_block(x, [h], [(0, 0)], 256, 3000, nb)
+        want = np.zeros(nb * 256, np.float32)
+        want[d:d + 3000] = h
+        assert np.array_equal(y[0], want)
+
+
+def test_drain_with_null_input_and_exact_zero_after_overflow():
+    x = W.signal_int(1000, 9, 50)
+    h = W.signal_int(700, 10, 50)
+    B = 128
+    nb_in = -(-1000 // B)
+    nb_drain = -(-699 // B) + 2
+    ref = oracle_run(x, [h], [(0, 0)], B, 700, nb_in + nb_drain)
+    import torch
+    from tests.gpu_harness import binding
+    T = binding()
+    s = T.Stream(B, 700, max_blocks_per_call=nb_drain)
+    s.set_ir(h)
+    xp = np.zeros(nb_in * B, np.float32)
+    xp[:1000] = x
+    xd = torch.from_numpy(xp).cuda()[None]
+    y1 = torch.empty_like(xd)
+    s.process_blocks(xd, y1, nb_in)
+    y2 = torch.empty((1, nb_drain * B), device="cuda")
+    s.process_blocks(None, y2, nb_drain)
+    y = torch.cat([y1, y2], 1).cpu().numpy()[0]
+    assert np.array_equal(y, ref[0])
+    assert not np.any(y[1000 + 699:])
+    assert s.info().live == 0
+
+
+def test_tail_state_matches_oracle_residue():
+    """After a few blocks the device tail equals the oracle's residue in
+    output order (Section 4.2's r, read from the current index on)."""
+    from oracle import oracle as O
+    from tests.gpu_harness import binding
+    T = binding()
+    B, L = 64, 500
+    x = W.signal_int(5 * B, 3, 100)
+    h = W.signal_int(L, 4, 100)
+    o = O.OracleStream(B, L, 1)
+    o.set_ir(h)
+    s = T.Stream(B, L)
+    s.set_ir(h)
+    for b in range(5):
+        o.process(x[b * B:(b + 1) * B])
+        s.process(x[b * B:(b + 1) * B])
+    assert np.array_equal(s.read_tail(0, L), o.residue(0))
+
+
+def test_multichannel_fp32_matches_per_channel_oracle():
+    C, B, L, n = 5, 128, 3000, 6000
+    x = np.stack([W.signal_gauss(n, 100 + c) for c in range(C)])
+    h = W.impulse_response(L, 99)
+    nb = -(-(n + L - 1) // B)
+    ref = oracle_run(x, [h], [(0, 0)], B, L, nb)
+    y, _ = gpu_multi_block(x, [h], [(0, 0)], B, L, nb)
+    for c in range(C):
+        assert rel_err(y[c], ref[c]) <= TOL
+    yb, _ = gpu_per_block(x, [h], [(0, 0)], B, L, nb)
+    assert np.array_equal(y, yb)
+
+
+def test_flat_white_noise_ir_parity():
+    """The paper's IRs are flat white noise (Section 5.1), the worst case."""
+    x = W.signal_gauss(20_000, 21)
+    h = W.impulse_response(16_384, 22, decay=0.0)
+    nb = -(-(20_000 + 16_383) // 256)
+    ref = oracle_run(x, [h], [(0, 0)], 256, 16_384, nb)
+    y, _ = gpu_multi_block(x, [h], [(0, 0)], 256, 16_384, nb)
+    assert rel_err(y, ref) <= TOL
+
+
+def test_long_ir_auto_picks_fp64_tail():
+    from tests.gpu_harness import binding
+    T = binding()
+    s = T.Stream(512, 1 << 18)
+    assert s.info().tail_fp64 == 1
+    s.close()
+    s = T.Stream(32, 131_072)
+    assert s.info().tail_fp64 == 0
+    s.close()
+    s = T.Stream(32, 131_073)
+    assert s.info().tail_fp64 == 1
+    s.close()
