@@ -171,7 +171,7 @@ int64_t taches_bytes_for(const taches_config* cfg);
  * tail holds for output head+k: the residue of Section 4.2 in output order. */
 int taches_read_tail(taches_stream* s, int32_t channel, double* out, int32_t n);
 
-/* Force the gather tile shape (R outputs per lane in {4, 8, 16}, W waves
+/* Force the gather tile shape (R outputs per lane in {4, 8, 12, 16}, W waves
  * per output tile in {1, 2, 4}); 0, 0 = automatic choice per call. */
 int taches_set_tile(taches_stream* s, int32_t r, int32_t w);
 

@@ -19,8 +19,8 @@
 // lane keeps two R-tap windows of h in registers; for each group of R input
 // samples it loads one new window (R/4 ds_read_b128) and the group's R
 // input samples (uniform ds_read_b128 broadcasts), then issues R*R FMAs.
-// The LDS copy of h inserts 4 pad floats after every R floats so that the
-// lanes' 16-byte window reads fall in distinct banks.
+// The LDS copy of h pads every R-float row so that the lanes' 16-byte
+// window reads fall in distinct banks.
 #include "taches_internal.h"
 
 namespace taches {
@@ -28,15 +28,20 @@ namespace {
 
 template <int R>
 struct Geo {
-  static constexpr int T = 64 * R;                    // outputs per wave tile
-  static constexpr int NW = T + CHUNK_MAX;            // staged taps (max)
-  static constexpr int HF = (NW / R) * (R + 4);       // padded LDS floats for h
-  static constexpr int WF = HF + CHUNK_MAX;           // + input samples
+  static_assert(R % 4 == 0, "R must be a multiple of 4");
+  static constexpr int T = 64 * R;                           // outputs per wave tile
+  static constexpr int LP = (CHUNK_MAX + R - 1) / R * R;     // longest padded chunk
+  static constexpr int NW = T + LP;                          // staged taps (max)
+  // padded floats per R-tap window row: a multiple of 4 with an odd number of
+  // 16-byte units, so the 16-byte reads of consecutive lanes hit distinct banks
+  static constexpr int ROW = ((R + 4) / 4) % 2 == 1 ? R + 4 : R + 8;
+  static constexpr int HF = (NW / R) * ROW;                  // LDS floats for h
+  static constexpr int WF = HF + LP;                         // + input samples
 };
 
 template <int R>
 __device__ __forceinline__ int hphys(int i) {
-  return (int)(((unsigned)i / R) * (R + 4) + ((unsigned)i % R));
+  return (int)(((unsigned)i / R) * Geo<R>::ROW + ((unsigned)i % R));
 }
 
 // Map the launch order of workgroups to tiles so that consecutive tiles run
@@ -100,7 +105,7 @@ __device__ __forceinline__ void fma_group(const float (&xv)[R], const float (&A)
 template <int R>
 __device__ __forceinline__ void chunk_compute(const float* hs, const float* xs, int lane,
                                               int len_pad, float (&p)[R]) {
-  constexpr int ROW = R + 4;  // padded floats per window
+  constexpr int ROW = Geo<R>::ROW;
   const int G = len_pad / R;   // wave-uniform
   const float* wl = hs + lane * ROW;
   float X[R], Y[R], xv[R];
@@ -301,6 +306,14 @@ hipError_t launch_r(const GatherCall& call, bool fp64, int w, hipStream_t st) {
   }
 }
 
+template <int R>
+hipError_t launch_batched_r(const GatherCall* calls_dev, const WorkItem* items_dev, const int32_t* wg_begin_dev,
+                            const int32_t* call_fp64_dev, int n_wg, hipStream_t st) {
+  hipLaunchKernelGGL(k_gather_batched<R>, dim3(n_wg), dim3(64), 0, st, calls_dev, items_dev, wg_begin_dev,
+                     call_fp64_dev);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_gather(const GatherCall& call, bool tail_fp64, int r, int w, hipStream_t st) {
@@ -308,6 +321,7 @@ hipError_t launch_gather(const GatherCall& call, bool tail_fp64, int r, int w, h
   switch (r) {
     case 4: return launch_r<4>(call, tail_fp64, w, st);
     case 8: return launch_r<8>(call, tail_fp64, w, st);
+    case 12: return launch_r<12>(call, tail_fp64, w, st);
     case 16: return launch_r<16>(call, tail_fp64, w, st);
     default: return hipErrorInvalidValue;
   }
@@ -318,18 +332,12 @@ hipError_t launch_gather_batched(const GatherCall* calls_dev, const WorkItem* it
                                  int r, hipStream_t st) {
   if (n_wg <= 0) return hipSuccess;
   switch (r) {
-    case 4:
-      hipLaunchKernelGGL(k_gather_batched<4>, dim3(n_wg), dim3(64), 0, st, calls_dev, items_dev, wg_begin_dev, call_fp64_dev);
-      break;
-    case 8:
-      hipLaunchKernelGGL(k_gather_batched<8>, dim3(n_wg), dim3(64), 0, st, calls_dev, items_dev, wg_begin_dev, call_fp64_dev);
-      break;
-    case 16:
-      hipLaunchKernelGGL(k_gather_batched<16>, dim3(n_wg), dim3(64), 0, st, calls_dev, items_dev, wg_begin_dev, call_fp64_dev);
-      break;
+    case 4: return launch_batched_r<4>(calls_dev, items_dev, wg_begin_dev, call_fp64_dev, n_wg, st);
+    case 8: return launch_batched_r<8>(calls_dev, items_dev, wg_begin_dev, call_fp64_dev, n_wg, st);
+    case 12: return launch_batched_r<12>(calls_dev, items_dev, wg_begin_dev, call_fp64_dev, n_wg, st);
+    case 16: return launch_batched_r<16>(calls_dev, items_dev, wg_begin_dev, call_fp64_dev, n_wg, st);
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 }  // namespace taches

@@ -58,7 +58,7 @@ struct WorkItem {
   int32_t pad_;
 };
 
-// Kernel launchers (k_gather.hip).  r in {4, 8, 16}, w in {1, 2, 4}.
+// Kernel launchers (k_gather.hip).  r in {4, 8, 12, 16}, w in {1, 2, 4}.
 hipError_t launch_gather(const GatherCall& call, bool tail_fp64, int r, int w, hipStream_t st);
 hipError_t launch_gather_batched(const GatherCall* calls_dev, const WorkItem* items_dev,
                                  const int32_t* wg_begin_dev, const int32_t* call_fp64_dev, int n_wg,

@@ -189,28 +189,40 @@ int load_slot(taches_stream* s, int slot, const float* h, int L, bool on_device)
   return TACHES_OK;
 }
 
-// Tile shape: prefer long per-lane tiles (fewer LDS reads per FMA) and
-// split the chunks of a tile over several waves only when the call has too
-// few tiles to give every SIMD two waves.
+// Tile shape (r outputs per lane, w waves per tile).  Estimated time of a
+// launch: the busiest CU holds ceil(tiles / 256) workgroups, i.e.
+// ceil(tiles / 256) * w / 4 waves per SIMD sharing its FMA pipe, each with
+// 1/w of a tile's r * 64 * span FMAs; a SIMD with less than one wave still
+// takes one wave's time.  Longer per-lane tiles need fewer LDS reads per FMA
+// (eff_r), and fewer than two waves per SIMD expose latency.
 void pick_tile(const taches_stream* s, int n_out, int chunks_per_tile, int* r, int* w) {
   if (s->force_r) {
     *r = s->force_r;
     *w = s->force_w ? s->force_w : 1;
     return;
   }
-  const int64_t target = 2048;
-  static const int cand[9][2] = {{16, 1}, {16, 2}, {16, 4}, {8, 1}, {8, 2}, {8, 4}, {4, 1}, {4, 2}, {4, 4}};
-  for (auto& cw : cand) {
-    const int64_t tiles = (int64_t)s->cfg.channels * ((n_out + 64 * cw[0] - 1) / (64 * cw[0]));
-    if (cw[1] > 1 && chunks_per_tile < 2 * cw[1]) continue;
-    if (tiles * cw[1] >= target) {
-      *r = cw[0];
-      *w = cw[1];
-      return;
-    }
-  }
+  static const int rs[4] = {16, 12, 8, 4};
+  static const double eff_r[4] = {0.97, 0.96, 0.93, 0.85};
+  static const int ws[3] = {1, 2, 4};
+  double best = 1e300;
   *r = 4;
   *w = 1;
+  for (int i = 0; i < 4; ++i) {
+    for (int wi : ws) {
+      if (wi > 1 && chunks_per_tile < 2 * wi) continue;
+      const int64_t tiles = (int64_t)s->cfg.channels * ((n_out + 64 * rs[i] - 1) / (64 * rs[i]));
+      const double per_cu = (double)((tiles + 255) / 256);
+      const double simd_load = per_cu * wi / 4.0;
+      const double per_wave = 64.0 * rs[i] / wi;
+      double cost = std::max(simd_load, 1.0) * per_wave / eff_r[i];
+      if (simd_load < 2.0) cost /= 0.9;
+      if (cost < best * 0.999) {
+        best = cost;
+        *r = rs[i];
+        *w = wi;
+      }
+    }
+  }
 }
 
 int process_common(taches_stream* s, const float* x_dev, float* y_dev, int n_blocks, const int32_t* sched) {
@@ -515,8 +527,8 @@ int taches_set_tile(taches_stream* s, int32_t r, int32_t w) {
     s->force_r = s->force_w = 0;
     return TACHES_OK;
   }
-  if ((r != 4 && r != 8 && r != 16) || (w != 1 && w != 2 && w != 4))
-    return fail(TACHES_EINVAL, "tile (%d, %d) not in {4,8,16} x {1,2,4}", r, w);
+  if ((r != 4 && r != 8 && r != 12 && r != 16) || (w != 1 && w != 2 && w != 4))
+    return fail(TACHES_EINVAL, "tile (%d, %d) not in {4,8,12,16} x {1,2,4}", r, w);
   s->force_r = r;
   s->force_w = w;
   return TACHES_OK;

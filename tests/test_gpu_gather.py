@@ -71,7 +71,7 @@ def test_config1_parity_and_modes_agree():
     assert i1.tail_fp64 == 0
 
 
-@pytest.mark.parametrize("tile", [(4, 1), (4, 2), (4, 4), (8, 1), (8, 2), (8, 4), (16, 1), (16, 2), (16, 4)])
+@pytest.mark.parametrize("tile", [(r, w) for r in (4, 8, 12, 16) for w in (1, 2, 4)])
 def test_every_tile_shape_gives_the_same_bits(tile):
     spec = W.config2(n=20_000, L=5000, block=256, period=4800)
     nb = -(-(spec.n_samples + 4999) // 256)
@@ -196,4 +196,42 @@ def test_long_ir_auto_picks_fp64_tail():
     s.close()
     s = T.Stream(32, 131_073)
     assert s.info().tail_fp64 == 1
+    s.close()
+
+
+def test_config2_full_size_sampled_parity():
+    """Full config-2 size in the benchmark's launch configuration (one
+    1875-block call with the IR schedule, then a NULL-input drain), checked
+    on sampled outputs against Eq. (4) in FP64 (numpy dot products)."""
+    import torch
+    from oracle import oracle as O
+    from tests.gpu_harness import binding
+    T = binding()
+    spec = W.config2()
+    B, L = spec.block, spec.max_ir_len
+    nb, nbd = spec.n_blocks(), -(-(L - 1) // B)
+    xp = np.zeros((1, nb * B), np.float32)
+    xp[0, :spec.n_samples] = spec.x[0]
+    s = T.Stream(B, L, max_blocks_per_call=nb, ir_slots=2)
+    for k, h in enumerate(spec.irs):
+        s.load_ir_slot(k, torch.from_numpy(h).cuda())
+    sched = np.full(nb, -1, np.int32)
+    for b, k in spec.schedule:
+        sched[b] = k
+    xd = torch.from_numpy(xp).cuda()
+    yd = torch.empty_like(xd)
+    yt = torch.empty((1, nbd * B), device="cuda")
+    s.process_blocks(xd, yd, nb, sched)
+    s.process_blocks(None, yt, nbd)
+    y = torch.cat([yd, yt], 1).cpu().numpy()[0].astype(np.float64)
+    rng = np.random.default_rng(7)
+    idx = set(rng.integers(0, spec.n_samples + L - 1, 600).tolist())
+    for b, _ in spec.schedule:          # both sides of every swap boundary
+        idx.update([b * B - 1, b * B, b * B + 1])
+    idx.update([0, 1, spec.n_samples - 1, spec.n_samples, spec.n_samples + L - 2])
+    idx = np.array(sorted(i for i in idx if 0 <= i < spec.n_samples + L - 1))
+    ref = O.sampled_outputs(spec.x[0], spec.irs, spec.schedule, B, idx)
+    rms = float(np.sqrt(np.mean(y[: spec.n_samples + L - 1] ** 2)))
+    assert np.max(np.abs(y[idx] - ref)) <= 1e-5 * rms
+    assert not np.any(y[spec.n_samples + L - 1:])
     s.close()
