@@ -98,9 +98,10 @@ int taches_close(taches_stream* s);
 /* Message of the last failure on this thread ("" if none). */
 const char* taches_last_error(void);
 
-/* Order all later device work of this handle on `hip_stream` (a
- * hipStream_t, e.g. torch.cuda.current_stream().cuda_stream; NULL = the
- * handle's own stream).  Work already enqueued is first waited for. */
+/* Order all later device work of this handle on `hip_stream`, a
+ * hipStream_t such as torch.cuda.current_stream().cuda_stream.  NULL is
+ * HIP's null (default) stream, as in the HIP API.  A handle starts on a
+ * non-blocking stream of its own.  Work already enqueued is first waited for. */
 int taches_set_hip_stream(taches_stream* s, void* hip_stream);
 
 /* Block the host until all device work of the handle is done. */

@@ -1,9 +1,40 @@
-// Split-BF16 path: IR staging (hi/lo BF16 copies) and the multichannel
-// Toeplitz-block MFMA kernel with an FP64 tail.
+// Split-BF16 path for channels that share one impulse response.
+//
+// For a tile of output slots n and a chunk of input samples m the taches of
+// all channels c form one dense contraction:
+//   P[n][c] = sum_m A[n][m] * X[m][c],   A[n][m] = h[n - m]  (Toeplitz in h),
+// which runs on the MFMA units (v_mfma_f32_32x32x16_bf16).  FP32 values are
+// split as v = hi + lo with hi = RN_bf16(v), lo = RN_bf16(v - hi); the
+// product is taken as A_hi X_hi + A_hi X_lo + A_lo X_hi (the A_lo X_lo term,
+// below 2^-16 |A||X|, is dropped) with FP32 accumulation inside the chunk.
+// Each chunk's FP32 partial is then added to the tail accumulator (FP64 for
+// long IRs) in chunk order, as on the FP32 gather path.  The paper points at
+// GPUs for the per-channel matrix form and names precision as the key factor
+// (Section 4.2); this extends its requantization count (Sections 5.3-5.5)
+// to a measured error against an FP64 reference.
+//
+// Data layout:
+//  - IR: FP32 taps plus BF16 hi/lo copies (split once per set_ir).
+//  - Input: per call, every chunk of every channel is split into hi/lo and
+//    stored as [chunk][k-group of 8 samples][channel (padded)][8] BF16 so a
+//    lane's MFMA B fragment (8 consecutive samples of one channel) is one
+//    aligned 16-byte load and 32 lanes read 512 contiguous bytes.
+//  - Tail: [slot][channel (padded)], so the 32 lanes of an MFMA result
+//    column group write contiguous memory.
+//  - LDS: the IR window a tile needs, reversed, in 8 copies shifted by one
+//    element each: the A fragment of a lane (8 taps, descending) is then
+//    one aligned 16-byte read from the copy that matches its alignment.
 #include "taches_internal.h"
 
 namespace taches {
 namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int MT = 128;                    // output slots per workgroup (4 waves x 32)
+constexpr int KC = CHUNK_MAX;              // longest chunk (samples)
+constexpr int CP_LEN = MT + KC + 16;       // elements per shifted copy (>= MT + KC + 7)
 
 // Round an FP32 value to the nearest BF16 (ties to even); returns the bits.
 __device__ __forceinline__ uint16_t bf16_rn(float v) {
@@ -24,6 +55,163 @@ __global__ void k_split_bf16(const float* __restrict__ h, uint16_t* __restrict__
   }
 }
 
+__device__ __forceinline__ void chunk_span(const GatherCall& d, int ck, int& m_lo, int& len, int& b) {
+  b = ck / d.cpb;
+  const int i = ck - b * d.cpb;
+  m_lo = b * d.B + (i * d.B) / d.cpb;
+  len = b * d.B + ((i + 1) * d.B) / d.cpb - m_lo;
+}
+
+// One thread per (chunk, k-group of 8 samples, padded channel): split 8
+// samples into hi/lo BF16 and store them as one 16-byte fragment each.
+__global__ __launch_bounds__(256) void k_split_input(GatherCall d, int n_chunks) {
+  const int cpad = d.cpad;
+  const int64_t total = (int64_t)n_chunks * 32 * cpad;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(t % cpad);
+    const int kg = (int)((t / cpad) % 32);
+    const int ck = (int)(t / ((int64_t)cpad * 32));
+    int m_lo, len, b;
+    chunk_span(d, ck, m_lo, len, b);
+    uint16_t hv[8], lv[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int s = kg * 8 + j;
+      float v = 0.f;
+      if (c < d.channels && s < len) v = d.x[(int64_t)c * d.x_cstride + m_lo + s];
+      hv[j] = bf16_rn(v);
+      lv[j] = bf16_rn(v - bf16_to_f(hv[j]));
+    }
+    uint4 ph, pl;
+    ph.x = hv[0] | ((uint32_t)hv[1] << 16); ph.y = hv[2] | ((uint32_t)hv[3] << 16);
+    ph.z = hv[4] | ((uint32_t)hv[5] << 16); ph.w = hv[6] | ((uint32_t)hv[7] << 16);
+    pl.x = lv[0] | ((uint32_t)lv[1] << 16); pl.y = lv[2] | ((uint32_t)lv[3] << 16);
+    pl.z = lv[4] | ((uint32_t)lv[5] << 16); pl.w = lv[6] | ((uint32_t)lv[7] << 16);
+    *reinterpret_cast<uint4*>(d.xs_hi + t * 8) = ph;
+    *reinterpret_cast<uint4*>(d.xs_lo + t * 8) = pl;
+  }
+}
+
+__device__ __forceinline__ int xcd_remap(int id, int n) {
+  const int x = id & 7;
+  const int k = id >> 3;
+  const int q = n >> 3, rem = n & 7;
+  return x * q + (x < rem ? x : rem) + k;
+}
+
+template <typename TailT>
+__global__ __launch_bounds__(256) void k_toeplitz(GatherCall d, int n_tiles) {
+  __shared__ __attribute__((aligned(16))) uint16_t cp_hi[8 * CP_LEN];
+  __shared__ __attribute__((aligned(16))) uint16_t cp_lo[8 * CP_LEN];
+  const int tid = threadIdx.x;
+  const int l = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int i = l & 31;   // row within the wave's 32-row MFMA tile (A) / column (B, D)
+  const int kg = l >> 5;  // k-group of 8 within a 16-deep K-step
+  const int tile = xcd_remap(blockIdx.x, n_tiles);
+  const int n0 = tile * MT;
+  const int cpad = d.cpad;
+  TailT* ring = reinterpret_cast<TailT*>(d.ring);
+
+  // accumulators: two 32x32 result tiles (channels 0-31, 32-63); lane l holds
+  // column l%32 and rows 8*(q/4) + 4*(l/32) + q%4 of its wave's 32 rows
+  TailT acc[2][16];
+#pragma unroll
+  for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int n = n0 + 32 * w + 8 * (q >> 2) + 4 * kg + (q & 3);
+      const int c = 32 * nt + i;
+      TailT v = 0;
+      if (n < d.live_in && c < cpad) {
+        int slot = d.head + n;
+        if (slot >= d.Rcap) slot -= d.Rcap;
+        v = ring[(int64_t)slot * cpad + c];
+      }
+      acc[nt][q] = v;
+    }
+
+  if (d.x != nullptr) {
+    const int lo = n0 - (d.Lmax_call - 1);
+    const int b_first = lo <= 0 ? 0 : lo / d.B;
+    const int b_last = min(d.n_blocks - 1, (n0 + MT - 1) / d.B);
+    const int c_first = b_first * d.cpb;
+    const int nch = b_first <= b_last ? (b_last - b_first + 1) * d.cpb : 0;
+    for (int k = 0; k < nch; ++k) {
+      const int ck = c_first + k;
+      int m_lo, len, b;
+      chunk_span(d, ck, m_lo, len, b);
+      const BlockIR ir = d.irs ? d.irs[b] : d.ir0;
+      if (len <= 0 || m_lo > n0 + MT - 1 || m_lo + len + ir.L - 2 < n0) continue;  // uniform
+      const int chp = (len + 15) & ~15;
+      __syncthreads();  // the previous chunk's reads of the copies are done
+      // stage: copy s, element v holds h[n0 - m_lo + MT - 1 - (v + s)]
+      const int top = n0 - m_lo + MT - 1;
+      for (int e = tid; e < 8 * CP_LEN; e += 256) {
+        const int s = e / CP_LEN;
+        const int v = e - s * CP_LEN;
+        const int hidx = top - v - s;
+        uint16_t vh = 0, vl = 0;
+        if (hidx >= 0 && hidx < ir.L) {
+          vh = ir.h_hi[hidx];
+          vl = ir.h_lo[hidx];
+        }
+        cp_hi[e] = vh;
+        cp_lo[e] = vl;
+      }
+      __syncthreads();
+      f32x16 p0 = {}, p1 = {};
+      const uint16_t* xh = d.xs_hi + ((int64_t)ck * 32) * cpad * 8;
+      const uint16_t* xl = d.xs_lo + ((int64_t)ck * 32) * cpad * 8;
+      const int ksteps = chp >> 4;
+      for (int t = 0; t < ksteps; ++t) {
+        // A fragment: taps for rows n0+32w+i and samples m_lo+16t+8kg+j
+        const int a = MT - 1 - 32 * w - i + 16 * t + 8 * kg;
+        const int aoff = (a & 7) * CP_LEN + (a & ~7);
+        const bf16x8 ah = *reinterpret_cast<const bf16x8*>(cp_hi + aoff);
+        const bf16x8 al = *reinterpret_cast<const bf16x8*>(cp_lo + aoff);
+        // B fragments: 8 samples of channel 32*nt + i, k-group 2t + kg
+        const int64_t xo = ((int64_t)(2 * t + kg) * cpad + i) * 8;
+        const bf16x8 bh0 = *reinterpret_cast<const bf16x8*>(xh + xo);
+        const bf16x8 bl0 = *reinterpret_cast<const bf16x8*>(xl + xo);
+        p0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh0, p0, 0, 0, 0);
+        p0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl0, p0, 0, 0, 0);
+        p0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh0, p0, 0, 0, 0);
+        if (cpad > 32) {
+          const bf16x8 bh1 = *reinterpret_cast<const bf16x8*>(xh + xo + 32 * 8);
+          const bf16x8 bl1 = *reinterpret_cast<const bf16x8*>(xl + xo + 32 * 8);
+          p1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh1, p1, 0, 0, 0);
+          p1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl1, p1, 0, 0, 0);
+          p1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh1, p1, 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        acc[0][q] += (TailT)p0[q];
+        acc[1][q] += (TailT)p1[q];
+      }
+    }
+  }
+
+#pragma unroll
+  for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int n = n0 + 32 * w + 8 * (q >> 2) + 4 * kg + (q & 3);
+      const int c = 32 * nt + i;
+      if (n < d.n_out && c < cpad) {
+        int slot = d.head + n;
+        if (slot >= d.Rcap) slot -= d.Rcap;
+        if (n < d.S) {
+          if (c < d.channels) d.y[(int64_t)c * d.y_cstride + n] = (float)acc[nt][q];
+          ring[(int64_t)slot * cpad + c] = (TailT)0;
+        } else {
+          ring[(int64_t)slot * cpad + c] = acc[nt][q];
+        }
+      }
+    }
+}
+
 }  // namespace
 
 hipError_t launch_split_bf16(const float* h, uint16_t* hi, uint16_t* lo, int L, hipStream_t st) {
@@ -35,6 +223,24 @@ hipError_t launch_split_bf16(const float* h, uint16_t* hi, uint16_t* lo, int L, 
 
 bool split_supported(const taches_config& cfg) { return cfg.channels >= 1 && cfg.channels <= 64; }
 
-hipError_t launch_toeplitz(const GatherCall&, hipStream_t) { return hipErrorNotSupported; }
+int split_cpad(int channels) { return channels <= 32 ? 32 : 64; }
+
+hipError_t launch_toeplitz(const GatherCall& call, bool tail_fp64, hipStream_t st) {
+  if (call.n_out <= 0) return hipSuccess;
+  if (call.x) {
+    const int n_chunks = call.n_blocks * call.cpb;
+    const int64_t total = (int64_t)n_chunks * 32 * call.cpad;
+    const int blocks = (int)((total + 255) / 256 < 4096 ? (total + 255) / 256 : 4096);
+    hipLaunchKernelGGL(k_split_input, dim3(blocks), dim3(256), 0, st, call, n_chunks);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  const int n_tiles = (call.n_out + MT - 1) / MT;
+  if (tail_fp64)
+    hipLaunchKernelGGL(k_toeplitz<double>, dim3(n_tiles), dim3(256), 0, st, call, n_tiles);
+  else
+    hipLaunchKernelGGL(k_toeplitz<float>, dim3(n_tiles), dim3(256), 0, st, call, n_tiles);
+  return hipGetLastError();
+}
 
 }  // namespace taches

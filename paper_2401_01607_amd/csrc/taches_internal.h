@@ -48,6 +48,11 @@ struct GatherCall {
   int32_t n_out;         // outputs to produce (>= S)
   int32_t Lmax_call;     // longest IR used by the call's blocks
   int32_t channels;
+  // split-BF16 path only: per-chunk hi/lo input fragments and padded channels
+  uint16_t* xs_hi;
+  uint16_t* xs_lo;
+  int32_t cpad;
+  int32_t pad_;
 };
 
 // One unit of batched work: an output tile of one channel of one call.
@@ -70,8 +75,10 @@ inline int tile_outputs(int r) { return 64 * r; }
 // lo = RN_bf16(h - hi), bit patterns stored as uint16.
 hipError_t launch_split_bf16(const float* h, uint16_t* hi, uint16_t* lo, int L, hipStream_t st);
 
-// Multichannel split-BF16 Toeplitz-block MFMA with FP64 tail (k_toeplitz.hip).
-hipError_t launch_toeplitz(const GatherCall& call, hipStream_t st);
+// Multichannel split-BF16 Toeplitz-block MFMA (k_toeplitz.hip).  The tail of
+// a split stream is laid out [slot][cpad] (channel fastest).
+hipError_t launch_toeplitz(const GatherCall& call, bool tail_fp64, hipStream_t st);
 bool split_supported(const taches_config& cfg);
+int split_cpad(int channels);
 
 }  // namespace taches

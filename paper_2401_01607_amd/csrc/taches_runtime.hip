@@ -48,6 +48,18 @@ int64_t ring_slots_for(const taches_config& c) {
   return round_up((int64_t)c.max_ir_len - 1 + (int64_t)c.block_size * c.max_blocks_per_call, 64);
 }
 
+bool is_split(const taches_config& c) { return c.precision == TACHES_PREC_SPLIT_BF16; }
+
+// channels stored per tail slot: the split path pads to its MFMA width
+int64_t ring_channels(const taches_config& c) { return is_split(c) ? taches::split_cpad(c.channels) : c.channels; }
+
+int64_t chunks_per_block(const taches_config& c) { return (c.block_size + taches::CHUNK_MAX - 1) / taches::CHUNK_MAX; }
+
+// bytes of one split input staging buffer (hi or lo) for the largest call
+int64_t xs_bytes(const taches_config& c) {
+  return is_split(c) ? (int64_t)c.max_blocks_per_call * chunks_per_block(c) * 32 * ring_channels(c) * 8 * 2 : 0;
+}
+
 int validate(const taches_config* c) {
   if (!c) return fail(TACHES_EINVAL, "config is NULL");
   if (c->block_size < 1 || c->max_ir_len < 1 || c->channels < 1 || c->max_blocks_per_call < 1)
@@ -59,6 +71,8 @@ int validate(const taches_config* c) {
   const int64_t S = (int64_t)c->block_size * c->max_blocks_per_call;
   if (S + c->max_ir_len >= (int64_t)1 << 30) return fail(TACHES_EINVAL, "block_size * max_blocks_per_call + max_ir_len too large");
   if ((int64_t)c->channels * ring_slots_for(*c) >= (int64_t)1 << 34) return fail(TACHES_EINVAL, "tail too large");
+  if (c->precision == TACHES_PREC_SPLIT_BF16 && (c->channels < 1 || c->channels > 64))
+    return fail(TACHES_EINVAL, "split-BF16 path needs 1 <= channels <= 64");
   return TACHES_OK;
 }
 
@@ -91,6 +105,8 @@ struct taches_stream {
   int force_r = 0, force_w = 0, last_r = 0, last_w = 0;
   int64_t device_bytes = 0;
   taches_pool* pool = nullptr;
+  uint16_t *xs_hi = nullptr, *xs_lo = nullptr;  // split path: per-call input fragments
+  int cpad = 0;                                 // channels per tail slot (split path)
 };
 
 namespace {
@@ -112,6 +128,8 @@ void free_stream(taches_stream* s) {
   (void)hipHostFree(s->y_pin);
   (void)hipFree(s->irtab_dev);
   (void)hipHostFree(s->irtab_pin);
+  (void)hipFree(s->xs_hi);
+  (void)hipFree(s->xs_lo);
   if (s->irtab_ev) (void)hipEventDestroy(s->irtab_ev);
   if (s->own) (void)hipStreamDestroy(s->own);
   delete s;
@@ -139,8 +157,9 @@ int stream_init(taches_stream* s) {
   s->stream = s->own;
   s->tail_fp64 = want_fp64(c);
   s->Rcap = (int)ring_slots_for(c);
+  s->cpad = (int)ring_channels(c);
   const size_t esz = s->tail_fp64 ? 8 : 4;
-  const size_t ring_bytes = (size_t)c.channels * s->Rcap * esz;
+  const size_t ring_bytes = (size_t)s->cpad * s->Rcap * esz;
   int rc;
   if ((rc = dev_alloc(s, &s->ring, ring_bytes))) return rc;
   HIPCHK(hipMemsetAsync(s->ring, 0, ring_bytes, s->stream));
@@ -163,6 +182,10 @@ int stream_init(taches_stream* s) {
   if ((rc = dev_alloc(s, &s->irtab_dev, tab))) return rc;
   if ((rc = host_alloc(&s->irtab_pin, tab))) return rc;
   HIPCHK(hipEventCreateWithFlags(&s->irtab_ev, hipEventDisableTiming));
+  if (is_split(c)) {
+    if ((rc = dev_alloc(s, &s->xs_hi, (size_t)xs_bytes(c)))) return rc;
+    if ((rc = dev_alloc(s, &s->xs_lo, (size_t)xs_bytes(c)))) return rc;
+  }
   HIPCHK(hipStreamSynchronize(s->stream));
   return TACHES_OK;
 }
@@ -279,6 +302,9 @@ int process_common(taches_stream* s, const float* x_dev, float* y_dev, int n_blo
   g.n_out = (int32_t)n_out;
   g.Lmax_call = std::max(Lmax_call, 1);
   g.channels = c.channels;
+  g.xs_hi = s->xs_hi;
+  g.xs_lo = s->xs_lo;
+  g.cpad = s->cpad;
   auto ir_of = [&](int k) {
     BlockIR ir{};
     if (k >= 0) {
@@ -310,7 +336,7 @@ int process_common(taches_stream* s, const float* x_dev, float* y_dev, int n_blo
   }
 
   if (c.precision == TACHES_PREC_SPLIT_BF16) {
-    hipError_t e = taches::launch_toeplitz(g, s->stream);
+    hipError_t e = taches::launch_toeplitz(g, s->tail_fp64, s->stream);
     if (e != hipSuccess) return fail(TACHES_EDEVICE, "toeplitz launch: %s", hipGetErrorString(e));
     s->last_r = 0;
     s->last_w = 0;
@@ -353,10 +379,6 @@ const char* taches_last_error(void) { return g_err.c_str(); }
 
 taches_stream* taches_open_ex(const taches_config* cfg) {
   if (validate(cfg) != TACHES_OK) return nullptr;
-  if (cfg->precision == TACHES_PREC_SPLIT_BF16 && !taches::split_supported(*cfg)) {
-    fail(TACHES_EINVAL, "split-BF16 path needs channels in [1, 64]");
-    return nullptr;
-  }
   taches_stream* s = new (std::nothrow) taches_stream();
   if (!s) {
     fail(TACHES_ENOMEM, "out of host memory");
@@ -387,7 +409,7 @@ int taches_close(taches_stream* s) {
 
 int taches_set_hip_stream(taches_stream* s, void* hip_stream) {
   if (!s) return fail(TACHES_EINVAL, "stream is NULL");
-  hipStream_t next = hip_stream ? (hipStream_t)hip_stream : s->own;
+  hipStream_t next = (hipStream_t)hip_stream;  // NULL: HIP's null stream
   if (next != s->stream) {
     HIPCHK(hipStreamSynchronize(s->stream));
     s->stream = next;
@@ -486,7 +508,8 @@ int taches_get_info(const taches_stream* s, taches_info* out) {
 int64_t taches_bytes_for(const taches_config* cfg) {
   if (validate(cfg) != TACHES_OK) return -1;
   const int64_t esz = want_fp64(*cfg) ? 8 : 4;
-  int64_t b = (int64_t)cfg->channels * ring_slots_for(*cfg) * esz;
+  int64_t b = ring_channels(*cfg) * ring_slots_for(*cfg) * esz;
+  b += 2 * xs_bytes(*cfg);
   b += (int64_t)cfg->ir_slots * cfg->max_ir_len * (cfg->precision == TACHES_PREC_SPLIT_BF16 ? 8 : 4);
   b += 2 * (int64_t)cfg->channels * cfg->block_size * 4;
   b += (int64_t)cfg->max_blocks_per_call * (int64_t)sizeof(BlockIR);
@@ -499,14 +522,26 @@ int taches_read_tail(taches_stream* s, int32_t channel, double* out, int32_t n) 
   if (n < 0 || n > s->Rcap) return fail(TACHES_EINVAL, "n=%d outside [0, %d]", n, s->Rcap);
   HIPCHK(hipStreamSynchronize(s->stream));
   const size_t esz = s->tail_fp64 ? 8 : 4;
-  std::vector<unsigned char> buf((size_t)n * esz);
-  const int first = std::min(n, s->Rcap - s->head);
   const unsigned char* base = (const unsigned char*)s->ring;
-  const int64_t coff = (int64_t)channel * s->Rcap;
-  if (first > 0)
-    HIPCHK(hipMemcpy(buf.data(), base + (coff + s->head) * esz, (size_t)first * esz, hipMemcpyDeviceToHost));
-  if (n > first)
-    HIPCHK(hipMemcpy(buf.data() + (size_t)first * esz, base + coff * esz, (size_t)(n - first) * esz, hipMemcpyDeviceToHost));
+  std::vector<unsigned char> buf((size_t)n * esz);
+  if (is_split(s->cfg)) {
+    // [slot][cpad]: strided copy of one channel column
+    for (int k = 0; k < n;) {
+      const int slot = (s->head + k) % s->Rcap;
+      const int run = std::min(n - k, s->Rcap - slot);
+      HIPCHK(hipMemcpy2D(buf.data() + (size_t)k * esz, esz, base + ((size_t)slot * s->cpad + channel) * esz,
+                         (size_t)s->cpad * esz, esz, run, hipMemcpyDeviceToHost));
+      k += run;
+    }
+  } else {
+    const int first = std::min(n, s->Rcap - s->head);
+    const int64_t coff = (int64_t)channel * s->Rcap;
+    if (first > 0)
+      HIPCHK(hipMemcpy(buf.data(), base + (coff + s->head) * esz, (size_t)first * esz, hipMemcpyDeviceToHost));
+    if (n > first)
+      HIPCHK(hipMemcpy(buf.data() + (size_t)first * esz, base + coff * esz, (size_t)(n - first) * esz,
+                       hipMemcpyDeviceToHost));
+  }
   for (int k = 0; k < n; ++k) {
     if (s->tail_fp64) {
       double v;

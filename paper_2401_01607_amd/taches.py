@@ -180,9 +180,9 @@ def taches_set_tile(s, r: int, w: int) -> int:
     return lib.taches_set_tile(s, r, w)
 
 
-def taches_set_hip_stream(s, stream=None) -> int:
-    ptr = None if stream is None else ctypes.c_void_p(stream)
-    return lib.taches_set_hip_stream(s, ptr)
+def taches_set_hip_stream(s, stream: int) -> int:
+    """stream: a hipStream_t value (torch.cuda.Stream.cuda_stream); 0 is HIP's null stream."""
+    return lib.taches_set_hip_stream(s, ctypes.c_void_p(stream) if stream else None)
 
 
 def taches_synchronize(s) -> int:

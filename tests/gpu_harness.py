@@ -19,14 +19,14 @@ def pad_signal(x: np.ndarray, n_blocks: int, B: int) -> np.ndarray:
     return out
 
 
-def gpu_per_block(x, irs, schedule, B, Lmax, n_blocks, tail=0, tile=None, host_io=False):
+def gpu_per_block(x, irs, schedule, B, Lmax, n_blocks, tail=0, tile=None, host_io=False, precision=0):
     """One taches_process_async (or taches_process) call per block; IR swaps
     through taches_set_ir before the scheduled block."""
     import torch
     T = binding()
     xp = pad_signal(x, n_blocks, B)
     C = xp.shape[0]
-    s = T.Stream(B, Lmax, channels=C, tail=tail)
+    s = T.Stream(B, Lmax, channels=C, tail=tail, precision=precision)
     if tile:
         s.set_tile(*tile)
     sched = dict(schedule)
@@ -51,7 +51,8 @@ def gpu_per_block(x, irs, schedule, B, Lmax, n_blocks, tail=0, tile=None, host_i
     return y, info
 
 
-def gpu_multi_block(x, irs, schedule, B, Lmax, n_blocks, tail=0, tile=None, calls=1, drain_x_null=0):
+def gpu_multi_block(x, irs, schedule, B, Lmax, n_blocks, tail=0, tile=None, calls=1, drain_x_null=0,
+                    precision=0):
     """All blocks in ``calls`` taches_process_blocks calls with an IR-slot
     schedule; then ``drain_x_null`` blocks with x = NULL."""
     import torch
@@ -60,7 +61,7 @@ def gpu_multi_block(x, irs, schedule, B, Lmax, n_blocks, tail=0, tile=None, call
     C = xp.shape[0]
     per = -(-n_blocks // calls)
     s = T.Stream(B, Lmax, channels=C, max_blocks_per_call=max(per, drain_x_null, 1), tail=tail,
-                 ir_slots=max(2, len(irs)))
+                 ir_slots=max(2, len(irs)), precision=precision)
     if tile:
         s.set_tile(*tile)
     for k, h in enumerate(irs):
@@ -91,6 +92,12 @@ def oracle_run(x, irs, schedule, B, Lmax, n_blocks):
     from oracle import oracle as O
     xp = np.atleast_2d(np.asarray(x, dtype=np.float32))
     return np.stack(O.run_channels(list(xp), irs, schedule, B, Lmax, n_blocks=n_blocks))
+
+
+def oracle_abs_run(x, irs, schedule, B, Lmax, n_blocks):
+    """sum_k |h_k| |x_{n-k}| per output: the oracle on absolute values."""
+    xa = np.abs(np.atleast_2d(np.asarray(x, dtype=np.float32)))
+    return oracle_run(xa, [np.abs(np.asarray(h, np.float32)) for h in irs], schedule, B, Lmax, n_blocks)
 
 
 def rel_err(y, y64):
