@@ -42,11 +42,29 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle sample duration")
     p.add_argument("--latency-blocks", type=int, default=400)
     p.add_argument("--tile", type=str, default="", help="force gather tile 'R,W'")
+    p.add_argument("--calibrate-copy", type=int, default=0, metavar="MB",
+                   help="only run a plain device copy of MB megabytes (HBM counter calibration)")
     return p.parse_args()
+
+
+def calibrate_copy(mb: int) -> None:
+    """A plain device-to-device copy of known size, for scaling the HBM byte
+    counters (FETCH_SIZE, WRITE_SIZE) of a profiler run."""
+    import torch
+    n = mb * (1 << 20) // 4
+    a = torch.ones(n, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_each_way": n * 4, "copies": 3}), flush=True)
 
 
 def main():
     args = parse()
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))

@@ -15,7 +15,8 @@
 // slot n in chunk order, in the tail's type (FP32, or FP64 for long IRs).
 //
 // Data movement per chunk and tile: the T + len - 1 taps of h that the tile
-// needs and the chunk's len input samples are staged in LDS (per wave).  A
+// needs and the chunk's len input samples are staged in LDS (per wave),
+// loaded into registers one chunk ahead.  A
 // lane keeps two R-tap windows of h in registers; for each group of R input
 // samples it loads one new window (R/4 ds_read_b128) and the group's R
 // input samples (uniform ds_read_b128 broadcasts), then issues R*R FMAs.
@@ -26,23 +27,25 @@
 namespace taches {
 namespace {
 
+// All LDS data lives in one dynamic array indexed by 32-bit float offsets.
+extern __shared__ __attribute__((aligned(16))) float g_lds[];
+typedef float vf4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ vf4 lds_read4(int off) { return *reinterpret_cast<const vf4*>(&g_lds[off]); }
+__device__ __forceinline__ void lds_write4(int off, vf4 v) { *reinterpret_cast<vf4*>(&g_lds[off]) = v; }
+
 template <int R>
 struct Geo {
   static_assert(R % 4 == 0, "R must be a multiple of 4");
   static constexpr int T = 64 * R;                           // outputs per wave tile
   static constexpr int LP = (CHUNK_MAX + R - 1) / R * R;     // longest padded chunk
   static constexpr int NW = T + LP;                          // staged taps (max)
-  // padded floats per R-tap window row: a multiple of 4 with an odd number of
-  // 16-byte units, so the 16-byte reads of consecutive lanes hit distinct banks
-  static constexpr int ROW = ((R + 4) / 4) % 2 == 1 ? R + 4 : R + 8;
+  // floats per R-tap window row in LDS: an odd number of 16-byte units, so
+  // the 16-byte reads of consecutive lanes hit distinct banks
+  static constexpr int ROW = (R / 4) % 2 == 1 ? R : R + 4;
   static constexpr int HF = (NW / R) * ROW;                  // LDS floats for h
   static constexpr int WF = HF + LP;                         // + input samples
 };
-
-template <int R>
-__device__ __forceinline__ int hphys(int i) {
-  return (int)(((unsigned)i / R) * Geo<R>::ROW + ((unsigned)i % R));
-}
 
 // Map the launch order of workgroups to tiles so that consecutive tiles run
 // on the same XCD (workgroups are dispatched to the 8 XCDs round-robin):
@@ -55,12 +58,22 @@ __device__ __forceinline__ int xcd_remap(int id, int n) {
   return x * q + (x < rem ? x : rem) + k;
 }
 
+// Center-out order: the middle tile first, then alternately right and left
+// of it.  In a call that spans many blocks the tiles near both ends of the
+// output range reach fewer input samples; launching them last lets the
+// workgroup dispatcher hand the light tiles to the CUs that already hold
+// heavy ones.
+__device__ __forceinline__ int center_out(int id, int n) {
+  const int mid = (n - 1) >> 1;
+  return (id & 1) ? mid + ((id + 1) >> 1) : mid - (id >> 1);
+}
+
 // Load the R taps of one window; `src` points at its first padded float.
 template <int R>
-__device__ __forceinline__ void load_win(const float* src, float (&v)[R]) {
+__device__ __forceinline__ void load_win(int src, float (&v)[R]) {
 #pragma unroll
   for (int j = 0; j < R; j += 4) {
-    const float4 q = *reinterpret_cast<const float4*>(src + j);
+    const vf4 q = lds_read4(src + j);
     v[j] = q.x;
     v[j + 1] = q.y;
     v[j + 2] = q.z;
@@ -69,10 +82,10 @@ __device__ __forceinline__ void load_win(const float* src, float (&v)[R]) {
 }
 
 template <int R>
-__device__ __forceinline__ void load_x(const float* xs, int s0, float (&v)[R]) {
+__device__ __forceinline__ void load_x(int xs, int s0, float (&v)[R]) {
 #pragma unroll
   for (int j = 0; j < R; j += 4) {
-    const float4 q = *reinterpret_cast<const float4*>(xs + s0 + j);
+    const vf4 q = lds_read4(xs + s0 + j);
     v[j] = q.x;
     v[j + 1] = q.y;
     v[j + 2] = q.z;
@@ -103,11 +116,10 @@ __device__ __forceinline__ void fma_group(const float (&xv)[R], const float (&A)
 //   hs[lane*R + (G - 1 - g)*R + (r - t + R - 1)], G = len_pad / R, i.e. the
 //   window pair starting at padded row lane + G - 1 - g.
 template <int R>
-__device__ __forceinline__ void chunk_compute(const float* hs, const float* xs, int lane,
-                                              int len_pad, float (&p)[R]) {
+__device__ __forceinline__ void chunk_compute(int hs, int xs, int lane, int len_pad, float (&p)[R]) {
   constexpr int ROW = Geo<R>::ROW;
   const int G = len_pad / R;   // wave-uniform
-  const float* wl = hs + lane * ROW;
+  const int wl = hs + lane * ROW;
   float X[R], Y[R], xv[R];
   load_win<R>(wl + (G - 1) * ROW, X);
   load_win<R>(wl + G * ROW, Y);
@@ -119,7 +131,7 @@ __device__ __forceinline__ void chunk_compute(const float* hs, const float* xs, 
     load_x<R>(xs, (g + 1) * R, xv);
     fma_group<R>(xv, Y, X, p);                                 // group g+1: A = Y, B = X
     // window of group g+2 (a harmless in-bounds read when the loop ends)
-    load_win<R>(wl + max(G - 3 - g, -lane) * ROW, X);
+    load_win<R>(hs + max(lane + G - 3 - g, 0) * ROW, X);
   }
   if (g < G) {
     load_x<R>(xs, g * R, xv);
@@ -148,32 +160,92 @@ __device__ __forceinline__ ChunkGeo chunk_geo(const GatherCall& d, int ck, int n
   return g;
 }
 
+// 16-byte load from a 4-byte-aligned global address.
+__device__ __forceinline__ float4 load4(const float* p) {
+  float4 v;
+  __builtin_memcpy(&v, p, sizeof v);
+  return v;
+}
+
+// One chunk's staged data on its way from global memory to LDS: each lane
+// holds two R-tap rows of the IR window (rows lane and lane + 64) and up to
+// XPL input samples.  Loading it one round ahead hides the global-memory
+// latency behind the FMAs of the current chunk.
 template <int R>
-__device__ __forceinline__ void chunk_stage(const ChunkGeo& g, const float* __restrict__ xc, int n0,
-                                            float* hs, float* xs, int lane) {
+struct Prefetch {
+  static constexpr int XPL = (Geo<R>::LP + 63) / 64;
+  float hrow[2][R];
+  float xv[XPL];
+};
+
+// Row r of the staged window holds taps base + r*R .. base + r*R + R - 1,
+// base = n0 - m_lo - len_pad + 1; taps outside [0, L) are zero.
+template <int R>
+__device__ __forceinline__ void chunk_load(const ChunkGeo& g, const float* __restrict__ xc, int n0, int lane,
+                                           Prefetch<R>& pf) {
   const int base = n0 - g.m_lo - g.len_pad + 1;
-  const int NW = Geo<R>::T + g.len_pad;
+  const int rows = (Geo<R>::T + g.len_pad) / R;
   const float* __restrict__ h = g.ir.h;
   const int L = g.ir.L;
-  for (int i = lane; i < NW; i += 64) {
-    const int j = base + i;
-    const float v = (j >= 0 && j < L) ? h[j] : 0.f;
-    hs[hphys<R>(i)] = v;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int row = lane + 64 * k;
+    const int j0 = base + row * R;
+    if (row < rows && j0 >= 0 && j0 + R <= L) {
+#pragma unroll
+      for (int e = 0; e < R; e += 4) {
+        const float4 q = load4(h + j0 + e);
+        pf.hrow[k][e] = q.x;
+        pf.hrow[k][e + 1] = q.y;
+        pf.hrow[k][e + 2] = q.z;
+        pf.hrow[k][e + 3] = q.w;
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < R; ++e) {
+        const int j = j0 + e;
+        pf.hrow[k][e] = (row < rows && j >= 0 && j < L) ? h[j] : 0.f;
+      }
+    }
   }
-  for (int s = lane; s < g.len_pad; s += 64) xs[s] = s < g.len ? xc[g.m_lo + s] : 0.f;
+#pragma unroll
+  for (int k = 0; k < Prefetch<R>::XPL; ++k) {
+    const int s = lane + 64 * k;
+    pf.xv[k] = s < g.len ? xc[g.m_lo + s] : 0.f;
+  }
+}
+
+template <int R>
+__device__ __forceinline__ void chunk_store(const ChunkGeo& g, int lane, const Prefetch<R>& pf, int hs, int xs) {
+  const int rows = (Geo<R>::T + g.len_pad) / R;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int row = lane + 64 * k;
+    if (row < rows) {
+      const int dst = hs + row * Geo<R>::ROW;
+#pragma unroll
+      for (int e = 0; e < R; e += 4)
+        lds_write4(dst + e, vf4{pf.hrow[k][e], pf.hrow[k][e + 1], pf.hrow[k][e + 2], pf.hrow[k][e + 3]});
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < Prefetch<R>::XPL; ++k) {
+    const int s = lane + 64 * k;
+    if (s < g.len_pad) g_lds[xs + s] = pf.xv[k];
+  }
 }
 
 // One output tile of one channel of one call.  W waves share the tile; wave
 // w handles chunks w, w+W, ... of each round and the partial sums are added
 // to the accumulators in chunk order after every round.
 template <int R, int W, typename TailT>
-__device__ __forceinline__ void gather_tile(const GatherCall& d, int c, int tile, float* lds) {
+__device__ __forceinline__ void gather_tile(const GatherCall& d, int c, int tile) {
   constexpr int T = Geo<R>::T;
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
-  float* hs = lds + w * Geo<R>::WF;
-  float* xs = hs + Geo<R>::HF;
-  float* pbuf = lds + W * Geo<R>::WF;  // [W][64][R], used when W > 1
+  const int hs = w * Geo<R>::WF;           // LDS float offsets of this wave's region
+  const int xs = hs + Geo<R>::HF;
+  const int pbuf = W * Geo<R>::WF;         // [W][64][R], used when W > 1
 
   const int n0 = tile * T;
   const int nb = n0 + lane * R;
@@ -199,33 +271,44 @@ __device__ __forceinline__ void gather_tile(const GatherCall& d, int c, int tile
     const int b_last = min(d.n_blocks - 1, (n0 + T - 1) / d.B);
     const int c_first = b_first * d.cpb;
     const int nch = b_first <= b_last ? (b_last - b_first + 1) * d.cpb : 0;
+    // Wave w handles chunks w, w + W, w + 2W, ...: `gc` is staged in LDS,
+    // `gn` (the wave's next chunk) is in registers.  A wave's LDS region is
+    // private and LDS operations of one wave complete in program order, so
+    // storing `gn` after computing `gc` needs no barrier.
+    Prefetch<R> pf;
+    ChunkGeo gc, gn;
+    gc.reaches = gn.reaches = false;
+    if (w < nch) gc = chunk_geo<R>(d, c_first + w, n0);
+    if (gc.reaches) {
+      chunk_load<R>(gc, xc, n0, lane, pf);
+      chunk_store<R>(gc, lane, pf, hs, xs);
+    }
+    if (w + W < nch) gn = chunk_geo<R>(d, c_first + w + W, n0);
+    if (gn.reaches) chunk_load<R>(gn, xc, n0, lane, pf);
     for (int base = 0; base < nch; base += W) {
-      const int k = base + w;
       float p[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) p[r] = 0.f;
-      ChunkGeo g;
-      g.reaches = false;
-      if (k < nch) {
-        g = chunk_geo<R>(d, c_first + k, n0);
-        if (g.reaches) chunk_stage<R>(g, xc, n0, hs, xs, lane);
-      }
-      __syncthreads();
-      if (g.reaches) chunk_compute<R>(hs, xs, lane, g.len_pad, p);
+      if (gc.reaches) chunk_compute<R>(hs, xs, lane, gc.len_pad, p);
+      if (gn.reaches) chunk_store<R>(gn, lane, pf, hs, xs);
+      gc = gn;
+      gn.reaches = false;
+      if (base + 2 * W + w < nch) gn = chunk_geo<R>(d, c_first + base + 2 * W + w, n0);
+      if (gn.reaches) chunk_load<R>(gn, xc, n0, lane, pf);
       if constexpr (W == 1) {
 #pragma unroll
         for (int r = 0; r < R; ++r) acc[r] += (TailT)p[r];
       } else {
-        float* mine = pbuf + (w * 64 + lane) * R;
+        const int mine = pbuf + (w * 64 + lane) * R;
 #pragma unroll
-        for (int r = 0; r < R; r += 4) *reinterpret_cast<float4*>(mine + r) = make_float4(p[r], p[r + 1], p[r + 2], p[r + 3]);
+        for (int r = 0; r < R; r += 4) lds_write4(mine + r, vf4{p[r], p[r + 1], p[r + 2], p[r + 3]});
         __syncthreads();
         const int nv = min(W, nch - base);
         for (int v = 0; v < nv; ++v) {
-          const float* src = pbuf + (v * 64 + lane) * R;
+          const int src = pbuf + (v * 64 + lane) * R;
 #pragma unroll
           for (int r = 0; r < R; r += 4) {
-            const float4 q = *reinterpret_cast<const float4*>(src + r);
+            const vf4 q = lds_read4(src + r);
             acc[r] += (TailT)q.x;
             acc[r + 1] += (TailT)q.y;
             acc[r + 2] += (TailT)q.z;
@@ -256,11 +339,16 @@ __device__ __forceinline__ void gather_tile(const GatherCall& d, int c, int tile
   }
 }
 
+template <int R, int W>
+constexpr int lds_bytes() {
+  return 4 * (W * Geo<R>::WF + (W > 1 ? W * 64 * R : 0));
+}
+
 template <int R, int W, typename TailT>
 __global__ __launch_bounds__(64 * W) void k_gather(GatherCall d, int n_tiles) {
-  __shared__ __attribute__((aligned(16))) float lds[W * Geo<R>::WF + (W > 1 ? W * 64 * R : 0)];
-  const int tile = xcd_remap(blockIdx.x, n_tiles);
-  gather_tile<R, W, TailT>(d, blockIdx.y, tile, lds);
+  const int tile = d.tile_order == 0 ? xcd_remap(blockIdx.x, n_tiles)
+                   : d.tile_order == 1 ? center_out(blockIdx.x, n_tiles) : (int)blockIdx.x;
+  gather_tile<R, W, TailT>(d, blockIdx.y, tile);
 }
 
 // Batched: workgroup b walks work items [wg_begin[b], wg_begin[b+1]) of a
@@ -271,16 +359,15 @@ __global__ __launch_bounds__(64) void k_gather_batched(const GatherCall* __restr
                                                        const WorkItem* __restrict__ items,
                                                        const int32_t* __restrict__ wg_begin,
                                                        const int32_t* __restrict__ call_fp64) {
-  __shared__ __attribute__((aligned(16))) float lds[Geo<R>::WF];
   const int b = blockIdx.x;
   const int it0 = wg_begin[b], it1 = wg_begin[b + 1];
   for (int it = it0; it < it1; ++it) {
     const WorkItem wi = items[it];
     const GatherCall d = calls[wi.call];
     if (call_fp64[wi.call])
-      gather_tile<R, 1, double>(d, wi.channel, wi.tile, lds);
+      gather_tile<R, 1, double>(d, wi.channel, wi.tile);
     else
-      gather_tile<R, 1, float>(d, wi.channel, wi.tile, lds);
+      gather_tile<R, 1, float>(d, wi.channel, wi.tile);
     __syncthreads();
   }
 }
@@ -289,10 +376,11 @@ template <int R, int W>
 hipError_t launch_rw(const GatherCall& call, bool fp64, hipStream_t st) {
   const int n_tiles = (call.n_out + Geo<R>::T - 1) / Geo<R>::T;
   dim3 grid(n_tiles, call.channels);
+  constexpr int shmem = lds_bytes<R, W>();
   if (fp64)
-    hipLaunchKernelGGL((k_gather<R, W, double>), grid, dim3(64 * W), 0, st, call, n_tiles);
+    hipLaunchKernelGGL((k_gather<R, W, double>), grid, dim3(64 * W), shmem, st, call, n_tiles);
   else
-    hipLaunchKernelGGL((k_gather<R, W, float>), grid, dim3(64 * W), 0, st, call, n_tiles);
+    hipLaunchKernelGGL((k_gather<R, W, float>), grid, dim3(64 * W), shmem, st, call, n_tiles);
   return hipGetLastError();
 }
 
@@ -309,7 +397,8 @@ hipError_t launch_r(const GatherCall& call, bool fp64, int w, hipStream_t st) {
 template <int R>
 hipError_t launch_batched_r(const GatherCall* calls_dev, const WorkItem* items_dev, const int32_t* wg_begin_dev,
                             const int32_t* call_fp64_dev, int n_wg, hipStream_t st) {
-  hipLaunchKernelGGL(k_gather_batched<R>, dim3(n_wg), dim3(64), 0, st, calls_dev, items_dev, wg_begin_dev,
+  constexpr int shmem = lds_bytes<R, 1>();
+  hipLaunchKernelGGL(k_gather_batched<R>, dim3(n_wg), dim3(64), shmem, st, calls_dev, items_dev, wg_begin_dev,
                      call_fp64_dev);
   return hipGetLastError();
 }

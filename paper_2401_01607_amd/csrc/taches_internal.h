@@ -52,7 +52,7 @@ struct GatherCall {
   uint16_t* xs_hi;
   uint16_t* xs_lo;
   int32_t cpad;
-  int32_t pad_;
+  int32_t tile_order;    // gather path: 0 = XCD-grouped, 1 = center-out, 2 = launch order
 };
 
 // One unit of batched work: an output tile of one channel of one call.

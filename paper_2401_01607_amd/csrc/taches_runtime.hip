@@ -107,6 +107,8 @@ struct taches_stream {
   taches_pool* pool = nullptr;
   uint16_t *xs_hi = nullptr, *xs_lo = nullptr;  // split path: per-call input fragments
   int cpad = 0;                                 // channels per tail slot (split path)
+  int64_t plan_key[4] = {-1, -1, -1, -1};        // last planned call shape and its tile plan
+  int plan_val[3] = {0, 0, 0};
 };
 
 namespace {
@@ -212,40 +214,83 @@ int load_slot(taches_stream* s, int slot, const float* h, int L, bool on_device)
   return TACHES_OK;
 }
 
-// Tile shape (r outputs per lane, w waves per tile).  Estimated time of a
-// launch: the busiest CU holds ceil(tiles / 256) workgroups, i.e.
-// ceil(tiles / 256) * w / 4 waves per SIMD sharing its FMA pipe, each with
-// 1/w of a tile's r * 64 * span FMAs; a SIMD with less than one wave still
-// takes one wave's time.  Longer per-lane tiles need fewer LDS reads per FMA
-// (eff_r), and fewer than two waves per SIMD expose latency.
-void pick_tile(const taches_stream* s, int n_out, int chunks_per_tile, int* r, int* w) {
+// Tile shape (r outputs per lane, w waves per tile) and tile order.  The
+// estimate simulates the dispatch: workgroup i (in launch order) goes to XCD
+// i % 8 and, within it, round-robin over its 32 CUs; a CU's time is the FMA
+// work of its tiles divided by the SIMDs it keeps busy; the launch takes as
+// long as its busiest CU.  Work per tile is
+// the number of input samples that reach it.  Longer per-lane tiles need
+// fewer LDS reads per FMA (eff_r) and fewer than two waves per SIMD expose
+// latency.
+struct TilePlan {
+  int r = 4, w = 1, order = 0;
+};
+
+double plan_cost(int64_t S, int64_t n_out, int64_t lmax, int channels, int r, int w, int order) {
+  const int64_t T = 64 * r;
+  const int64_t nt = (n_out + T - 1) / T;
+  const int ncu = 256;
+  std::vector<double> cu(ncu, 0.0);
+  std::vector<int> cnt(ncu, 0);
+  const int64_t total = nt * channels;
+  const int64_t mid = (nt - 1) / 2;
+  const int64_t q = nt >> 3, rem = nt & 7;
+  for (int64_t id = 0; id < total; ++id) {
+    const int64_t ci = id % nt;  // launch index within one channel
+    int64_t t;
+    if (order == 0) {
+      const int64_t x = ci & 7, k = ci >> 3;
+      t = x * q + std::min(x, rem) + k;
+    } else if (order == 1) {
+      t = (ci & 1) ? mid + ((ci + 1) >> 1) : mid - (ci >> 1);
+    } else {
+      t = ci;
+    }
+    const int64_t n0 = t * T;
+    const int64_t lo = std::max<int64_t>(0, n0 - (lmax - 1));
+    const int64_t hi = std::min<int64_t>(S, n0 + T);
+    const double work = (double)std::max<int64_t>(hi - lo, 0) * T + 64.0 * T;  // + staging/tail io
+    const int c = (int)((id & 7) * 32 + (id >> 3) % 32);
+    cu[c] += work;
+    cnt[c] += 1;
+  }
+  static const double eff_r[17] = {0, 0, 0, 0, 0.85, 0, 0, 0, 0.92, 0, 0, 0, 0.95, 0, 0, 0, 0.97};
+  double worst = 0.0;
+  for (int i = 0; i < ncu; ++i) {
+    const double waves = (double)cnt[i] * w;
+    const double simds = std::min(4.0, waves);
+    double t = simds > 0 ? cu[i] / simds : 0.0;
+    if (waves < 8.0) t /= 0.9;  // fewer than two waves per SIMD
+    worst = std::max(worst, t);
+  }
+  return worst / eff_r[r];
+}
+
+TilePlan pick_tile(const taches_stream* s, int64_t S, int64_t n_out, int64_t lmax, int chunks_per_tile) {
+  TilePlan best;
   if (s->force_r) {
-    *r = s->force_r;
-    *w = s->force_w ? s->force_w : 1;
-    return;
+    best.r = s->force_r;
+    best.w = s->force_w ? s->force_w : 1;
+    best.order = 2;
+    return best;
   }
   static const int rs[4] = {16, 12, 8, 4};
-  static const double eff_r[4] = {0.97, 0.96, 0.93, 0.85};
   static const int ws[3] = {1, 2, 4};
-  double best = 1e300;
-  *r = 4;
-  *w = 1;
-  for (int i = 0; i < 4; ++i) {
-    for (int wi : ws) {
-      if (wi > 1 && chunks_per_tile < 2 * wi) continue;
-      const int64_t tiles = (int64_t)s->cfg.channels * ((n_out + 64 * rs[i] - 1) / (64 * rs[i]));
-      const double per_cu = (double)((tiles + 255) / 256);
-      const double simd_load = per_cu * wi / 4.0;
-      const double per_wave = 64.0 * rs[i] / wi;
-      double cost = std::max(simd_load, 1.0) * per_wave / eff_r[i];
-      if (simd_load < 2.0) cost /= 0.9;
-      if (cost < best * 0.999) {
-        best = cost;
-        *r = rs[i];
-        *w = wi;
+  double best_cost = 1e300;
+  for (int r : rs)
+    for (int w : ws) {
+      if (w > 1 && chunks_per_tile < 2 * w) continue;
+      for (int order = 0; order < 3; ++order) {
+        const double c = plan_cost(S, n_out, lmax, s->cfg.channels, r, w, order);
+        if (c < best_cost * 0.999) {
+          best_cost = c;
+          best.r = r;
+          best.w = w;
+          best.order = order;
+        }
       }
     }
-  }
+  return best;
 }
 
 int process_common(taches_stream* s, const float* x_dev, float* y_dev, int n_blocks, const int32_t* sched) {
@@ -342,8 +387,21 @@ int process_common(taches_stream* s, const float* x_dev, float* y_dev, int n_blo
     s->last_w = 0;
   } else {
     const int span_blocks = (int)std::min<int64_t>(n_blocks, (64 * 16 + g.Lmax_call - 1 + B - 1) / B + 1);
-    int r, w;
-    pick_tile(s, (int)n_out, x_dev ? span_blocks * g.cpb : 0, &r, &w);
+    const int64_t key[4] = {S, n_out, x_dev ? g.Lmax_call : 1, (int64_t)s->force_r * 8 + s->force_w};
+    TilePlan plan;
+    if (std::equal(key, key + 4, s->plan_key)) {
+      plan.r = s->plan_val[0];
+      plan.w = s->plan_val[1];
+      plan.order = s->plan_val[2];
+    } else {
+      plan = pick_tile(s, S, n_out, x_dev ? g.Lmax_call : 1, x_dev ? span_blocks * g.cpb : 0);
+      std::copy(key, key + 4, s->plan_key);
+      s->plan_val[0] = plan.r;
+      s->plan_val[1] = plan.w;
+      s->plan_val[2] = plan.order;
+    }
+    const int r = plan.r, w = plan.w;
+    g.tile_order = plan.order;
     hipError_t e = taches::launch_gather(g, s->tail_fp64, r, w, s->stream);
     if (e != hipSuccess) return fail(TACHES_EDEVICE, "gather launch: %s", hipGetErrorString(e));
     s->last_r = r;
