@@ -44,6 +44,9 @@ def parse():
     p.add_argument("--tile", type=str, default="", help="force gather tile 'R,W'")
     p.add_argument("--calibrate-copy", type=int, default=0, metavar="MB",
                    help="only run a plain device copy of MB megabytes (HBM counter calibration)")
+    p.add_argument("--no-extras", action="store_true",
+                   help="skip the multichannel, batched and latency comparisons")
+    p.add_argument("--only", type=str, default="", help="run one extra section only (c1, c3, c4, c5)")
     return p.parse_args()
 
 
@@ -199,11 +202,197 @@ def main():
         },
     }
 
+    if not args.no_extras:
+        out["extras"] = extras(args)
+
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, args.cpu_seconds)
 
     print(json.dumps(out), flush=True)
     s.close()
+
+
+def _timed(fn, reps=3, warm=1):
+    """Median wall time of fn() (synchronized) over reps runs."""
+    import torch
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    return float(np.median(ts))
+
+
+def extra_c1_latency():
+    """Plain taches, 1 mono stream, L = 1024, B = 64: host-synchronous
+    per-block latency (taches_process with host buffers)."""
+    from paper_2401_01607_amd import taches as T
+    from paper_2401_01607_amd import workloads as W
+    spec = W.config1()
+    B = spec.block
+    s = T.Stream(B, spec.max_ir_len)
+    s.set_ir(spec.irs[0])
+    y = np.zeros(B, np.float32)
+    lat = []
+    for b in range(spec.n_blocks()):
+        xb = np.ascontiguousarray(spec.x[0, b * B:(b + 1) * B])
+        if xb.size < B:
+            xb = np.pad(xb, (0, B - xb.size))
+        t0 = time.perf_counter()
+        assert T.taches_process(s.h, xb, y) == 0
+        lat.append(time.perf_counter() - t0)
+    s.close()
+    us = np.array(lat[20:]) * 1e6
+    return {"workload": "1 mono stream, 48000 uniform samples, L=1024, B=64, one taches_process per block",
+            "p50_us": round(float(np.percentile(us, 50)), 2), "p99_us": round(float(np.percentile(us, 99)), 2),
+            "max_us": round(float(us.max()), 2), "deadline_us": round(B / 48_000 * 1e6, 1),
+            "gmacs": round(spec.direct_macs() / float(np.sum(lat)) / 1e9, 3)}
+
+
+def extra_c3_split_vs_fp32():
+    """64 channels x 240 000 samples sharing one IR of 2^18 taps, B = 512:
+    split-BF16 Toeplitz MFMA (FP64 tail) vs the FP32 gather (FP64 tail),
+    whole signal in one call each, device-resident."""
+    import torch
+    from paper_2401_01607_amd import taches as T
+    from paper_2401_01607_amd import workloads as W
+    spec = W.config3()
+    B, L, C = spec.block, spec.max_ir_len, spec.channels
+    nb = spec.n_blocks()
+    macs = spec.direct_macs()
+    xp = np.zeros((C, nb * B), np.float32)
+    xp[:, :spec.n_samples] = spec.x
+    xd = torch.from_numpy(xp).cuda()
+    res = {"workload": "64 channels x 240000 Gaussian samples, one decaying-noise IR L=262144, B=512, "
+                       "469 blocks in one call", "direct_macs": macs}
+    outs = {}
+    for name, prec in (("split_bf16", T.TACHES_PREC_SPLIT_BF16), ("fp32", T.TACHES_PREC_FP32)):
+        s = T.Stream(B, L, channels=C, max_blocks_per_call=nb, precision=prec)
+        s.set_ir(spec.irs[0])
+        yd = torch.empty_like(xd)
+
+        def run():
+            # each run starts from an empty tail: drain is not part of it
+            s.process_blocks(xd, yd, nb)
+        run()
+        torch.cuda.synchronize()
+        # reopen so every timed run starts from the same empty tail
+        s.close()
+        s = T.Stream(B, L, channels=C, max_blocks_per_call=nb, precision=prec)
+        s.set_ir(spec.irs[0])
+        st = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        s.process_blocks(xd, yd, nb)
+        e1.record(st)
+        torch.cuda.synchronize()
+        sec = e0.elapsed_time(e1) / 1e3
+        info = s.info()
+        res[name] = {"ms": round(sec * 1e3, 3), "gmacs": round(macs / sec / 1e9, 1),
+                     "tail": "fp64" if info.tail_fp64 else "fp32"}
+        if name == "split_bf16":
+            # MFMA work: three BF16 products per direct MAC (plus Toeplitz padding)
+            res[name]["mfma_tflops_bf16"] = round(3 * 2 * macs / sec / 1e12, 1)
+            res[name]["frac_of_bf16_dense_peak"] = round(3 * 2 * macs / sec / 2.5e15, 4)
+        else:
+            res[name]["tflops"] = round(2 * macs / sec / 1e12, 2)
+            res[name]["tile"] = [info.tile_r, info.tile_w]
+        outs[name] = yd.clone()
+        s.close()
+    d = (outs["split_bf16"].double() - outs["fp32"].double()).abs().max().item()
+    rms = outs["fp32"].double().pow(2).mean().sqrt().item()
+    res["speedup_split_over_fp32"] = round(res["fp32"]["ms"] / res["split_bf16"]["ms"], 2)
+    res["max_abs_split_minus_fp32_over_rms"] = float(f"{d / rms:.3e}")
+    return res
+
+
+def extra_c4_batched_vs_plain():
+    """512 independent mono streams of 96 000 samples, L log-uniform in
+    [256, 131072], B in {32..512}: every stream's whole input in one pool
+    step (one persistent launch replayed from a hipGraph) vs one
+    taches_process_blocks launch per stream."""
+    import torch
+    from paper_2401_01607_amd import taches as T
+    from paper_2401_01607_amd import workloads as W
+    Ls, Bs = W.config4_draws()
+    n = 96_000
+    nbs = [-(-n // B) for B in Bs]
+    macs = sum(n * L for L in Ls)
+    xs, ys = [], []
+    for i, (L, B) in enumerate(zip(Ls, Bs)):
+        xp = np.zeros(nbs[i] * B, np.float32)
+        xp[:n] = W.signal_gauss(n, 410_000 + i)
+        xs.append(torch.from_numpy(xp).cuda()[None])
+        ys.append(torch.empty_like(xs[-1]))
+    irs = [W.impulse_response(L, 420_000 + i) for i, L in enumerate(Ls)]
+
+    def open_streams():
+        ss = []
+        for i, (L, B) in enumerate(zip(Ls, Bs)):
+            s = T.Stream(B, L, max_blocks_per_call=nbs[i])
+            s.set_ir(irs[i])
+            ss.append(s)
+        return ss
+
+    res = {"workload": "512 mono streams x 96000 Gaussian samples, L log-uniform [256, 131072], "
+                       "B from {32..512}, whole input per stream", "direct_macs": macs}
+    # plain: one launch per stream
+    ss = open_streams()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s, x, y, nb in zip(ss, xs, ys, nbs):
+        s.process_blocks(x, y, nb)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    alone = [ys[i].clone() for i in range(0, 512, 64)]
+    for s in ss:
+        s.close()
+    # batched: one pool step per repetition, replayed from the pool's graph
+    timings = []
+    pool = T.Pool(512, 1 << 40, use_graph=True)
+    for rep in range(4):
+        ss = open_streams()
+        for s in ss:
+            pool.attach(s)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pool.step(ss, xs, ys, nbs)
+        torch.cuda.synchronize()
+        timings.append(time.perf_counter() - t0)
+        info = pool.info()
+        for s in ss:
+            pool.detach(s)
+            s.close()
+    pool.close()
+    timings = timings[1:]  # the first step also captures the graph
+    t_batch = float(np.median(timings))
+    same = all(torch.equal(a, ys[i * 64]) for i, a in enumerate(alone))
+    res["plain"] = {"ms": round(t_plain * 1e3, 2), "gmacs": round(macs / t_plain / 1e9, 1)}
+    res["batched"] = {"ms": round(t_batch * 1e3, 2), "gmacs": round(macs / t_batch / 1e9, 1),
+                      "tflops": round(2 * macs / t_batch / 1e12, 2),
+                      "frac_of_fp32_peak": round(2 * macs / t_batch / 1e12 / FP32_PEAK_TFLOPS, 4),
+                      "tile_r": info.last_r, "items": info.last_items, "workgroups": info.last_workgroups,
+                      "plan_ms": round(info.last_plan_ms, 2), "imbalance": round(info.last_imbalance, 4),
+                      "graph_replays": int(info.graph_replays)}
+    res["speedup_batched_over_plain"] = round(t_plain / t_batch, 2)
+    res["batched_equals_alone_bitwise"] = bool(same)
+    return res
+
+
+def extras(args):
+    out = {}
+    sections = {"c1": extra_c1_latency, "c3": extra_c3_split_vs_fp32, "c4": extra_c4_batched_vs_plain}
+    for name, fn in sections.items():
+        if args.only and args.only != name:
+            continue
+        t0 = time.perf_counter()
+        out[name] = fn()
+        out[name]["section_s"] = round(time.perf_counter() - t0, 1)
+    return out
 
 
 def cpu_baseline(spec, target_s):

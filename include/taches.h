@@ -176,6 +176,66 @@ int taches_read_tail(taches_stream* s, int32_t channel, double* out, int32_t n);
  * per output tile in {1, 2, 4}); 0, 0 = automatic choice per call. */
 int taches_set_tile(taches_stream* s, int32_t r, int32_t w);
 
+/* ---- a6/a7: pools — many streams advanced by one batched launch ----------
+ *
+ * A pool admits streams up to a stream count and an HBM byte budget (the
+ * sum of the attached streams' device_bytes).  taches_pool_step advances a
+ * set of attached streams by n_blocks[i] blocks each in one persistent
+ * launch: the host cuts every stream's call into output tiles and spreads
+ * them over the resident workgroups, largest first.  Each stream's result
+ * is bit-identical to processing it alone.  While attached, a stream's
+ * device work runs on the pool's HIP stream; taches_set_ir and
+ * taches_load_ir_slot stay usable (a pending IR applies at the stream's next
+ * step); taches_process* and taches_close return TACHES_EBUSY. */
+
+/* NULL on failure.  max_streams in [1, 2^20], hbm_budget_bytes >= 0. */
+taches_pool* taches_pool_create(int32_t max_streams, int64_t hbm_budget_bytes, int32_t device);
+
+/* TACHES_EBUSY while streams are attached.  NULL is a no-op. */
+int taches_pool_destroy(taches_pool* p);
+
+/* Admit a stream: TACHES_EBUSY if the pool is full or the stream is already
+ * in a pool, TACHES_ENOMEM if its device bytes exceed the remaining budget. */
+int taches_pool_attach(taches_pool* p, taches_stream* s);
+
+/* Release the stream's slot and bytes; waits for the pool's work first. */
+int taches_pool_detach(taches_pool* p, taches_stream* s);
+
+/* Advance n attached streams (each listed once): stream i processes
+ * n_blocks[i] blocks, input x_dev[i] ([C][n_blocks*B] device, or NULL /
+ * x_dev == NULL for zero input), output y_dev[i] (same shape).  Device
+ * buffers must stay alive until the pool's HIP stream has run the step.
+ * On error no stream is advanced. */
+int taches_pool_step(taches_pool* p, int32_t n, taches_stream* const* streams, const float* const* x_dev,
+                     float* const* y_dev, const int32_t* n_blocks);
+
+/* HIP stream for the pool and its attached streams (NULL = HIP's null
+ * stream).  Work already enqueued is first waited for. */
+int taches_pool_set_hip_stream(taches_pool* p, void* hip_stream);
+
+/* Per-lane tile of the batched kernel (4, 8, 12, 16; 0 = automatic). */
+int taches_pool_set_tile(taches_pool* p, int32_t r);
+
+/* Run each step as a replay of a captured hipGraph (table copy + kernel);
+ * the graph is captured again when the tile or workgroup count changes. */
+int taches_pool_use_graph(taches_pool* p, int32_t on);
+
+int taches_pool_synchronize(taches_pool* p);
+
+typedef struct taches_pool_info {
+  int32_t attached, max_streams;
+  int64_t budget_bytes, used_bytes;
+  int32_t last_items;       /* work items of the last step */
+  int32_t last_workgroups;  /* persistent workgroups of the last step */
+  int32_t last_r;           /* per-lane tile of the last step */
+  int32_t pad_;
+  int64_t graph_replays;
+  double last_plan_ms;      /* host time to plan the last step */
+  double last_imbalance;    /* busiest workgroup's work / mean work */
+} taches_pool_info;
+
+int taches_pool_get_info(const taches_pool* p, taches_pool_info* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -351,14 +351,17 @@ __global__ __launch_bounds__(64 * W) void k_gather(GatherCall d, int n_tiles) {
   gather_tile<R, W, TailT>(d, blockIdx.y, tile);
 }
 
-// Batched: workgroup b walks work items [wg_begin[b], wg_begin[b+1]) of a
-// host-built list (largest items first, balanced over workgroups).  Each
-// call's tail type is chosen per stream.
+// Batched: one packed table (header, call descriptors, per-call tail type,
+// per-workgroup item ranges, work items).  Workgroup b walks items
+// [wg_begin[b], wg_begin[b+1]) of a host-built list (largest items first,
+// balanced over workgroups); each call's tail type is chosen per stream.
 template <int R>
-__global__ __launch_bounds__(64) void k_gather_batched(const GatherCall* __restrict__ calls,
-                                                       const WorkItem* __restrict__ items,
-                                                       const int32_t* __restrict__ wg_begin,
-                                                       const int32_t* __restrict__ call_fp64) {
+__global__ __launch_bounds__(64) void k_gather_batched(const unsigned char* __restrict__ table) {
+  const BatchHeader hd = *reinterpret_cast<const BatchHeader*>(table);
+  const GatherCall* __restrict__ calls = reinterpret_cast<const GatherCall*>(table + hd.off_calls);
+  const int32_t* __restrict__ call_fp64 = reinterpret_cast<const int32_t*>(table + hd.off_fp64);
+  const int32_t* __restrict__ wg_begin = reinterpret_cast<const int32_t*>(table + hd.off_wgb);
+  const WorkItem* __restrict__ items = reinterpret_cast<const WorkItem*>(table + hd.off_items);
   const int b = blockIdx.x;
   const int it0 = wg_begin[b], it1 = wg_begin[b + 1];
   for (int it = it0; it < it1; ++it) {
@@ -395,11 +398,9 @@ hipError_t launch_r(const GatherCall& call, bool fp64, int w, hipStream_t st) {
 }
 
 template <int R>
-hipError_t launch_batched_r(const GatherCall* calls_dev, const WorkItem* items_dev, const int32_t* wg_begin_dev,
-                            const int32_t* call_fp64_dev, int n_wg, hipStream_t st) {
+hipError_t launch_batched_r(const unsigned char* table_dev, int n_wg, hipStream_t st) {
   constexpr int shmem = lds_bytes<R, 1>();
-  hipLaunchKernelGGL(k_gather_batched<R>, dim3(n_wg), dim3(64), shmem, st, calls_dev, items_dev, wg_begin_dev,
-                     call_fp64_dev);
+  hipLaunchKernelGGL(k_gather_batched<R>, dim3(n_wg), dim3(64), shmem, st, table_dev);
   return hipGetLastError();
 }
 
@@ -416,15 +417,26 @@ hipError_t launch_gather(const GatherCall& call, bool tail_fp64, int r, int w, h
   }
 }
 
-hipError_t launch_gather_batched(const GatherCall* calls_dev, const WorkItem* items_dev,
-                                 const int32_t* wg_begin_dev, const int32_t* call_fp64_dev, int n_wg,
-                                 int r, hipStream_t st) {
+int gather_batched_waves_per_cu(int r) {
+  int n = 0;
+  hipError_t e = hipErrorInvalidValue;
+  switch (r) {
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gather_batched<4>, 64, lds_bytes<4, 1>()); break;
+    case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gather_batched<8>, 64, lds_bytes<8, 1>()); break;
+    case 12: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gather_batched<12>, 64, lds_bytes<12, 1>()); break;
+    case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gather_batched<16>, 64, lds_bytes<16, 1>()); break;
+    default: break;
+  }
+  return (e == hipSuccess && n > 0) ? n : 8;
+}
+
+hipError_t launch_gather_batched(const unsigned char* table_dev, int n_wg, int r, hipStream_t st) {
   if (n_wg <= 0) return hipSuccess;
   switch (r) {
-    case 4: return launch_batched_r<4>(calls_dev, items_dev, wg_begin_dev, call_fp64_dev, n_wg, st);
-    case 8: return launch_batched_r<8>(calls_dev, items_dev, wg_begin_dev, call_fp64_dev, n_wg, st);
-    case 12: return launch_batched_r<12>(calls_dev, items_dev, wg_begin_dev, call_fp64_dev, n_wg, st);
-    case 16: return launch_batched_r<16>(calls_dev, items_dev, wg_begin_dev, call_fp64_dev, n_wg, st);
+    case 4: return launch_batched_r<4>(table_dev, n_wg, st);
+    case 8: return launch_batched_r<8>(table_dev, n_wg, st);
+    case 12: return launch_batched_r<12>(table_dev, n_wg, st);
+    case 16: return launch_batched_r<16>(table_dev, n_wg, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -65,11 +65,18 @@ struct WorkItem {
 
 // Kernel launchers (k_gather.hip).  r in {4, 8, 12, 16}, w in {1, 2, 4}.
 hipError_t launch_gather(const GatherCall& call, bool tail_fp64, int r, int w, hipStream_t st);
-hipError_t launch_gather_batched(const GatherCall* calls_dev, const WorkItem* items_dev,
-                                 const int32_t* wg_begin_dev, const int32_t* call_fp64_dev, int n_wg,
-                                 int r, hipStream_t st);
+// Packed table of a batched launch: this header, then the sub-tables at the
+// given byte offsets (GatherCall[n_calls], int32 tail-is-FP64[n_calls],
+// int32 wg_begin[n_wg + 1], WorkItem[n_items]).
+struct BatchHeader {
+  int32_t off_calls, off_fp64, off_wgb, off_items;
+};
+hipError_t launch_gather_batched(const unsigned char* table_dev, int n_wg, int r, hipStream_t st);
 
 inline int tile_outputs(int r) { return 64 * r; }
+
+// Resident one-wave workgroups per CU of the batched gather kernel.
+int gather_batched_waves_per_cu(int r);
 
 // IR staging for the split-BF16 path (k_toeplitz.hip): hi = RN_bf16(h),
 // lo = RN_bf16(h - hi), bit patterns stored as uint16.

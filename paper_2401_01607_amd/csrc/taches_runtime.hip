@@ -1,6 +1,7 @@
 // Host runtime and C-ABI of libtaches: stream handles, IR slots, the
 // circular tail, call planning and kernel launches.
 #include <algorithm>
+#include <chrono>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -105,6 +106,7 @@ struct taches_stream {
   int force_r = 0, force_w = 0, last_r = 0, last_w = 0;
   int64_t device_bytes = 0;
   taches_pool* pool = nullptr;
+  hipStream_t stream_before_pool = nullptr;
   uint16_t *xs_hi = nullptr, *xs_lo = nullptr;  // split path: per-call input fragments
   int cpad = 0;                                 // channels per tail slot (split path)
   int64_t plan_key[4] = {-1, -1, -1, -1};        // last planned call shape and its tile plan
@@ -293,14 +295,24 @@ TilePlan pick_tile(const taches_stream* s, int64_t S, int64_t n_out, int64_t lma
   return best;
 }
 
-int process_common(taches_stream* s, const float* x_dev, float* y_dev, int n_blocks, const int32_t* sched) {
+// A planned call: the kernel descriptor plus the stream state to commit once
+// the call is enqueued.
+struct CallPlan {
+  GatherCall g{};
+  int next_active = -1;
+  int64_t S = 0, n_out = 0;
+  int n_blocks = 0;
+};
+
+// Validate a call and build its descriptor.  Uploads the per-block IR table
+// when the IR changes inside the call.  Nothing is launched.
+int plan_call(taches_stream* s, const float* x_dev, float* y_dev, int n_blocks, const int32_t* sched, CallPlan* out) {
   const taches_config& c = s->cfg;
   if (n_blocks < 1 || n_blocks > c.max_blocks_per_call)
     return fail(TACHES_EINVAL, "n_blocks %d outside [1, %d]", n_blocks, c.max_blocks_per_call);
   if (!y_dev) return fail(TACHES_EINVAL, "y is NULL");
-  if (s->pool) return fail(TACHES_EBUSY, "stream is attached to a pool");
   // resolve the IR of every block: a pending set_ir applies first, then the schedule
-  int act = s->pending >= 0 ? s->pending : s->active;
+  const int act = s->pending >= 0 ? s->pending : s->active;
   if (sched) {
     for (int b = 0; b < n_blocks; ++b) {
       const int k = sched[b];
@@ -326,11 +338,11 @@ int process_common(taches_stream* s, const float* x_dev, float* y_dev, int n_blo
       ext = std::max<int64_t>(ext, (int64_t)b * B + B + L - 1);
     }
   }
-  if (x_dev && cur < 0) return fail(TACHES_ENOIR, "no impulse response set");
   const int64_t n_out = std::max<int64_t>(std::max<int64_t>(S, s->live), ext);
   if (n_out > s->Rcap) return fail(TACHES_EINVAL, "call needs %lld tail slots, ring has %d", (long long)n_out, s->Rcap);
 
-  GatherCall g{};
+  GatherCall& g = out->g;
+  g = GatherCall{};
   g.x = x_dev;
   g.y = y_dev;
   g.ring = s->ring;
@@ -379,40 +391,63 @@ int process_common(taches_stream* s, const float* x_dev, float* y_dev, int n_blo
     s->irtab_pending = true;
     g.irs = s->irtab_dev;
   }
+  out->next_active = cur >= 0 ? cur : act;
+  out->S = S;
+  out->n_out = n_out;
+  out->n_blocks = n_blocks;
+  return TACHES_OK;
+}
 
-  if (c.precision == TACHES_PREC_SPLIT_BF16) {
+void commit_call(taches_stream* s, const CallPlan& p) {
+  s->active = p.next_active;
+  s->pending = -1;
+  s->head = (int)((s->head + p.S) % s->Rcap);
+  s->live = (int)(p.n_out - p.S);
+  s->blocks_done += p.n_blocks;
+}
+
+// Launch one planned call on the stream's own kernels.
+int launch_call(taches_stream* s, CallPlan& p) {
+  GatherCall& g = p.g;
+  if (s->cfg.precision == TACHES_PREC_SPLIT_BF16) {
     hipError_t e = taches::launch_toeplitz(g, s->tail_fp64, s->stream);
     if (e != hipSuccess) return fail(TACHES_EDEVICE, "toeplitz launch: %s", hipGetErrorString(e));
     s->last_r = 0;
     s->last_w = 0;
-  } else {
-    const int span_blocks = (int)std::min<int64_t>(n_blocks, (64 * 16 + g.Lmax_call - 1 + B - 1) / B + 1);
-    const int64_t key[4] = {S, n_out, x_dev ? g.Lmax_call : 1, (int64_t)s->force_r * 8 + s->force_w};
-    TilePlan plan;
-    if (std::equal(key, key + 4, s->plan_key)) {
-      plan.r = s->plan_val[0];
-      plan.w = s->plan_val[1];
-      plan.order = s->plan_val[2];
-    } else {
-      plan = pick_tile(s, S, n_out, x_dev ? g.Lmax_call : 1, x_dev ? span_blocks * g.cpb : 0);
-      std::copy(key, key + 4, s->plan_key);
-      s->plan_val[0] = plan.r;
-      s->plan_val[1] = plan.w;
-      s->plan_val[2] = plan.order;
-    }
-    const int r = plan.r, w = plan.w;
-    g.tile_order = plan.order;
-    hipError_t e = taches::launch_gather(g, s->tail_fp64, r, w, s->stream);
-    if (e != hipSuccess) return fail(TACHES_EDEVICE, "gather launch: %s", hipGetErrorString(e));
-    s->last_r = r;
-    s->last_w = w;
+    return TACHES_OK;
   }
-  // commit the new stream state
-  s->active = cur >= 0 ? cur : act;
-  s->pending = -1;
-  s->head = (int)((s->head + S) % s->Rcap);
-  s->live = (int)(n_out - S);
-  s->blocks_done += n_blocks;
+  const int B = g.B;
+  const bool has_x = g.x != nullptr;
+  const int span_blocks = (int)std::min<int64_t>(g.n_blocks, (64 * 16 + g.Lmax_call - 1 + B - 1) / B + 1);
+  const int64_t key[4] = {p.S, p.n_out, has_x ? g.Lmax_call : 1, (int64_t)s->force_r * 8 + s->force_w};
+  TilePlan plan;
+  if (std::equal(key, key + 4, s->plan_key)) {
+    plan.r = s->plan_val[0];
+    plan.w = s->plan_val[1];
+    plan.order = s->plan_val[2];
+  } else {
+    plan = pick_tile(s, p.S, p.n_out, has_x ? g.Lmax_call : 1, has_x ? span_blocks * g.cpb : 0);
+    std::copy(key, key + 4, s->plan_key);
+    s->plan_val[0] = plan.r;
+    s->plan_val[1] = plan.w;
+    s->plan_val[2] = plan.order;
+  }
+  g.tile_order = plan.order;
+  hipError_t e = taches::launch_gather(g, s->tail_fp64, plan.r, plan.w, s->stream);
+  if (e != hipSuccess) return fail(TACHES_EDEVICE, "gather launch: %s", hipGetErrorString(e));
+  s->last_r = plan.r;
+  s->last_w = plan.w;
+  return TACHES_OK;
+}
+
+int process_common(taches_stream* s, const float* x_dev, float* y_dev, int n_blocks, const int32_t* sched) {
+  if (s->pool) return fail(TACHES_EBUSY, "stream is attached to a pool; use taches_pool_step");
+  CallPlan p;
+  int rc = plan_call(s, x_dev, y_dev, n_blocks, sched, &p);
+  if (rc != TACHES_OK) return rc;
+  rc = launch_call(s, p);
+  if (rc != TACHES_OK) return rc;
+  commit_call(s, p);
   return TACHES_OK;
 }
 
@@ -467,6 +502,7 @@ int taches_close(taches_stream* s) {
 
 int taches_set_hip_stream(taches_stream* s, void* hip_stream) {
   if (!s) return fail(TACHES_EINVAL, "stream is NULL");
+  if (s->pool) return fail(TACHES_EBUSY, "stream is attached to a pool; it runs on the pool's HIP stream");
   hipStream_t next = (hipStream_t)hip_stream;  // NULL: HIP's null stream
   if (next != s->stream) {
     HIPCHK(hipStreamSynchronize(s->stream));
@@ -485,7 +521,6 @@ static int set_ir_common(taches_stream* s, const float* h, int32_t L, bool on_de
   if (!s) return fail(TACHES_EINVAL, "stream is NULL");
   if (!h) return fail(TACHES_EINVAL, "h is NULL");
   if (L < 1 || L > s->cfg.max_ir_len) return fail(TACHES_EINVAL, "L=%d outside [1, %d]", L, s->cfg.max_ir_len);
-  if (s->pool) return fail(TACHES_EBUSY, "stream is attached to a pool; use the pool's IR call");
   int slot = s->pending;
   if (slot < 0) {
     for (int k = 0; k < (int)s->slots.size(); ++k)
@@ -509,7 +544,6 @@ int taches_load_ir_slot(taches_stream* s, int32_t slot, const float* h, int32_t 
   if (slot < 0 || slot >= (int)s->slots.size()) return fail(TACHES_EINVAL, "slot %d outside [0, %zu)", slot, s->slots.size());
   if (!h) return fail(TACHES_EINVAL, "h is NULL");
   if (L < 1 || L > s->cfg.max_ir_len) return fail(TACHES_EINVAL, "L=%d outside [1, %d]", L, s->cfg.max_ir_len);
-  if (s->pool) return fail(TACHES_EBUSY, "stream is attached to a pool");
   if (slot == s->pending) s->pending = -1;
   return load_slot(s, slot, h, L, h_on_device != 0);
 }
@@ -624,6 +658,378 @@ int taches_set_tile(taches_stream* s, int32_t r, int32_t w) {
     return fail(TACHES_EINVAL, "tile (%d, %d) not in {4,8,12,16} x {1,2,4}", r, w);
   s->force_r = r;
   s->force_w = w;
+  return TACHES_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Pools: many streams advanced by one batched launch.
+// ===========================================================================
+
+using taches::WorkItem;
+
+struct taches_pool {
+  int max_streams = 0;
+  int64_t budget = 0, used = 0;
+  int device = 0;
+  std::vector<taches_stream*> attached;
+  hipStream_t own = nullptr, stream = nullptr, capture = nullptr;
+  // one packed table: [calls][fp64 flags][wg_begin][items], pinned and device
+  unsigned char* tab_pin = nullptr;
+  unsigned char* tab_dev = nullptr;
+  size_t tab_cap = 0;
+  hipEvent_t tab_free = nullptr;
+  bool tab_pending = false;
+  int force_r = 0;
+  bool use_graph = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipGraphNode_t copy_node = nullptr;
+  int graph_r = 0, graph_nwg = 0;
+  size_t graph_cap = 0;
+  int64_t replays = 0;
+  int last_items = 0, last_wg = 0, last_r = 0;
+  double last_plan_ms = 0.0;
+  double last_imbalance = 0.0;
+};
+
+namespace {
+
+void pool_drop_graph(taches_pool* p) {
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  p->exec = nullptr;
+  p->graph = nullptr;
+  p->copy_node = nullptr;
+}
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+int pool_reserve(taches_pool* p, size_t bytes) {
+  if (bytes <= p->tab_cap) return TACHES_OK;
+  if (p->tab_pending) {
+    HIPCHK(hipEventSynchronize(p->tab_free));
+    p->tab_pending = false;
+  }
+  HIPCHK(hipStreamSynchronize(p->stream));
+  pool_drop_graph(p);
+  (void)hipHostFree(p->tab_pin);
+  (void)hipFree(p->tab_dev);
+  p->tab_pin = nullptr;
+  p->tab_dev = nullptr;
+  p->tab_cap = 0;
+  const size_t cap = align256(bytes + bytes / 2);
+  hipError_t e = hipHostMalloc((void**)&p->tab_pin, cap, hipHostMallocDefault);
+  if (e != hipSuccess) return fail(TACHES_ENOMEM, "pool table (host): %s", hipGetErrorString(e));
+  e = hipMalloc((void**)&p->tab_dev, cap);
+  if (e != hipSuccess) return fail(TACHES_ENOMEM, "pool table (device): %s", hipGetErrorString(e));
+  p->tab_cap = cap;
+  return TACHES_OK;
+}
+
+// Tile shape of a batched launch: the same per-lane tile for every stream.
+// Longer tiles need fewer LDS reads per FMA; the largest one that still
+// leaves about four items per resident workgroup keeps the greedy balance
+// tight.
+int pool_pick_r(const taches_pool* p, const std::vector<const GatherCall*>& calls) {
+  if (p->force_r) return p->force_r;
+  static const int rs[4] = {16, 12, 8, 4};
+  for (int r : rs) {
+    const int64_t T = 64 * r;
+    int64_t items = 0;
+    for (const GatherCall* g : calls) items += (int64_t)g->channels * ((g->n_out + T - 1) / T);
+    if (items >= 4LL * 256 * taches::gather_batched_waves_per_cu(r)) return r;
+  }
+  return 4;
+}
+
+}  // namespace
+
+extern "C" {
+
+taches_pool* taches_pool_create(int32_t max_streams, int64_t hbm_budget_bytes, int32_t device) {
+  if (max_streams < 1 || max_streams > (1 << 20) || hbm_budget_bytes < 0) {
+    fail(TACHES_EINVAL, "max_streams must be in [1, 2^20] and the budget >= 0");
+    return nullptr;
+  }
+  taches_pool* p = new (std::nothrow) taches_pool();
+  if (!p) {
+    fail(TACHES_ENOMEM, "out of host memory");
+    return nullptr;
+  }
+  p->max_streams = max_streams;
+  p->budget = hbm_budget_bytes;
+  p->device = device;
+  if (hipSetDevice(device) != hipSuccess || hipStreamCreateWithFlags(&p->own, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&p->capture, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&p->tab_free, hipEventDisableTiming) != hipSuccess) {
+    fail(TACHES_EDEVICE, "pool stream/event creation failed");
+    if (p->own) (void)hipStreamDestroy(p->own);
+    if (p->capture) (void)hipStreamDestroy(p->capture);
+    delete p;
+    return nullptr;
+  }
+  p->stream = p->own;
+  return p;
+}
+
+int taches_pool_destroy(taches_pool* p) {
+  if (!p) return TACHES_OK;
+  if (!p->attached.empty()) return fail(TACHES_EBUSY, "pool still has %zu attached streams", p->attached.size());
+  (void)hipStreamSynchronize(p->stream);
+  pool_drop_graph(p);
+  (void)hipHostFree(p->tab_pin);
+  (void)hipFree(p->tab_dev);
+  if (p->tab_free) (void)hipEventDestroy(p->tab_free);
+  (void)hipStreamDestroy(p->own);
+  (void)hipStreamDestroy(p->capture);
+  delete p;
+  return TACHES_OK;
+}
+
+int taches_pool_set_hip_stream(taches_pool* p, void* hip_stream) {
+  if (!p) return fail(TACHES_EINVAL, "pool is NULL");
+  hipStream_t next = (hipStream_t)hip_stream;
+  if (next != p->stream) {
+    HIPCHK(hipStreamSynchronize(p->stream));
+    p->stream = next;
+    for (taches_stream* s : p->attached) s->stream = next;
+  }
+  return TACHES_OK;
+}
+
+int taches_pool_attach(taches_pool* p, taches_stream* s) {
+  if (!p || !s) return fail(TACHES_EINVAL, "NULL argument");
+  if (s->pool) return fail(TACHES_EBUSY, "stream already attached to a pool");
+  if ((int)p->attached.size() >= p->max_streams) return fail(TACHES_EBUSY, "pool has no free slot (%d streams)", p->max_streams);
+  if (s->cfg.device != p->device) return fail(TACHES_EINVAL, "stream and pool are on different devices");
+  if (p->used + s->device_bytes > p->budget)
+    return fail(TACHES_ENOMEM, "HBM budget: %lld + %lld bytes exceed %lld", (long long)p->used, (long long)s->device_bytes,
+                (long long)p->budget);
+  HIPCHK(hipStreamSynchronize(s->stream));
+  s->stream_before_pool = s->stream;
+  s->stream = p->stream;
+  s->pool = p;
+  p->used += s->device_bytes;
+  p->attached.push_back(s);
+  return TACHES_OK;
+}
+
+int taches_pool_detach(taches_pool* p, taches_stream* s) {
+  if (!p || !s) return fail(TACHES_EINVAL, "NULL argument");
+  if (s->pool != p) return fail(TACHES_EINVAL, "stream is not attached to this pool");
+  HIPCHK(hipStreamSynchronize(p->stream));
+  p->attached.erase(std::find(p->attached.begin(), p->attached.end(), s));
+  p->used -= s->device_bytes;
+  s->pool = nullptr;
+  s->stream = s->stream_before_pool;
+  return TACHES_OK;
+}
+
+int taches_pool_set_tile(taches_pool* p, int32_t r) {
+  if (!p) return fail(TACHES_EINVAL, "pool is NULL");
+  if (r != 0 && r != 4 && r != 8 && r != 12 && r != 16) return fail(TACHES_EINVAL, "r=%d not in {0,4,8,12,16}", r);
+  p->force_r = r;
+  return TACHES_OK;
+}
+
+int taches_pool_use_graph(taches_pool* p, int32_t on) {
+  if (!p) return fail(TACHES_EINVAL, "pool is NULL");
+  p->use_graph = on != 0;
+  return TACHES_OK;
+}
+
+int taches_pool_synchronize(taches_pool* p) {
+  if (!p) return fail(TACHES_EINVAL, "pool is NULL");
+  HIPCHK(hipStreamSynchronize(p->stream));
+  return TACHES_OK;
+}
+
+int taches_pool_get_info(const taches_pool* p, taches_pool_info* out) {
+  if (!p || !out) return fail(TACHES_EINVAL, "NULL argument");
+  std::memset(out, 0, sizeof *out);
+  out->attached = (int32_t)p->attached.size();
+  out->max_streams = p->max_streams;
+  out->budget_bytes = p->budget;
+  out->used_bytes = p->used;
+  out->last_items = p->last_items;
+  out->last_workgroups = p->last_wg;
+  out->last_r = p->last_r;
+  out->graph_replays = p->replays;
+  out->last_plan_ms = p->last_plan_ms;
+  out->last_imbalance = p->last_imbalance;
+  return TACHES_OK;
+}
+
+int taches_pool_step(taches_pool* p, int32_t n, taches_stream* const* streams, const float* const* x_dev,
+                     float* const* y_dev, const int32_t* n_blocks) {
+  if (!p) return fail(TACHES_EINVAL, "pool is NULL");
+  if (n < 0 || (n > 0 && (!streams || !y_dev || !n_blocks))) return fail(TACHES_EINVAL, "bad step arguments");
+  if (n == 0) return TACHES_OK;
+  const auto t0 = std::chrono::steady_clock::now();
+  for (int i = 0; i < n; ++i) {
+    if (!streams[i] || streams[i]->pool != p) return fail(TACHES_EINVAL, "stream %d is not attached to this pool", i);
+    for (int j = 0; j < i; ++j)
+      if (streams[j] == streams[i]) return fail(TACHES_EINVAL, "stream listed twice in one step");
+  }
+  // plan every call (validation first: an error leaves every stream untouched)
+  std::vector<CallPlan> plans(n);
+  for (int i = 0; i < n; ++i) {
+    int rc = plan_call(streams[i], x_dev ? x_dev[i] : nullptr, y_dev[i], n_blocks[i], nullptr, &plans[i]);
+    if (rc != TACHES_OK) return rc;
+  }
+  // split-precision streams run their own MFMA kernel on the pool's stream
+  std::vector<int> gather_ids;
+  std::vector<const GatherCall*> gcalls;
+  for (int i = 0; i < n; ++i) {
+    if (streams[i]->cfg.precision == TACHES_PREC_SPLIT_BF16) {
+      int rc = launch_call(streams[i], plans[i]);
+      if (rc != TACHES_OK) return rc;
+    } else {
+      gather_ids.push_back(i);
+      gcalls.push_back(&plans[i].g);
+    }
+  }
+  if (!gather_ids.empty()) {
+    const int r = pool_pick_r(p, gcalls);
+    const int64_t T = 64 * r;
+    // work items: (call, channel, tile) with their FMA count
+    struct Item {
+      WorkItem w;
+      int64_t work;
+    };
+    std::vector<Item> items;
+    const int ng = (int)gather_ids.size();
+    for (int k = 0; k < ng; ++k) {
+      const GatherCall& g = plans[gather_ids[k]].g;
+      const int64_t nt = (g.n_out + T - 1) / T;
+      for (int c = 0; c < g.channels; ++c)
+        for (int64_t t = 0; t < nt; ++t) {
+          const int64_t n0 = t * T;
+          int64_t work = 4 * T;  // tail read/write
+          if (g.x) {
+            const int64_t lo = std::max<int64_t>(0, n0 - (g.Lmax_call - 1));
+            const int64_t hi = std::min<int64_t>(g.S, n0 + T);
+            work += std::max<int64_t>(hi - lo, 0) * T;
+          }
+          items.push_back({WorkItem{k, c, (int32_t)t, 0}, work});
+        }
+    }
+    // persistent workgroups (one wave each): as many as stay resident, but
+    // no more than leave each at least the largest item's work
+    const int per_cu = taches::gather_batched_waves_per_cu(r);
+    int64_t total_work = 0, max_work = 1;
+    for (const Item& it : items) {
+      total_work += it.work;
+      max_work = std::max(max_work, it.work);
+    }
+    const int64_t by_work = std::max<int64_t>(1, total_work / max_work);
+    const int nwg = (int)std::max<int64_t>(std::min<int64_t>(256, (int64_t)items.size()),
+                                           std::min<int64_t>(256LL * per_cu, by_work));
+    // largest item first onto the least-loaded workgroup
+    std::sort(items.begin(), items.end(), [](const Item& a, const Item& b) { return a.work > b.work; });
+    std::vector<std::pair<int64_t, int>> heap;
+    heap.reserve(nwg);
+    for (int b = 0; b < nwg; ++b) heap.push_back({0, b});
+    std::vector<int> owner(items.size());
+    std::vector<int> count(nwg, 0);
+    auto cmp = [](const std::pair<int64_t, int>& a, const std::pair<int64_t, int>& b) { return a.first > b.first; };
+    for (size_t i = 0; i < items.size(); ++i) {
+      std::pop_heap(heap.begin(), heap.end(), cmp);
+      heap.back().first += items[i].work;
+      owner[i] = heap.back().second;
+      count[owner[i]] += 1;
+      std::push_heap(heap.begin(), heap.end(), cmp);
+    }
+    int64_t mx = 0, sum = 0;
+    for (auto& h : heap) {
+      mx = std::max(mx, h.first);
+      sum += h.first;
+    }
+    p->last_imbalance = sum > 0 ? (double)mx * nwg / (double)sum : 1.0;
+    // pack the table: header, calls, fp64 flags, wg_begin, items grouped by workgroup
+    const size_t off_calls = align256(sizeof(taches::BatchHeader));
+    const size_t off_fp64 = align256(off_calls + sizeof(GatherCall) * ng);
+    const size_t off_wgb = align256(off_fp64 + sizeof(int32_t) * ng);
+    const size_t off_items = align256(off_wgb + sizeof(int32_t) * (nwg + 1));
+    const size_t bytes = align256(off_items + sizeof(WorkItem) * items.size());
+    int rc = pool_reserve(p, bytes);
+    if (rc != TACHES_OK) return rc;
+    if (p->tab_pending) {
+      HIPCHK(hipEventSynchronize(p->tab_free));
+      p->tab_pending = false;
+    }
+    taches::BatchHeader* hd = (taches::BatchHeader*)p->tab_pin;
+    hd->off_calls = (int32_t)off_calls;
+    hd->off_fp64 = (int32_t)off_fp64;
+    hd->off_wgb = (int32_t)off_wgb;
+    hd->off_items = (int32_t)off_items;
+    GatherCall* calls = (GatherCall*)(p->tab_pin + off_calls);
+    int32_t* fp64 = (int32_t*)(p->tab_pin + off_fp64);
+    int32_t* wgb = (int32_t*)(p->tab_pin + off_wgb);
+    WorkItem* wit = (WorkItem*)(p->tab_pin + off_items);
+    for (int k = 0; k < ng; ++k) {
+      calls[k] = plans[gather_ids[k]].g;
+      calls[k].tile_order = 2;
+      fp64[k] = streams[gather_ids[k]]->tail_fp64 ? 1 : 0;
+    }
+    wgb[0] = 0;
+    for (int b = 0; b < nwg; ++b) wgb[b + 1] = wgb[b] + count[b];
+    std::vector<int32_t> fill(wgb, wgb + nwg);
+    for (size_t i = 0; i < items.size(); ++i) wit[fill[owner[i]]++] = items[i].w;
+    const auto t1 = std::chrono::steady_clock::now();
+    p->last_plan_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    bool launched = false;
+    if (p->use_graph) {
+      // capture [table copy -> batched kernel] once per (tile, workgroups,
+      // table capacity); later steps only resize the copy and replay
+      if (!p->exec || p->graph_r != r || p->graph_nwg != nwg || p->graph_cap != p->tab_cap) {
+        pool_drop_graph(p);
+        HIPCHK(hipStreamBeginCapture(p->capture, hipStreamCaptureModeThreadLocal));
+        hipError_t e1 = hipMemcpyAsync(p->tab_dev, p->tab_pin, p->tab_cap, hipMemcpyHostToDevice, p->capture);
+        hipError_t e2 = taches::launch_gather_batched(p->tab_dev, nwg, r, p->capture);
+        hipError_t e3 = hipStreamEndCapture(p->capture, &p->graph);
+        if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess)
+          return fail(TACHES_EDEVICE, "graph capture failed: %s", hipGetErrorString(e1 != hipSuccess ? e1 : e2 != hipSuccess ? e2 : e3));
+        HIPCHK(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
+        size_t nn = 0;
+        HIPCHK(hipGraphGetNodes(p->graph, nullptr, &nn));
+        std::vector<hipGraphNode_t> nodes(nn);
+        HIPCHK(hipGraphGetNodes(p->graph, nodes.data(), &nn));
+        for (auto nd : nodes) {
+          hipGraphNodeType ty;
+          HIPCHK(hipGraphNodeGetType(nd, &ty));
+          if (ty == hipGraphNodeTypeMemcpy) p->copy_node = nd;
+        }
+        p->graph_r = r;
+        p->graph_nwg = nwg;
+        p->graph_cap = p->tab_cap;
+      }
+      if (p->copy_node &&
+          hipGraphExecMemcpyNodeSetParams1D(p->exec, p->copy_node, p->tab_dev, p->tab_pin, bytes, hipMemcpyHostToDevice) ==
+              hipSuccess) {
+        HIPCHK(hipGraphLaunch(p->exec, p->stream));
+        p->replays += 1;
+        launched = true;
+      }
+    }
+    if (!launched) {
+      HIPCHK(hipMemcpyAsync(p->tab_dev, p->tab_pin, bytes, hipMemcpyHostToDevice, p->stream));
+      hipError_t e = taches::launch_gather_batched(p->tab_dev, nwg, r, p->stream);
+      if (e != hipSuccess) return fail(TACHES_EDEVICE, "batched launch: %s", hipGetErrorString(e));
+    }
+    HIPCHK(hipEventRecord(p->tab_free, p->stream));
+    p->tab_pending = true;
+    p->last_items = (int)items.size();
+    p->last_wg = nwg;
+    p->last_r = r;
+    for (int k = 0; k < ng; ++k) {
+      streams[gather_ids[k]]->last_r = r;
+      streams[gather_ids[k]]->last_w = 1;
+    }
+  }
+  for (int i = 0; i < n; ++i) commit_call(streams[i], plans[i]);
   return TACHES_OK;
 }
 

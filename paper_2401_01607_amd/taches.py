@@ -48,6 +48,14 @@ class taches_info(ctypes.Structure):
                 ("device_bytes", ctypes.c_int64), ("tile_r", ctypes.c_int32), ("tile_w", ctypes.c_int32)]
 
 
+class taches_pool_info(ctypes.Structure):
+    _fields_ = [("attached", ctypes.c_int32), ("max_streams", ctypes.c_int32),
+                ("budget_bytes", ctypes.c_int64), ("used_bytes", ctypes.c_int64),
+                ("last_items", ctypes.c_int32), ("last_workgroups", ctypes.c_int32),
+                ("last_r", ctypes.c_int32), ("pad_", ctypes.c_int32), ("graph_replays", ctypes.c_int64),
+                ("last_plan_ms", ctypes.c_double), ("last_imbalance", ctypes.c_double)]
+
+
 _vp, _i32, _i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
 _P = ctypes.POINTER
 _SIGS = {
@@ -68,6 +76,16 @@ _SIGS = {
     "taches_bytes_for": (_i64, [_P(taches_config)]),
     "taches_read_tail": (ctypes.c_int, [_vp, _i32, _vp, _i32]),
     "taches_set_tile": (ctypes.c_int, [_vp, _i32, _i32]),
+    "taches_pool_create": (_vp, [_i32, _i64, _i32]),
+    "taches_pool_destroy": (ctypes.c_int, [_vp]),
+    "taches_pool_attach": (ctypes.c_int, [_vp, _vp]),
+    "taches_pool_detach": (ctypes.c_int, [_vp, _vp]),
+    "taches_pool_step": (ctypes.c_int, [_vp, _i32, _vp, _vp, _vp, _vp]),
+    "taches_pool_set_hip_stream": (ctypes.c_int, [_vp, _vp]),
+    "taches_pool_set_tile": (ctypes.c_int, [_vp, _i32]),
+    "taches_pool_use_graph": (ctypes.c_int, [_vp, _i32]),
+    "taches_pool_synchronize": (ctypes.c_int, [_vp]),
+    "taches_pool_get_info": (ctypes.c_int, [_vp, _P(taches_pool_info)]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(lib, _name)
@@ -193,7 +211,60 @@ def taches_last_error() -> str:
     return lib.taches_last_error().decode(errors="replace")
 
 
-# ---- convenience wrapper ------------------------------------------------------
+def taches_pool_create(max_streams: int, hbm_budget_bytes: int, device: int = 0):
+    h = lib.taches_pool_create(max_streams, hbm_budget_bytes, device)
+    if not h:
+        raise TachesError(TACHES_EINVAL, "taches_pool_create")
+    return h
+
+
+def taches_pool_destroy(p) -> int:
+    return lib.taches_pool_destroy(p)
+
+
+def taches_pool_attach(p, s) -> int:
+    return lib.taches_pool_attach(p, s)
+
+
+def taches_pool_detach(p, s) -> int:
+    return lib.taches_pool_detach(p, s)
+
+
+def taches_pool_step(p, streams, xs, ys, n_blocks) -> int:
+    """streams: handles; xs: CUDA tensors or None (zero input); ys: CUDA tensors."""
+    n = len(streams)
+    sarr = (ctypes.c_void_p * n)(*streams)
+    xarr = None
+    if xs is not None:
+        xarr = (ctypes.c_void_p * n)(*[None if x is None else _dev_ptr(x).value for x in xs])
+    yarr = (ctypes.c_void_p * n)(*[_dev_ptr(y).value for y in ys])
+    nb = (ctypes.c_int32 * n)(*n_blocks)
+    return lib.taches_pool_step(p, n, sarr, xarr, yarr, nb)
+
+
+def taches_pool_set_hip_stream(p, stream: int) -> int:
+    return lib.taches_pool_set_hip_stream(p, ctypes.c_void_p(stream) if stream else None)
+
+
+def taches_pool_set_tile(p, r: int) -> int:
+    return lib.taches_pool_set_tile(p, r)
+
+
+def taches_pool_use_graph(p, on: bool) -> int:
+    return lib.taches_pool_use_graph(p, 1 if on else 0)
+
+
+def taches_pool_synchronize(p) -> int:
+    return lib.taches_pool_synchronize(p)
+
+
+def taches_pool_get_info(p) -> taches_pool_info:
+    info = taches_pool_info()
+    _check(lib.taches_pool_get_info(p, ctypes.byref(info)), "taches_pool_get_info")
+    return info
+
+
+# ---- convenience wrappers -----------------------------------------------------
 
 class Stream:
     """One taches stream (a handle).  Raises TachesError on any failure."""
@@ -273,5 +344,57 @@ class Stream:
             if self.h:
                 lib.taches_close(self.h)
                 self.h = None
+        except Exception:
+            pass
+
+
+class Pool:
+    """A pool of attached streams advanced by one batched launch per step."""
+
+    def __init__(self, max_streams: int, hbm_budget_bytes: int, device: int = 0, torch_stream: bool = True,
+                 use_graph: bool = False, tile_r: int = 0):
+        self.h = taches_pool_create(max_streams, hbm_budget_bytes, device)
+        if torch_stream:
+            _check(taches_pool_set_hip_stream(self.h, torch.cuda.current_stream(device).cuda_stream),
+                   "taches_pool_set_hip_stream")
+        _check(taches_pool_use_graph(self.h, use_graph), "taches_pool_use_graph")
+        _check(taches_pool_set_tile(self.h, tile_r), "taches_pool_set_tile")
+        self.members = set()
+
+    def attach(self, stream: "Stream") -> int:
+        rc = taches_pool_attach(self.h, stream.h)
+        if rc == TACHES_OK:
+            self.members.add(stream)
+        return rc
+
+    def detach(self, stream: "Stream") -> None:
+        _check(taches_pool_detach(self.h, stream.h), "taches_pool_detach")
+        self.members.discard(stream)
+
+    def step(self, streams, xs, ys, n_blocks) -> None:
+        _check(taches_pool_step(self.h, [s.h for s in streams], xs, ys, n_blocks), "taches_pool_step")
+
+    def set_tile(self, r: int) -> None:
+        _check(taches_pool_set_tile(self.h, r), "taches_pool_set_tile")
+
+    def use_graph(self, on: bool) -> None:
+        _check(taches_pool_use_graph(self.h, on), "taches_pool_use_graph")
+
+    def synchronize(self) -> None:
+        _check(taches_pool_synchronize(self.h), "taches_pool_synchronize")
+
+    def info(self) -> taches_pool_info:
+        return taches_pool_get_info(self.h)
+
+    def close(self) -> None:
+        if self.h:
+            for s in list(self.members):
+                self.detach(s)
+            _check(taches_pool_destroy(self.h), "taches_pool_destroy")
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
         except Exception:
             pass

@@ -1,0 +1,223 @@
+"""Pools: many streams advanced by one batched launch (optionally a hipGraph
+replay).  Every stream's output must equal, bit for bit, the same stream
+processed alone; float results must match the FP64 oracle within
+1e-5 * RMS."""
+import numpy as np
+import pytest
+
+from paper_2401_01607_amd import workloads as W
+from tests.gpu_harness import binding, oracle_run, rel_err
+
+pytestmark = pytest.mark.gpu
+
+GB = 1 << 30
+
+
+def _streams(n, seed, n_samples, lmin=64, lmax=4096, blocks=(32, 64, 128, 256, 512)):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        L = int(W.log_uniform_int(rng, lmin, lmax))
+        B = int(rng.choice(np.array(blocks)))
+        x = W.signal_gauss(n_samples, seed * 1000 + i)
+        h = W.impulse_response(L, seed * 1000 + 500 + i)
+        out.append((x, h, B, L))
+    return out
+
+
+def _alone(x, h, B, L, nb):
+    import torch
+    T = binding()
+    s = T.Stream(B, L, max_blocks_per_call=nb)
+    s.set_ir(h)
+    xp = np.zeros(nb * B, np.float32)
+    xp[: min(x.size, nb * B)] = x[: nb * B]
+    xd = torch.from_numpy(xp).cuda()[None]
+    yd = torch.empty_like(xd)
+    s.process_blocks(xd, yd, nb)
+    s.synchronize()
+    y = yd.cpu().numpy()[0]
+    s.close()
+    return y
+
+
+def _pool_run(specs, steps, use_graph=False, tile=0, between=None):
+    """Run every stream through `steps` pool steps; specs: (x, h, B, L);
+    steps: list of per-step block counts (same for every stream)."""
+    import torch
+    T = binding()
+    total = sum(steps)
+    pool = T.Pool(len(specs), 64 * GB, use_graph=use_graph, tile_r=tile)
+    ss, xs = [], []
+    for x, h, B, L in specs:
+        s = T.Stream(B, L, max_blocks_per_call=max(steps))
+        s.set_ir(h)
+        assert pool.attach(s) == T.TACHES_OK
+        ss.append(s)
+        xp = np.zeros(total * B, np.float32)
+        xp[: min(x.size, total * B)] = x[: total * B]
+        xs.append(torch.from_numpy(xp).cuda())
+    ys = [torch.empty_like(x) for x in xs]
+    done = 0
+    for k, nbk in enumerate(steps):
+        xin = [x[done * s.B:(done + nbk) * s.B][None] for x, s in zip(xs, ss)]
+        yout = [torch.empty((1, nbk * s.B), device="cuda") for s in ss]
+        pool.step(ss, xin, yout, [nbk] * len(ss))
+        for y, yo, s in zip(ys, yout, ss):
+            y[done * s.B:(done + nbk) * s.B] = yo[0]
+        done += nbk
+        if between is not None:
+            between(k)
+    pool.synchronize()
+    info = pool.info()
+    res = [y.cpu().numpy() for y in ys]
+    pool.close()
+    for s in ss:
+        s.close()
+    return res, info
+
+
+def test_batched_equals_alone_bitwise_and_oracle():
+    specs = _streams(24, 7, 6000)
+    nb_of = [-(-(6000 + L - 1) // B) for _, _, B, L in specs]
+    nb = max(nb_of)
+    # one step covering the whole input of every stream (blocks beyond a
+    # stream's input are zero input)
+    ys, info = _pool_run(specs, [nb])
+    assert info.last_items > 0 and info.last_workgroups > 0
+    for (x, h, B, L), y in zip(specs, ys):
+        alone = _alone(x, h, B, L, nb)
+        assert np.array_equal(y, alone)
+        ref = oracle_run(x, [h], [(0, 0)], B, L, nb)[0]
+        assert rel_err(y, ref) <= 1e-5
+
+
+@pytest.mark.parametrize("tile", [4, 8, 12, 16])
+def test_every_pool_tile_gives_the_same_bits(tile):
+    specs = _streams(10, 11, 3000, lmax=2000)
+    base, _ = _pool_run(specs, [4, 7, 5], tile=16)
+    ys, info = _pool_run(specs, [4, 7, 5], tile=tile)
+    assert info.last_r == tile
+    for a, b in zip(base, ys):
+        assert np.array_equal(a, b)
+
+
+def test_graph_replays_equal_eager_steps():
+    """Many small steps (one block per stream per step) replayed from a
+    captured graph, with eager torch work and synchronisations between
+    replays; every step's outputs must equal the eager pool's."""
+    import torch
+    specs = _streams(16, 13, 2048, lmax=1500, blocks=(32, 64))
+    steps = [1] * 24
+    scratch = torch.zeros(1 << 20, device="cuda")
+
+    def eager_work(k):
+        scratch.add_(1.0)
+        if k % 5 == 0:
+            torch.cuda.synchronize()
+
+    eager, _ = _pool_run(specs, steps)
+    graphed, info = _pool_run(specs, steps, use_graph=True, between=eager_work)
+    assert info.graph_replays >= len(steps) - 1
+    for a, b in zip(eager, graphed):
+        assert np.array_equal(a, b)
+    assert float(scratch[0]) == len(steps)
+
+
+def test_admission_budget_and_slots():
+    T = binding()
+    s1, s2, s3 = T.Stream(64, 4096), T.Stream(64, 4096), T.Stream(64, 4096)
+    b = s1.info().device_bytes
+    pool = T.Pool(2, 2 * b + b // 2)
+    assert pool.attach(s1) == T.TACHES_OK
+    assert pool.attach(s1) == T.TACHES_EBUSY          # already attached
+    assert pool.attach(s2) == T.TACHES_OK
+    assert pool.attach(s3) == T.TACHES_EBUSY          # no free slot
+    pool.detach(s2)
+    big = T.Stream(64, 1 << 16)
+    assert pool.attach(big) == T.TACHES_ENOMEM        # over the byte budget
+    assert pool.info().used_bytes == b
+    # an attached stream can only advance through the pool
+    import torch
+    x = torch.zeros((1, 64), device="cuda")
+    with pytest.raises(T.TachesError) as e:
+        s1.process_async(x, torch.empty_like(x))
+    assert e.value.status == T.TACHES_EBUSY
+    assert T.taches_close(s1.h) == T.TACHES_EBUSY
+    assert T.taches_pool_destroy(pool.h) == T.TACHES_EBUSY
+    pool.close()
+    for s in (s1, s2, s3, big):
+        s.close()
+
+
+def test_ir_swap_between_steps_on_attached_stream():
+    import torch
+    T = binding()
+    B, L = 64, 700
+    x = W.signal_int(40 * B, 3, 30)
+    ha, hb = W.signal_int(L, 4, 30), W.signal_int(L, 5, 30)
+    s = T.Stream(B, L, max_blocks_per_call=10)
+    s.set_ir(ha)
+    pool = T.Pool(4, 8 * GB)
+    pool.attach(s)
+    outs = []
+    for k in range(4):
+        if k == 2:
+            s.set_ir(hb)   # takes effect at the next step (block 20)
+        xd = torch.from_numpy(x[k * 10 * B:(k + 1) * 10 * B]).cuda()[None]
+        yd = torch.empty_like(xd)
+        pool.step([s], [xd], [yd], [10])
+        outs.append(yd)
+    pool.synchronize()
+    y = torch.cat(outs, 1).cpu().numpy()[0]
+    ref = oracle_run(x, [ha, hb], [(0, 0), (20, 1)], B, L, 40)[0]
+    assert np.array_equal(y, ref)
+    pool.close()
+    s.close()
+
+
+def test_mixed_split_and_fp32_streams_in_one_step():
+    import torch
+    T = binding()
+    B, L, n = 128, 1500, 4000
+    nb = -(-(n + L - 1) // B)
+    xs = np.stack([W.signal_gauss(n, 60 + c) for c in range(3)])
+    h = W.impulse_response(L, 61)
+    sf = T.Stream(B, L, max_blocks_per_call=nb)
+    sp = T.Stream(B, L, channels=3, max_blocks_per_call=nb, precision=T.TACHES_PREC_SPLIT_BF16)
+    sf.set_ir(h)
+    sp.set_ir(h)
+    pool = T.Pool(4, 8 * GB)
+    pool.attach(sf)
+    pool.attach(sp)
+    xpad = np.zeros((3, nb * B), np.float32)
+    xpad[:, :n] = xs
+    xf = torch.from_numpy(xpad[:1].copy()).cuda()
+    xsplit = torch.from_numpy(xpad).cuda()
+    yf, ysp = torch.empty_like(xf), torch.empty_like(xsplit)
+    pool.step([sf, sp], [xf, xsplit], [yf, ysp], [nb, nb])
+    pool.synchronize()
+    ref = oracle_run(xs, [h], [(0, 0)], B, L, nb)
+    assert rel_err(yf.cpu().numpy()[0], ref[0]) <= 1e-5
+    err = np.abs(ysp.cpu().numpy().astype(np.float64) - ref)
+    assert err.max() <= 1e-4 * np.sqrt(np.mean(ref**2))
+    pool.close()
+    sf.close()
+    sp.close()
+
+
+def test_config4_reduced_parity():
+    """Batched-workload shape (log-uniform L, B in {32..512}) on 48 streams
+    of 12 000 samples with L up to 16 384, one launch, vs the oracle."""
+    rng = np.random.default_rng(401)
+    specs = []
+    for i in range(48):
+        L = int(W.log_uniform_int(rng, 256, 16384))
+        B = int(rng.choice(np.array(W.BLOCK_CHOICES)))
+        specs.append((W.signal_gauss(12_000, 410_000 + i), W.impulse_response(L, 420_000 + i), B, L))
+    nb = max(-(-12_000 // B) for _, _, B, _ in specs)
+    ys, info = _pool_run(specs, [nb])
+    assert info.last_imbalance < 1.5
+    for (x, h, B, L), y in list(zip(specs, ys))[::6]:
+        ref = oracle_run(x, [h], [(0, 0)], B, L, nb)[0]
+        assert rel_err(y, ref) <= 1e-5
