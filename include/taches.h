@@ -172,6 +172,11 @@ int64_t taches_bytes_for(const taches_config* cfg);
  * tail holds for output head+k: the residue of Section 4.2 in output order. */
 int taches_read_tail(taches_stream* s, int32_t channel, double* out, int32_t n);
 
+/* Return the stream to its state right after open (empty tail, no IR)
+ * without freeing memory: a stream-ordered clear of the tail.  For reusing
+ * a stream for a new input. */
+int taches_reset(taches_stream* s);
+
 /* Force the gather tile shape (R outputs per lane in {4, 8, 12, 16}, W waves
  * per output tile in {1, 2, 4}); 0, 0 = automatic choice per call. */
 int taches_set_tile(taches_stream* s, int32_t r, int32_t w);

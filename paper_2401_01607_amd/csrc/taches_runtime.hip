@@ -174,17 +174,13 @@ int stream_init(taches_stream* s) {
       if ((rc = dev_alloc(s, &sl.hi, (size_t)c.max_ir_len * 2))) return rc;
       if ((rc = dev_alloc(s, &sl.lo, (size_t)c.max_ir_len * 2))) return rc;
     }
-    if ((rc = host_alloc(&sl.staging, (size_t)c.max_ir_len * 4))) return rc;
     HIPCHK(hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming));
   }
   const size_t blk = (size_t)c.channels * c.block_size * 4;
   if ((rc = dev_alloc(s, &s->x_dev, blk))) return rc;
   if ((rc = dev_alloc(s, &s->y_dev, blk))) return rc;
-  if ((rc = host_alloc(&s->x_pin, blk))) return rc;
-  if ((rc = host_alloc(&s->y_pin, blk))) return rc;
   const size_t tab = (size_t)c.max_blocks_per_call * sizeof(BlockIR);
   if ((rc = dev_alloc(s, &s->irtab_dev, tab))) return rc;
-  if ((rc = host_alloc(&s->irtab_pin, tab))) return rc;
   HIPCHK(hipEventCreateWithFlags(&s->irtab_ev, hipEventDisableTiming));
   if (is_split(c)) {
     if ((rc = dev_alloc(s, &s->xs_hi, (size_t)xs_bytes(c)))) return rc;
@@ -199,6 +195,10 @@ int load_slot(taches_stream* s, int slot, const float* h, int L, bool on_device)
   if (on_device) {
     HIPCHK(hipMemcpyAsync(sl.h, h, (size_t)L * 4, hipMemcpyDeviceToDevice, s->stream));
   } else {
+    if (!sl.staging) {  // pinned staging is allocated on first use
+      int rc = host_alloc(&sl.staging, (size_t)s->cfg.max_ir_len * 4);
+      if (rc != TACHES_OK) return rc;
+    }
     if (sl.ev_pending) {
       HIPCHK(hipEventSynchronize(sl.ev));
       sl.ev_pending = false;
@@ -376,6 +376,10 @@ int plan_call(taches_stream* s, const float* x_dev, float* y_dev, int n_blocks, 
     g.irs = nullptr;
     g.ir0 = ir_of(first_slot);
   } else {
+    if (!s->irtab_pin) {
+      int rc = host_alloc(&s->irtab_pin, (size_t)c.max_blocks_per_call * sizeof(BlockIR));
+      if (rc != TACHES_OK) return rc;
+    }
     if (s->irtab_pending) {
       HIPCHK(hipEventSynchronize(s->irtab_ev));
       s->irtab_pending = false;
@@ -552,6 +556,11 @@ int taches_process(taches_stream* s, const float* x, float* y) {
   if (!s) return fail(TACHES_EINVAL, "stream is NULL");
   if (!x || !y) return fail(TACHES_EINVAL, "x or y is NULL");
   const size_t n = (size_t)s->cfg.channels * s->cfg.block_size;
+  if (!s->x_pin) {
+    int rc = host_alloc(&s->x_pin, n * 4);
+    if (rc == TACHES_OK) rc = host_alloc(&s->y_pin, n * 4);
+    if (rc != TACHES_OK) return rc;
+  }
   std::memcpy(s->x_pin, x, n * 4);
   HIPCHK(hipMemcpyAsync(s->x_dev, s->x_pin, n * 4, hipMemcpyHostToDevice, s->stream));
   int rc = process_common(s, s->x_dev, s->y_dev, 1, nullptr);
@@ -645,6 +654,17 @@ int taches_read_tail(taches_stream* s, int32_t channel, double* out, int32_t n) 
       out[k] = v;
     }
   }
+  return TACHES_OK;
+}
+
+int taches_reset(taches_stream* s) {
+  if (!s) return fail(TACHES_EINVAL, "stream is NULL");
+  const size_t esz = s->tail_fp64 ? 8 : 4;
+  HIPCHK(hipMemsetAsync(s->ring, 0, (size_t)s->cpad * s->Rcap * esz, s->stream));
+  for (auto& sl : s->slots) sl.L = 0;
+  s->active = s->pending = -1;
+  s->head = s->live = 0;
+  s->blocks_done = 0;
   return TACHES_OK;
 }
 

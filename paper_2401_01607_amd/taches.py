@@ -76,6 +76,7 @@ _SIGS = {
     "taches_bytes_for": (_i64, [_P(taches_config)]),
     "taches_read_tail": (ctypes.c_int, [_vp, _i32, _vp, _i32]),
     "taches_set_tile": (ctypes.c_int, [_vp, _i32, _i32]),
+    "taches_reset": (ctypes.c_int, [_vp]),
     "taches_pool_create": (_vp, [_i32, _i64, _i32]),
     "taches_pool_destroy": (ctypes.c_int, [_vp]),
     "taches_pool_attach": (ctypes.c_int, [_vp, _vp]),
@@ -196,6 +197,10 @@ def taches_read_tail(s, channel: int, n: int) -> np.ndarray:
 
 def taches_set_tile(s, r: int, w: int) -> int:
     return lib.taches_set_tile(s, r, w)
+
+
+def taches_reset(s) -> int:
+    return lib.taches_reset(s)
 
 
 def taches_set_hip_stream(s, stream: int) -> int:
@@ -327,6 +332,9 @@ class Stream:
 
     def synchronize(self) -> None:
         _check(taches_synchronize(self.h), "taches_synchronize")
+
+    def reset(self) -> None:
+        _check(taches_reset(self.h), "taches_reset")
 
     def close(self) -> None:
         if self.h:

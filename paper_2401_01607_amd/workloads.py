@@ -226,7 +226,7 @@ def config5_requests(horizon_s: float, rate_hz: float = 200.0, seed: int = 501,
         L = int(log_uniform_int(rng, lrange[0], lrange[1]))
         swaps = []
         ts = 0.0
-        while True:
+        while swap_rate_hz > 0:
             ts += float(rng.exponential(1.0 / swap_rate_hz))
             if ts >= d:
                 break

@@ -1,0 +1,139 @@
+"""Serving policy on the CPU: the scheduler driven on a simulated clock by a
+stub executor that runs each stream through the oracle."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2401_01607_amd import workloads as W
+from paper_2401_01607_amd.serving import AdmissionRefused, Scheduler
+
+
+class OracleExecutor:
+    """Slots and a byte budget like the pool; outputs from the FP64 oracle."""
+
+    def __init__(self, max_streams, budget):
+        self.max_streams, self.budget = max_streams, budget
+        self.live, self.used, self.out, self.steps = {}, 0, {}, []
+        self.active_counts = []
+
+    @staticmethod
+    def bytes_for(req):
+        return req.channels * (req.ir_len + req.block) * 4 + 2 * req.ir_len * 4
+
+    @staticmethod
+    def ir(req, v):
+        return W.impulse_response(req.ir_len, req.seed * 1000 + 7 + v)
+
+    @staticmethod
+    def signal(req):
+        n_in = max(1, math.ceil(req.n_samples() / req.block))
+        x = np.zeros((req.channels, n_in * req.block), np.float32)
+        rng = np.random.default_rng(req.seed)
+        x[:, :req.n_samples()] = rng.standard_normal((req.channels, req.n_samples())).astype(np.float32)
+        return x
+
+    def admit(self, req):
+        b = self.bytes_for(req)
+        if len(self.live) >= self.max_streams or self.used + b > self.budget:
+            raise AdmissionRefused("full")
+        s = O.OracleStream(req.block, req.ir_len, req.channels)
+        s.set_ir(self.ir(req, 0))
+        self.live[req.rid] = (s, self.signal(req), [])
+        self.used += b
+        return req.rid
+
+    def set_ir(self, h, req, v):
+        self.live[h][0].set_ir(self.ir(req, v))
+
+    def step(self, batch):
+        self.steps.append(len(batch))
+        self.active_counts.append(len(self.live))
+        for h, req, k0, n in batch:
+            s, x, ys = self.live[h]
+            for k in range(k0, k0 + n):
+                xb = x[:, k * req.block:(k + 1) * req.block]
+                if xb.shape[1] < req.block:
+                    xb = np.zeros((req.channels, req.block), np.float32)
+                ys.append(s.process(xb)[1])
+
+    def retire(self, h, req):
+        s, x, ys = self.live.pop(h)
+        self.out[h] = (x, np.concatenate(ys, axis=1))
+        self.used -= self.bytes_for(req)
+
+
+def _reqs(n, rate, dur=(0.02, 0.08), L=(32, 600), seed=5, swap_rate=30.0):
+    return W.config5_requests(horizon_s=n / rate, rate_hz=rate, seed=seed, dur=dur, lrange=L, swap_rate_hz=swap_rate)
+
+
+def test_every_request_completes_with_its_exact_output():
+    reqs = _reqs(30, 200.0)
+    ex = OracleExecutor(max_streams=8, budget=1 << 30)
+    sch = Scheduler(reqs, ex, step_cost_s=1e-4)
+    st = sch.run_simulated(10.0)
+    assert st["admitted"] == st["completed"] == len(reqs)
+    for r in reqs:
+        x, y = ex.out[r.rid]
+        a = sch.history[r.rid]
+        # swaps apply at the first block starting at or after their time
+        want = [math.ceil(t * W.FS / r.block - 1e-9) for t in r.swap_times_s]
+        want = [b for b in want if b < a.n_in]
+        assert a.swap_blocks == want
+        sched = [(0, 0)] + [(b, v + 1) for v, b in enumerate(a.swap_blocks)]
+        irs = [ex.ir(r, v) for v in range(len(a.swap_blocks) + 1)]
+        n_blocks = a.n_in + a.n_drain
+        for c in range(r.channels):
+            ref = O.run_channel(x[c], irs, sched, r.block, r.ir_len, n_blocks=n_blocks)
+            assert np.array_equal(y[c], ref)
+        # the drain covers the temporal overflow: nothing is left after it
+        assert n_blocks * r.block >= r.n_samples() + r.ir_len - 1
+
+
+def test_slot_limit_and_fifo_admission():
+    reqs = _reqs(40, 2000.0, dur=(0.05, 0.1))
+    ex = OracleExecutor(max_streams=3, budget=1 << 30)
+    sch = Scheduler(reqs, ex, step_cost_s=1e-4)
+    st = sch.run_simulated(10.0)
+    assert max(ex.active_counts) <= 3
+    assert st["completed"] == len(reqs)
+    assert st["queue_wait_s_p99"] > 0
+    order = sorted(sch.history.values(), key=lambda a: a.start_s)
+    assert [a.req.rid for a in order] == sorted(a.req.rid for a in order)  # FIFO
+
+
+def test_hbm_budget_limits_admission():
+    reqs = _reqs(20, 2000.0, L=(4000, 4000))
+    per = OracleExecutor.bytes_for(reqs[0])
+    ex = OracleExecutor(max_streams=100, budget=int(2.5 * per) + 10_000)
+    sch = Scheduler(reqs, ex, step_cost_s=1e-4)
+    sch.run_simulated(10.0)
+    assert max(ex.active_counts) <= 2
+    assert sch.stats.refused_attempts > 0
+    assert sch.stats.completed == len(reqs)
+
+
+def test_latency_is_step_completion_minus_block_arrival():
+    reqs = _reqs(5, 50.0)
+    ex = OracleExecutor(max_streams=10, budget=1 << 30)
+    sch = Scheduler(reqs, ex, step_cost_s=2e-3)
+    st = sch.run_simulated(10.0)
+    lat = np.array(sch.stats.latencies_s)
+    assert np.all(lat >= 2e-3 - 1e-12)
+    assert st["latency_ms_p50"] >= 2.0
+    assert st["blocks"] == sum(a.n_in + a.n_drain for a in sch.history.values())
+
+
+def test_continuous_batching_joins_streams_in_one_step():
+    """Blocks that arrive while a step runs, from streams admitted at
+    different times, join the next step."""
+    reqs = _reqs(12, 400.0, dur=(0.2, 0.3))
+    ex = OracleExecutor(max_streams=16, budget=1 << 30)
+    sch = Scheduler(reqs, ex, step_cost_s=2e-3)
+    sch.run_simulated(10.0)
+    assert max(ex.steps) >= 4
+    ex2 = OracleExecutor(max_streams=16, budget=1 << 30)
+    sch2 = Scheduler(reqs, ex2, step_cost_s=0.0, min_tick_s=5e-3)
+    sch2.run_simulated(10.0)
+    assert max(ex2.steps) >= 4 and len(ex2.steps) < len(ex.steps) * 3
