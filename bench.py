@@ -383,9 +383,30 @@ def extra_c4_batched_vs_plain():
     return res
 
 
+def extra_c5_serving(duration_s=30.0, warmup_s=10.0):
+    """Poisson arrivals (200 / s) of mono/stereo streams lasting 10-60 s, IRs
+    log-uniform in [512, 262144] taps, IR swaps at 0.5 / s, B in {32..512},
+    up to 4096 streams admitted by HBM budget, real-time paced at 48 kHz,
+    continuous batching through one pool (graph replays)."""
+    from paper_2401_01607_amd import workloads as W
+    from paper_2401_01607_amd.serving import GpuExecutor, Scheduler
+    reqs = W.config5_requests(horizon_s=duration_s)
+    ex = GpuExecutor(max_streams=4096, hbm_budget_bytes=64 << 30, use_graph=True)
+    sch = Scheduler(reqs, ex, warmup_s=warmup_s)
+    st = sch.run_realtime(duration_s)
+    info = ex.pool.info()
+    ex.close()
+    st.update({"workload": "Poisson 200 streams/s, 10-60 s, mono/stereo, L log-U[512, 262144], swaps 0.5/s, "
+                           "B from {32..512}, <= 4096 streams, 64 GiB budget, FP32, real-time 48 kHz",
+               "run_s": duration_s, "warmup_s": warmup_s, "last_step_items": info.last_items,
+               "last_plan_ms": round(info.last_plan_ms, 2), "graph_replays": int(info.graph_replays)})
+    return st
+
+
 def extras(args):
     out = {}
-    sections = {"c1": extra_c1_latency, "c3": extra_c3_split_vs_fp32, "c4": extra_c4_batched_vs_plain}
+    sections = {"c1": extra_c1_latency, "c3": extra_c3_split_vs_fp32, "c4": extra_c4_batched_vs_plain,
+                "c5": extra_c5_serving}
     for name, fn in sections.items():
         if args.only and args.only != name:
             continue

@@ -23,7 +23,9 @@
 //    column group write contiguous memory.
 //  - LDS: the IR window a tile needs, reversed, in 8 copies shifted by one
 //    element each: the A fragment of a lane (8 taps, descending) is then
-//    one aligned 16-byte read from the copy that matches its alignment.
+//    one aligned 16-byte read from the copy that matches its alignment.  The
+//    window is loaded into registers one chunk ahead, stored once, and the
+//    shifted copies are built from it inside LDS.
 #include "taches_internal.h"
 
 namespace taches {
@@ -32,9 +34,16 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
+struct BFrag {
+  bf16x8 h0, l0, h1, l1;  // hi/lo B fragments of the two 32-channel tiles
+};
+
 constexpr int MT = 128;                    // output slots per workgroup (4 waves x 32)
 constexpr int KC = CHUNK_MAX;              // longest chunk (samples)
 constexpr int CP_LEN = MT + KC + 16;       // elements per shifted copy (>= MT + KC + 7)
+constexpr int REV_LEN = CP_LEN + 16;       // reversed window staged once per chunk
+constexpr int REV_PER_THREAD = (REV_LEN + 255) / 256;
+static_assert(CP_LEN % 8 == 0 && 2 * (CP_LEN / 8) <= 256, "copy-building needs one group per thread");
 
 // Round an FP32 value to the nearest BF16 (ties to even); returns the bits.
 __device__ __forceinline__ uint16_t bf16_rn(float v) {
@@ -99,10 +108,27 @@ __device__ __forceinline__ int xcd_remap(int id, int n) {
   return x * q + (x < rem ? x : rem) + k;
 }
 
+// A thread's share of one chunk's reversed IR window (hi and lo halves).
+struct RevPrefetch {
+  uint16_t hi[REV_PER_THREAD], lo[REV_PER_THREAD];
+};
+
+__device__ __forceinline__ void rev_load(const BlockIR& ir, int top, int tid, RevPrefetch& pf) {
+#pragma unroll
+  for (int j = 0; j < REV_PER_THREAD; ++j) {
+    const int hidx = top - (tid + 256 * j);
+    const bool ok = tid + 256 * j < REV_LEN && hidx >= 0 && hidx < ir.L;
+    pf.hi[j] = ok ? ir.h_hi[hidx] : (uint16_t)0;
+    pf.lo[j] = ok ? ir.h_lo[hidx] : (uint16_t)0;
+  }
+}
+
 template <typename TailT>
 __global__ __launch_bounds__(256) void k_toeplitz(GatherCall d, int n_tiles) {
   __shared__ __attribute__((aligned(16))) uint16_t cp_hi[8 * CP_LEN];
   __shared__ __attribute__((aligned(16))) uint16_t cp_lo[8 * CP_LEN];
+  __shared__ __attribute__((aligned(16))) uint16_t rev_hi[REV_LEN];
+  __shared__ __attribute__((aligned(16))) uint16_t rev_lo[REV_LEN];
   const int tid = threadIdx.x;
   const int l = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -131,6 +157,9 @@ __global__ __launch_bounds__(256) void k_toeplitz(GatherCall d, int n_tiles) {
       acc[nt][q] = v;
     }
 
+  RevPrefetch pf;
+  bool pf_valid = false;
+  int pf_ck = -1;
   if (d.x != nullptr) {
     const int lo = n0 - (d.Lmax_call - 1);
     const int b_first = lo <= 0 ? 0 : lo / d.B;
@@ -145,44 +174,99 @@ __global__ __launch_bounds__(256) void k_toeplitz(GatherCall d, int n_tiles) {
       if (len <= 0 || m_lo > n0 + MT - 1 || m_lo + len + ir.L - 2 < n0) continue;  // uniform
       const int chp = (len + 15) & ~15;
       __syncthreads();  // the previous chunk's reads of the copies are done
-      // stage: copy s, element v holds h[n0 - m_lo + MT - 1 - (v + s)]
-      const int top = n0 - m_lo + MT - 1;
-      for (int e = tid; e < 8 * CP_LEN; e += 256) {
-        const int s = e / CP_LEN;
-        const int v = e - s * CP_LEN;
-        const int hidx = top - v - s;
-        uint16_t vh = 0, vl = 0;
-        if (hidx >= 0 && hidx < ir.L) {
-          vh = ir.h_hi[hidx];
-          vl = ir.h_lo[hidx];
+      // 1) the reversed window rev[u] = h[n0 - m_lo + MT - 1 - u] (hi and lo),
+      //    loaded into registers one chunk earlier (or now, for the first)
+      if (!pf_valid || pf_ck != ck) rev_load(ir, n0 - m_lo + MT - 1, tid, pf);
+#pragma unroll
+      for (int j = 0; j < REV_PER_THREAD; ++j) {
+        const int u = tid + 256 * j;
+        if (u < REV_LEN) {
+          rev_hi[u] = pf.hi[j];
+          rev_lo[u] = pf.lo[j];
         }
-        cp_hi[e] = vh;
-        cp_lo[e] = vl;
       }
       __syncthreads();
+      // 2) eight copies shifted by s = 0..7: cp_s[v] = rev[v + s]; one thread
+      //    per 8-element group reads 16 elements and writes 8 aligned groups
+      if (tid < 2 * (CP_LEN / 8)) {
+        const bool lo_set = tid >= CP_LEN / 8;
+        const int v0 = 8 * (lo_set ? tid - CP_LEN / 8 : tid);
+        const uint16_t* src = lo_set ? rev_lo : rev_hi;
+        uint16_t* dst = lo_set ? cp_lo : cp_hi;
+        const uint4 a = *reinterpret_cast<const uint4*>(src + v0);
+        const uint4 b = *reinterpret_cast<const uint4*>(src + v0 + 8);
+        const uint32_t dw[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+        for (int sh = 0; sh < 8; ++sh) {
+          uint32_t o[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            if (sh % 2 == 0) {
+              o[k] = dw[sh / 2 + k];
+            } else {
+              const int m = (sh - 1) / 2 + k;
+              o[k] = (dw[m] >> 16) | (dw[m + 1] << 16);
+            }
+          }
+          *reinterpret_cast<uint4*>(dst + sh * CP_LEN + v0) = make_uint4(o[0], o[1], o[2], o[3]);
+        }
+      }
+      __syncthreads();
+      // 3) prefetch the next reaching chunk's window during this chunk's MFMAs
+      pf_valid = false;
+      for (int k2 = k + 1; k2 < nch; ++k2) {
+        int m2, len2, b2;
+        chunk_span(d, c_first + k2, m2, len2, b2);
+        const BlockIR ir2 = d.irs ? d.irs[b2] : d.ir0;
+        if (len2 <= 0 || m2 > n0 + MT - 1 || m2 + len2 + ir2.L - 2 < n0) continue;
+        rev_load(ir2, n0 - m2 + MT - 1, tid, pf);
+        pf_ck = c_first + k2;
+        pf_valid = true;
+        break;
+      }
       f32x16 p0 = {}, p1 = {};
       const uint16_t* xh = d.xs_hi + ((int64_t)ck * 32) * cpad * 8;
       const uint16_t* xl = d.xs_lo + ((int64_t)ck * 32) * cpad * 8;
       const int ksteps = chp >> 4;
-      for (int t = 0; t < ksteps; ++t) {
+      // B fragments (8 samples of channel 32*nt + i, k-group 2t + kg) are
+      // loaded two K-steps ahead into a ring of three register buffers
+      BFrag bf[3];
+      auto load_b = [&](int t, BFrag& f) {
+        const int64_t xo = ((int64_t)(2 * t + kg) * cpad + i) * 8;
+        f.h0 = *reinterpret_cast<const bf16x8*>(xh + xo);
+        f.l0 = *reinterpret_cast<const bf16x8*>(xl + xo);
+        if (cpad > 32) {
+          f.h1 = *reinterpret_cast<const bf16x8*>(xh + xo + 32 * 8);
+          f.l1 = *reinterpret_cast<const bf16x8*>(xl + xo + 32 * 8);
+        }
+      };
+      auto kstep = [&](int t, const BFrag& f) {
         // A fragment: taps for rows n0+32w+i and samples m_lo+16t+8kg+j
         const int a = MT - 1 - 32 * w - i + 16 * t + 8 * kg;
         const int aoff = (a & 7) * CP_LEN + (a & ~7);
         const bf16x8 ah = *reinterpret_cast<const bf16x8*>(cp_hi + aoff);
         const bf16x8 al = *reinterpret_cast<const bf16x8*>(cp_lo + aoff);
-        // B fragments: 8 samples of channel 32*nt + i, k-group 2t + kg
-        const int64_t xo = ((int64_t)(2 * t + kg) * cpad + i) * 8;
-        const bf16x8 bh0 = *reinterpret_cast<const bf16x8*>(xh + xo);
-        const bf16x8 bl0 = *reinterpret_cast<const bf16x8*>(xl + xo);
-        p0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh0, p0, 0, 0, 0);
-        p0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl0, p0, 0, 0, 0);
-        p0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh0, p0, 0, 0, 0);
+        p0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, f.h0, p0, 0, 0, 0);
+        p0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, f.l0, p0, 0, 0, 0);
+        p0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, f.h0, p0, 0, 0, 0);
         if (cpad > 32) {
-          const bf16x8 bh1 = *reinterpret_cast<const bf16x8*>(xh + xo + 32 * 8);
-          const bf16x8 bl1 = *reinterpret_cast<const bf16x8*>(xl + xo + 32 * 8);
-          p1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh1, p1, 0, 0, 0);
-          p1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl1, p1, 0, 0, 0);
-          p1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh1, p1, 0, 0, 0);
+          p1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, f.h1, p1, 0, 0, 0);
+          p1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, f.l1, p1, 0, 0, 0);
+          p1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, f.h1, p1, 0, 0, 0);
+        }
+      };
+      if (ksteps == KC / 16) {
+        load_b(0, bf[0]);
+        load_b(1, bf[1]);
+#pragma unroll
+        for (int t = 0; t < KC / 16; ++t) {
+          if (t + 2 < KC / 16) load_b(t + 2, bf[(t + 2) % 3]);
+          kstep(t, bf[t % 3]);
+        }
+      } else {
+        for (int t = 0; t < ksteps; ++t) {
+          load_b(t, bf[0]);
+          kstep(t, bf[0]);
         }
       }
 #pragma unroll
