@@ -214,6 +214,18 @@ int taches_pool_detach(taches_pool* p, taches_stream* s);
 int taches_pool_step(taches_pool* p, int32_t n, taches_stream* const* streams, const float* const* x_dev,
                      float* const* y_dev, const int32_t* n_blocks);
 
+/* taches_pool_step with explicit channel strides (in floats): channel c of
+ * stream i reads x_dev[i] + c * x_cstride[i] and writes y_dev[i] +
+ * c * y_cstride[i], n_blocks[i] * B samples each, so the buffers can be
+ * slices of larger planar arrays (e.g. blocks k..k+n-1 of a whole-signal
+ * buffer).  A NULL stride array, or a 0 entry, means packed channels
+ * (stride n_blocks[i] * B).  Multichannel strides shorter than
+ * n_blocks[i] * B are TACHES_EINVAL.  Same ownership and errors as
+ * taches_pool_step. */
+int taches_pool_step_strided(taches_pool* p, int32_t n, taches_stream* const* streams, const float* const* x_dev,
+                             const int64_t* x_cstride, float* const* y_dev, const int64_t* y_cstride,
+                             const int32_t* n_blocks);
+
 /* HIP stream for the pool and its attached streams (NULL = HIP's null
  * stream).  Work already enqueued is first waited for. */
 int taches_pool_set_hip_stream(taches_pool* p, void* hip_stream);

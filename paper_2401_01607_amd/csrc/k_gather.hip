@@ -115,16 +115,17 @@ __device__ __forceinline__ void fma_group(const float (&xv)[R], const float (&A)
 //   Output n0 + lane*R + r, sample s = g*R + t uses
 //   hs[lane*R + (G - 1 - g)*R + (r - t + R - 1)], G = len_pad / R, i.e. the
 //   window pair starting at padded row lane + G - 1 - g.
+//   Only groups [g0, g1) are summed (a run of several chunks staged together
+//   is computed one chunk at a time).
 template <int R>
-__device__ __forceinline__ void chunk_compute(int hs, int xs, int lane, int len_pad, float (&p)[R]) {
+__device__ __forceinline__ void chunk_compute(int hs, int xs, int lane, int G, int g0, int g1, float (&p)[R]) {
   constexpr int ROW = Geo<R>::ROW;
-  const int G = len_pad / R;   // wave-uniform
   const int wl = hs + lane * ROW;
   float X[R], Y[R], xv[R];
-  load_win<R>(wl + (G - 1) * ROW, X);
-  load_win<R>(wl + G * ROW, Y);
-  int g = 0;
-  for (; g + 2 <= G; g += 2) {
+  load_win<R>(wl + (G - 1 - g0) * ROW, X);
+  load_win<R>(wl + (G - g0) * ROW, Y);
+  int g = g0;
+  for (; g + 2 <= g1; g += 2) {
     load_x<R>(xs, g * R, xv);
     fma_group<R>(xv, X, Y, p);                                 // group g:   A = X, B = Y
     load_win<R>(wl + (G - 2 - g) * ROW, Y);
@@ -133,14 +134,17 @@ __device__ __forceinline__ void chunk_compute(int hs, int xs, int lane, int len_
     // window of group g+2 (a harmless in-bounds read when the loop ends)
     load_win<R>(hs + max(lane + G - 3 - g, 0) * ROW, X);
   }
-  if (g < G) {
+  if (g < g1) {
     load_x<R>(xs, g * R, xv);
     fma_group<R>(xv, X, Y, p);
   }
 }
 
+// Samples staged together in one wave's LDS region: chunk `ck` alone, or
+// (one-wave tiles) a run of `nsub` consecutive whole blocks of B samples.
 struct ChunkGeo {
   int m_lo, len, len_pad;
+  int ck, nsub;
   BlockIR ir;
   bool reaches;
 };
@@ -157,6 +161,45 @@ __device__ __forceinline__ ChunkGeo chunk_geo(const GatherCall& d, int ck, int n
   g.ir = d.irs ? d.irs[b] : d.ir0;
   // the chunk's taches cover outputs [m_lo, m_hi - 1 + L - 1]
   g.reaches = g.len > 0 && g.m_lo <= n0 + Geo<R>::T - 1 && m_hi + g.ir.L - 2 >= n0;
+  g.ck = ck;
+  g.nsub = 1;
+  return g;
+}
+
+// The staging unit that starts at chunk ck (one-wave tiles).  When whole
+// blocks are short (kmax = CHUNK_MAX / B > 1, one chunk per block, B a
+// multiple of R), up to kmax consecutive blocks that use the same IR are
+// staged as one unit: one IR window of T + kmax*B - 1 taps serves them all,
+// so short blocks no longer pay a full staging round each.  Their partial
+// sums are still formed and added to the tail one block at a time.
+template <int R>
+__device__ __forceinline__ ChunkGeo unit_geo(const GatherCall& d, int ck, int ck_end, int kmax, int n0) {
+  ChunkGeo g;
+  if (ck >= ck_end) {
+    g.m_lo = g.len = g.len_pad = 0;
+    g.ck = ck;
+    g.nsub = 0;
+    g.reaches = false;
+    return g;
+  }
+  if (kmax == 1) return chunk_geo<R>(d, ck, n0);
+  g.ir = d.irs ? d.irs[ck] : d.ir0;
+  int e = min(ck + kmax, ck_end);
+  if (d.irs) {
+    for (int b = ck + 1; b < e; ++b) {
+      const BlockIR o = d.irs[b];
+      if (o.h != g.ir.h || o.L != g.ir.L) {
+        e = b;
+        break;
+      }
+    }
+  }
+  g.ck = ck;
+  g.nsub = e - ck;
+  g.m_lo = ck * d.B;
+  g.len = g.nsub * d.B;
+  g.len_pad = g.len;
+  g.reaches = g.m_lo <= n0 + Geo<R>::T - 1 && g.m_lo + g.len + g.ir.L - 2 >= n0;
   return g;
 }
 
@@ -271,11 +314,45 @@ __device__ __forceinline__ void gather_tile(const GatherCall& d, int c, int tile
     const int b_last = min(d.n_blocks - 1, (n0 + T - 1) / d.B);
     const int c_first = b_first * d.cpb;
     const int nch = b_first <= b_last ? (b_last - b_first + 1) * d.cpb : 0;
-    // Wave w handles chunks w, w + W, w + 2W, ...: `gc` is staged in LDS,
-    // `gn` (the wave's next chunk) is in registers.  A wave's LDS region is
-    // private and LDS operations of one wave complete in program order, so
-    // storing `gn` after computing `gc` needs no barrier.
+    // `gc` is staged in LDS, `gn` (the wave's next unit) is in registers.
+    // A wave's LDS region is private and LDS operations of one wave complete
+    // in program order, so storing `gn` after computing `gc` needs no
+    // barrier.
     Prefetch<R> pf;
+    if constexpr (W == 1) {
+      const int kmax = (d.cpb == 1 && d.B % R == 0) ? max(1, CHUNK_MAX / d.B) : 1;
+      const int c_end = c_first + nch;
+      ChunkGeo gc = unit_geo<R>(d, c_first, c_end, kmax, n0);
+      if (gc.reaches) {
+        chunk_load<R>(gc, xc, n0, lane, pf);
+        chunk_store<R>(gc, lane, pf, hs, xs);
+      }
+      ChunkGeo gn = unit_geo<R>(d, gc.ck + gc.nsub, c_end, kmax, n0);
+      if (gn.reaches) chunk_load<R>(gn, xc, n0, lane, pf);
+      while (gc.nsub > 0) {
+        if (gc.reaches) {
+          const int G = gc.len_pad / R;
+          const int gs = G / gc.nsub;        // groups per block (all of G for a single chunk)
+          const int L = gc.ir.L;
+          for (int j = 0; j < gc.nsub; ++j) {
+            const int m0 = gc.m_lo + j * d.B;
+            if (gc.nsub > 1 && !(m0 <= n0 + T - 1 && m0 + d.B + L - 2 >= n0)) continue;
+            float p[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) p[r] = 0.f;
+            chunk_compute<R>(hs, xs, lane, G, j * gs, (j + 1) * gs, p);
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[r] += (TailT)p[r];
+          }
+        }
+        if (gn.reaches) chunk_store<R>(gn, lane, pf, hs, xs);
+        gc = gn;
+        gn = unit_geo<R>(d, gc.ck + gc.nsub, c_end, kmax, n0);
+        if (gn.reaches) chunk_load<R>(gn, xc, n0, lane, pf);
+      }
+    } else {
+    // Wave w handles chunks w, w + W, w + 2W, ... and the partial sums of
+    // each round are added in chunk order.
     ChunkGeo gc, gn;
     gc.reaches = gn.reaches = false;
     if (w < nch) gc = chunk_geo<R>(d, c_first + w, n0);
@@ -289,16 +366,13 @@ __device__ __forceinline__ void gather_tile(const GatherCall& d, int c, int tile
       float p[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) p[r] = 0.f;
-      if (gc.reaches) chunk_compute<R>(hs, xs, lane, gc.len_pad, p);
+      if (gc.reaches) chunk_compute<R>(hs, xs, lane, gc.len_pad / R, 0, gc.len_pad / R, p);
       if (gn.reaches) chunk_store<R>(gn, lane, pf, hs, xs);
       gc = gn;
       gn.reaches = false;
       if (base + 2 * W + w < nch) gn = chunk_geo<R>(d, c_first + base + 2 * W + w, n0);
       if (gn.reaches) chunk_load<R>(gn, xc, n0, lane, pf);
-      if constexpr (W == 1) {
-#pragma unroll
-        for (int r = 0; r < R; ++r) acc[r] += (TailT)p[r];
-      } else {
+      {
         const int mine = pbuf + (w * 64 + lane) * R;
 #pragma unroll
         for (int r = 0; r < R; r += 4) lds_write4(mine + r, vf4{p[r], p[r + 1], p[r + 2], p[r + 3]});
@@ -317,6 +391,7 @@ __device__ __forceinline__ void gather_tile(const GatherCall& d, int c, int tile
         }
         __syncthreads();
       }
+    }
     }
   }
 

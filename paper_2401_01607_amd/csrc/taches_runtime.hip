@@ -111,6 +111,7 @@ struct taches_stream {
   int cpad = 0;                                 // channels per tail slot (split path)
   int64_t plan_key[4] = {-1, -1, -1, -1};        // last planned call shape and its tile plan
   int plan_val[3] = {0, 0, 0};
+  uint64_t step_mark = 0;                         // pool step that last listed the stream
 };
 
 namespace {
@@ -306,11 +307,21 @@ struct CallPlan {
 
 // Validate a call and build its descriptor.  Uploads the per-block IR table
 // when the IR changes inside the call.  Nothing is launched.
-int plan_call(taches_stream* s, const float* x_dev, float* y_dev, int n_blocks, const int32_t* sched, CallPlan* out) {
+// Channel strides of 0 mean packed channels (stride n_blocks * B).
+int plan_call(taches_stream* s, const float* x_dev, int64_t x_cstride, float* y_dev, int64_t y_cstride, int n_blocks,
+              const int32_t* sched, CallPlan* out) {
   const taches_config& c = s->cfg;
   if (n_blocks < 1 || n_blocks > c.max_blocks_per_call)
     return fail(TACHES_EINVAL, "n_blocks %d outside [1, %d]", n_blocks, c.max_blocks_per_call);
   if (!y_dev) return fail(TACHES_EINVAL, "y is NULL");
+  {
+    const int64_t S = (int64_t)n_blocks * c.block_size;
+    if (x_cstride == 0) x_cstride = S;
+    if (y_cstride == 0) y_cstride = S;
+    if (c.channels > 1 && (x_cstride < S || y_cstride < S))
+      return fail(TACHES_EINVAL, "channel stride (x %lld, y %lld) shorter than the call's %lld samples",
+                  (long long)x_cstride, (long long)y_cstride, (long long)S);
+  }
   // resolve the IR of every block: a pending set_ir applies first, then the schedule
   const int act = s->pending >= 0 ? s->pending : s->active;
   if (sched) {
@@ -346,8 +357,8 @@ int plan_call(taches_stream* s, const float* x_dev, float* y_dev, int n_blocks, 
   g.x = x_dev;
   g.y = y_dev;
   g.ring = s->ring;
-  g.x_cstride = S;
-  g.y_cstride = S;
+  g.x_cstride = x_cstride;
+  g.y_cstride = y_cstride;
   g.ring_cstride = s->Rcap;
   g.S = (int32_t)S;
   g.B = B;
@@ -447,7 +458,7 @@ int launch_call(taches_stream* s, CallPlan& p) {
 int process_common(taches_stream* s, const float* x_dev, float* y_dev, int n_blocks, const int32_t* sched) {
   if (s->pool) return fail(TACHES_EBUSY, "stream is attached to a pool; use taches_pool_step");
   CallPlan p;
-  int rc = plan_call(s, x_dev, y_dev, n_blocks, sched, &p);
+  int rc = plan_call(s, x_dev, 0, y_dev, 0, n_blocks, sched, &p);
   if (rc != TACHES_OK) return rc;
   rc = launch_call(s, p);
   if (rc != TACHES_OK) return rc;
@@ -712,6 +723,7 @@ struct taches_pool {
   int last_items = 0, last_wg = 0, last_r = 0;
   double last_plan_ms = 0.0;
   double last_imbalance = 0.0;
+  uint64_t steps = 0;                             // step counter (duplicate detection)
 };
 
 namespace {
@@ -884,19 +896,27 @@ int taches_pool_get_info(const taches_pool* p, taches_pool_info* out) {
 
 int taches_pool_step(taches_pool* p, int32_t n, taches_stream* const* streams, const float* const* x_dev,
                      float* const* y_dev, const int32_t* n_blocks) {
+  return taches_pool_step_strided(p, n, streams, x_dev, nullptr, y_dev, nullptr, n_blocks);
+}
+
+int taches_pool_step_strided(taches_pool* p, int32_t n, taches_stream* const* streams, const float* const* x_dev,
+                             const int64_t* x_cstride, float* const* y_dev, const int64_t* y_cstride,
+                             const int32_t* n_blocks) {
   if (!p) return fail(TACHES_EINVAL, "pool is NULL");
   if (n < 0 || (n > 0 && (!streams || !y_dev || !n_blocks))) return fail(TACHES_EINVAL, "bad step arguments");
   if (n == 0) return TACHES_OK;
   const auto t0 = std::chrono::steady_clock::now();
+  const uint64_t mark = ++p->steps;
   for (int i = 0; i < n; ++i) {
     if (!streams[i] || streams[i]->pool != p) return fail(TACHES_EINVAL, "stream %d is not attached to this pool", i);
-    for (int j = 0; j < i; ++j)
-      if (streams[j] == streams[i]) return fail(TACHES_EINVAL, "stream listed twice in one step");
+    if (streams[i]->step_mark == mark) return fail(TACHES_EINVAL, "stream listed twice in one step");
+    streams[i]->step_mark = mark;
   }
   // plan every call (validation first: an error leaves every stream untouched)
   std::vector<CallPlan> plans(n);
   for (int i = 0; i < n; ++i) {
-    int rc = plan_call(streams[i], x_dev ? x_dev[i] : nullptr, y_dev[i], n_blocks[i], nullptr, &plans[i]);
+    int rc = plan_call(streams[i], x_dev ? x_dev[i] : nullptr, x_cstride ? x_cstride[i] : 0, y_dev[i],
+                       y_cstride ? y_cstride[i] : 0, n_blocks[i], nullptr, &plans[i]);
     if (rc != TACHES_OK) return rc;
   }
   // split-precision streams run their own MFMA kernel on the pool's stream
@@ -947,25 +967,46 @@ int taches_pool_step(taches_pool* p, int32_t n, taches_stream* const* streams, c
     const int64_t by_work = std::max<int64_t>(1, total_work / max_work);
     const int nwg = (int)std::max<int64_t>(std::min<int64_t>(256, (int64_t)items.size()),
                                            std::min<int64_t>(256LL * per_cu, by_work));
-    // largest item first onto the least-loaded workgroup
-    std::sort(items.begin(), items.end(), [](const Item& a, const Item& b) { return a.work > b.work; });
-    std::vector<std::pair<int64_t, int>> heap;
-    heap.reserve(nwg);
-    for (int b = 0; b < nwg; ++b) heap.push_back({0, b});
     std::vector<int> owner(items.size());
     std::vector<int> count(nwg, 0);
-    auto cmp = [](const std::pair<int64_t, int>& a, const std::pair<int64_t, int>& b) { return a.first > b.first; };
-    for (size_t i = 0; i < items.size(); ++i) {
-      std::pop_heap(heap.begin(), heap.end(), cmp);
-      heap.back().first += items[i].work;
-      owner[i] = heap.back().second;
-      count[owner[i]] += 1;
-      std::push_heap(heap.begin(), heap.end(), cmp);
+    std::vector<int64_t> load(nwg, 0);
+    if (total_work >= 8 * max_work * (int64_t)nwg) {
+      // many small items: cut the list, in stream and tile order, into nwg
+      // runs of near-equal work (item i goes to the workgroup holding the
+      // middle of its work).  O(n); neighbouring tiles of a stream share
+      // most of their IR window, so a run keeps it in one XCD's L2.  No
+      // workgroup exceeds the mean by more than one item.
+      int64_t before = 0;
+      for (size_t i = 0; i < items.size(); ++i) {
+        const int64_t mid2 = 2 * before + items[i].work;   // twice the item's midpoint
+        const int b = (int)std::min<int64_t>(nwg - 1, mid2 * nwg / (2 * total_work));
+        owner[i] = b;
+        count[b] += 1;
+        load[b] += items[i].work;
+        before += items[i].work;
+      }
+    } else {
+      // largest item first onto the least-loaded workgroup
+      std::vector<size_t> order(items.size());
+      for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+      std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return items[a].work > items[b].work; });
+      std::vector<std::pair<int64_t, int>> heap;
+      heap.reserve(nwg);
+      for (int b = 0; b < nwg; ++b) heap.push_back({0, b});
+      auto cmp = [](const std::pair<int64_t, int>& a, const std::pair<int64_t, int>& b) { return a.first > b.first; };
+      for (size_t i : order) {
+        std::pop_heap(heap.begin(), heap.end(), cmp);
+        heap.back().first += items[i].work;
+        owner[i] = heap.back().second;
+        count[owner[i]] += 1;
+        std::push_heap(heap.begin(), heap.end(), cmp);
+      }
+      for (auto& h : heap) load[h.second] = h.first;
     }
     int64_t mx = 0, sum = 0;
-    for (auto& h : heap) {
-      mx = std::max(mx, h.first);
-      sum += h.first;
+    for (int b = 0; b < nwg; ++b) {
+      mx = std::max(mx, load[b]);
+      sum += load[b];
     }
     p->last_imbalance = sum > 0 ? (double)mx * nwg / (double)sum : 1.0;
     // pack the table: header, calls, fp64 flags, wg_begin, items grouped by workgroup

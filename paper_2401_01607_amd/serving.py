@@ -72,6 +72,7 @@ class Stats:
     busy_s: float = 0.0
     max_active: int = 0
     refused_attempts: int = 0
+    max_range: int = 0                                  # most blocks of one stream in one step
 
     def summary(self, wall_s: float) -> dict:
         lat = np.array(self.latencies_s) * 1e3
@@ -81,6 +82,7 @@ class Stats:
             "max_active_streams": self.max_active, "wall_s": round(wall_s, 2),
             "gmacs": round(self.macs / wall_s / 1e9, 2) if wall_s > 0 else 0.0,
             "step_busy_fraction": round(self.busy_s / wall_s, 3) if wall_s > 0 else 0.0,
+            "max_blocks_in_a_range": self.max_range,
         }
         if lat.size:
             out.update({"latency_ms_p50": round(float(np.percentile(lat, 50)), 3),
@@ -98,14 +100,15 @@ class Stats:
 class Scheduler:
     """Admission, pacing, IR swaps, batching and retirement."""
 
-    def __init__(self, requests, executor, fs: float = W.FS, max_blocks_per_step: int = 1,
+    def __init__(self, requests, executor, fs: float = W.FS, max_blocks_per_step=None,
                  warmup_s: float = 0.0, step_cost_s=None, min_tick_s: float = 0.0):
         self.pending = deque(sorted(requests, key=lambda r: r.arrival_s))
         self.queue: deque = deque()
         self.active: dict = {}
         self.ex = executor
         self.fs = fs
-        self.max_blocks_per_step = max_blocks_per_step
+        # blocks of one stream per step: the executor's limit unless given
+        self.max_blocks_per_step = max_blocks_per_step or getattr(executor, "max_blocks_per_step", 1)
         self.warmup_s = warmup_s
         self.stats = Stats()
         self.history: dict = {}   # rid -> Active after retirement (swap blocks etc.)
@@ -150,11 +153,20 @@ class Scheduler:
                 a.ir_version += 1
                 self.ex.set_ir(a.handle, a.req, a.ir_version)
                 a.swap_blocks.append(a.next_block)
+            # catch up on every block that has arrived, in one range that
+            # stops before the next due swap (it applies to the block that
+            # starts the next range) and at the end of the input (drain
+            # blocks have no input)
+            k0 = a.next_block
+            stop = a.n_in if k0 < a.n_in else a.n_total
+            next_swap = a.req.swap_times_s[a.ir_version] \
+                if k0 < a.n_in and a.ir_version < len(a.req.swap_times_s) else math.inf
             n = 1
-            while n < self.max_blocks_per_step and a.next_block + n < a.n_total \
-                    and a.block_ready_s(a.next_block + n, self.fs) <= now:
+            while n < self.max_blocks_per_step and k0 + n < stop \
+                    and a.block_ready_s(k0 + n, self.fs) <= now \
+                    and not (next_swap <= a.block_start_s(k0 + n, self.fs) - a.start_s):
                 n += 1
-            batch.append((a, a.next_block, n))
+            batch.append((a, k0, n))
         if not batch:
             return False
         self._last_step_s = now
@@ -172,6 +184,7 @@ class Scheduler:
                 if k < a.n_in:
                     self.stats.macs += a.req.block * a.req.ir_len * a.req.channels
             self.stats.blocks += n
+            self.stats.max_range = max(self.stats.max_range, n)
             a.next_block += n
         for rid in [rid for rid, a in self.active.items() if a.next_block >= a.n_total]:
             a = self.active.pop(rid)
@@ -225,23 +238,26 @@ class Scheduler:
 class GpuExecutor:
     """Runs the scheduler's steps on the library's pool.
 
-    Input audio comes from seeded noise banks in HBM, one per block size,
-    stored block-major ([block][2][B], 70 s each): block k of a request is
-    the contiguous [C][B] view bank_B[k0 + k, :C] (its last block, if
-    partial, a zero-padded copy); drain blocks have no input.  IRs are built
-    on the device from a seeded noise bank: tap n of version v of request r
-    is irbank[(r.seed + v) mod NB][n] * exp(-6.91 n / L), normalised to unit
-    L2 norm.  Outputs of the requests listed in keep_outputs are kept; the
-    others go to a per-step scratch buffer.  Retired streams are reset and
-    reused for later requests with the same (B, channels, IR-length class);
-    idle ones count against the HBM budget and are closed when a new stream
-    needs their bytes."""
+    Input audio comes from one seeded two-channel noise bank in HBM, planar
+    [2][70 s]: request r reads channels [0, C) from a seeded sample offset
+    on, its duration rounded up to whole blocks.  A step over blocks
+    k0 .. k0+n-1 of a stream passes the bank slice that starts at block k0,
+    with the bank's channel stride, so no input is copied; drain blocks have
+    no input.  IRs are built on the device from a seeded noise bank: tap n of
+    version v of request r is irbank[(r.seed + v) mod NB][n] *
+    exp(-6.91 n / L), normalised to unit L2 norm.  Outputs of the requests
+    listed in keep_outputs go to a [C][n_total*B] buffer per request, the
+    others to a scratch buffer reused by every step.  Retired streams are
+    reset and reused for later requests with the same (B, channels,
+    IR-length class); idle ones count against the HBM budget and are closed
+    when a new stream needs their bytes."""
 
     BANK_SECONDS = 70.0
+    DEFAULT_MAX_BLOCKS = 64
 
     def __init__(self, max_streams: int, hbm_budget_bytes: int, precision: int = 0, use_graph: bool = True,
                  ir_bank: int = 16, max_ir_len: int = 262_144, seed: int = 9, keep_outputs=(),
-                 max_blocks_per_step: int = 1):
+                 max_blocks_per_step: int = DEFAULT_MAX_BLOCKS):
         import torch
         from . import taches as T
         self.T, self.torch = T, torch
@@ -250,11 +266,9 @@ class GpuExecutor:
         self.max_blocks_per_step = max_blocks_per_step
         n = int(self.BANK_SECONDS * W.FS)
         noise = np.stack([W.signal_gauss(n, seed * 100 + c) for c in range(2)])
-        self.banks = {}
-        for B in W.BLOCK_CHOICES:
-            nb = n // B
-            self.banks[B] = torch.from_numpy(
-                np.ascontiguousarray(noise[:, :nb * B].reshape(2, nb, B).transpose(1, 0, 2))).cuda()
+        self.bank = torch.from_numpy(noise).cuda()
+        self.bank_len = n
+        self.bank_addr = self.bank.data_ptr()
         self.irbank = torch.from_numpy(np.stack([W.impulse_response(max_ir_len, seed * 1000 + k, decay=0.0)
                                                  for k in range(ir_bank)])).cuda()
         self.max_ir_len = max_ir_len
@@ -266,6 +280,7 @@ class GpuExecutor:
         self.max_streams = max_streams
         self.budget = hbm_budget_bytes
         self.idle_bytes = 0          # recycled streams not attached (counted against the budget)
+        self.scratch = torch.empty(1 << 20, device="cuda")
 
     @staticmethod
     def ir_class(L: int) -> int:
@@ -279,18 +294,18 @@ class GpuExecutor:
         v = base.double() * env
         return (v / torch.linalg.vector_norm(v)).float().contiguous()
 
-    def input_blocks(self, req):
-        """[n_in][C][B] input of a request (views into its bank; a partial
-        last block is a zero-padded copy)."""
-        B, C = req.block, req.channels
-        bank = self.banks[B]
-        n_in = max(1, math.ceil(req.n_samples() / B))
-        k0 = (req.seed * 7919) % (bank.shape[0] - n_in)
-        x = bank[k0:k0 + n_in, :C]
-        tail = req.n_samples() - (n_in - 1) * B
-        last = x[n_in - 1].clone()
-        last[:, tail:] = 0
-        return x, last
+    @staticmethod
+    def n_input_blocks(req) -> int:
+        return max(1, math.ceil(req.n_samples() / req.block))
+
+    def input_offset(self, req) -> int:
+        span = self.n_input_blocks(req) * req.block
+        return ((req.seed * 7919) % ((self.bank_len - span) // 64 + 1)) * 64
+
+    def input_signal(self, req):
+        """[C][n_in * B] input of a request (a view of the bank)."""
+        off = self.input_offset(req)
+        return self.bank[:req.channels, off:off + self.n_input_blocks(req) * req.block]
 
     def admit(self, req):
         T = self.T
@@ -324,12 +339,13 @@ class GpuExecutor:
             self.idle_bytes += s.info().device_bytes
             raise AdmissionRefused(T.STATUS_NAMES.get(rc, rc))
         s.set_ir(self.ir(req, 0))
-        x, last = self.input_blocks(req)
-        n_total = x.shape[0] + math.ceil((req.ir_len - 1) / req.block)
+        n_in = self.n_input_blocks(req)
+        n_total = n_in + math.ceil((req.ir_len - 1) / req.block)
         y = None
         if req.rid in self.keep:
-            y = self.torch.empty((n_total, req.channels, req.block), device="cuda")
-        self.live[req.rid] = (s, x, last, y, key)
+            y = self.torch.empty((req.channels, n_total * req.block), device="cuda")
+        x_addr = self.bank_addr + 4 * self.input_offset(req)
+        self.live[req.rid] = (s, x_addr, n_in, y, key)
         self.slots_used += 1
         return req.rid
 
@@ -337,33 +353,40 @@ class GpuExecutor:
         self.live[handle][0].set_ir(self.ir(req, version))
 
     def step(self, batch) -> None:
-        torch = self.torch
-        scratch_n = sum(req.channels * req.block * n for h, req, k0, n in batch if self.live[h][3] is None)
-        scratch = torch.empty(max(scratch_n, 1), device="cuda")
+        n = len(batch)
+        sp = np.empty(n, np.uint64)
+        xp = np.zeros(n, np.uint64)
+        yp = np.empty(n, np.uint64)
+        ycs = np.zeros(n, np.int64)
+        nbs = np.empty(n, np.int32)
+        scratch_n = sum(req.channels * req.block * nb for h, req, k0, nb in batch if self.live[h][3] is None)
+        if scratch_n > self.scratch.numel():
+            self.scratch = self.torch.empty(scratch_n, device="cuda")
+        sa = self.scratch.data_ptr()
         pos = 0
-        streams, xs, ys, nbs = [], [], [], []
-        for handle, req, k0, n in batch:
-            s, x, last, y, _ = self.live[handle]
-            n_in = x.shape[0]
-            assert n == 1, "one block per stream per step"
-            streams.append(s)
-            xs.append(None if k0 >= n_in else (last if k0 == n_in - 1 else x[k0]))
+        for i, (handle, req, k0, nb) in enumerate(batch):
+            s, x_addr, n_in, y, _ = self.live[handle]
+            B = req.block
+            sp[i] = s.h
+            if k0 < n_in:
+                xp[i] = x_addr + 4 * k0 * B
             if y is not None:
-                ys.append(y[k0])
+                yp[i] = y.data_ptr() + 4 * k0 * B
+                ycs[i] = y.shape[1]
             else:
-                m = req.channels * req.block
-                ys.append(scratch[pos:pos + m].view(req.channels, req.block))
-                pos += m
-            nbs.append(1)
-        self.pool.step(streams, xs, ys, nbs)
+                yp[i] = sa + 4 * pos
+                pos += req.channels * B * nb
+            nbs[i] = nb
+        self.pool.step_strided(sp, xp, np.full(n, self.bank_len, np.int64), yp, ycs, nbs)
         self.pool.synchronize()
 
     def retire(self, handle, req):
-        s, x, last, y, key = self.live.pop(handle)
+        s, x_addr, n_in, y, key = self.live.pop(handle)
         if y is not None:
-            xin = x.clone()
-            xin[-1] = last
-            self.kept[handle] = (xin.cpu().numpy(), y.cpu().numpy())
+            C, B = req.channels, req.block
+            xin = self.input_signal(req).cpu().numpy()
+            self.kept[handle] = (xin.reshape(C, n_in, B).transpose(1, 0, 2).copy(),
+                                 y.cpu().numpy().reshape(C, -1, B).transpose(1, 0, 2).copy())
         self.pool.detach(s)
         s.reset()
         self.free.setdefault(key, []).append(s)

@@ -82,6 +82,7 @@ _SIGS = {
     "taches_pool_attach": (ctypes.c_int, [_vp, _vp]),
     "taches_pool_detach": (ctypes.c_int, [_vp, _vp]),
     "taches_pool_step": (ctypes.c_int, [_vp, _i32, _vp, _vp, _vp, _vp]),
+    "taches_pool_step_strided": (ctypes.c_int, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp]),
     "taches_pool_set_hip_stream": (ctypes.c_int, [_vp, _vp]),
     "taches_pool_set_tile": (ctypes.c_int, [_vp, _i32]),
     "taches_pool_use_graph": (ctypes.c_int, [_vp, _i32]),
@@ -247,6 +248,26 @@ def taches_pool_step(p, streams, xs, ys, n_blocks) -> int:
     return lib.taches_pool_step(p, n, sarr, xarr, yarr, nb)
 
 
+def taches_pool_step_strided(p, streams, x_ptrs, x_cstride, y_ptrs, y_cstride, n_blocks) -> int:
+    """Raw-address form for large steps: numpy arrays of length n holding
+    stream handles and device addresses (uint64, 0 = NULL input), channel
+    strides in floats (int64, or None = packed) and block counts (int32)."""
+    n = len(n_blocks)
+
+    def arr(a, dt):
+        if a is None:
+            return None, None
+        a = np.ascontiguousarray(a, dtype=dt)
+        if a.shape != (n,):
+            raise ValueError("per-stream arrays must have one entry per stream")
+        return a, ctypes.c_void_p(a.ctypes.data)
+    keep = [arr(streams, np.uint64), arr(x_ptrs, np.uint64), arr(x_cstride, np.int64), arr(y_ptrs, np.uint64),
+            arr(y_cstride, np.int64), arr(n_blocks, np.int32)]
+    if keep[0][0] is None or keep[3][0] is None:
+        raise ValueError("streams and y_ptrs are required")
+    return lib.taches_pool_step_strided(p, n, *[k[1] for k in keep])
+
+
 def taches_pool_set_hip_stream(p, stream: int) -> int:
     return lib.taches_pool_set_hip_stream(p, ctypes.c_void_p(stream) if stream else None)
 
@@ -381,6 +402,11 @@ class Pool:
 
     def step(self, streams, xs, ys, n_blocks) -> None:
         _check(taches_pool_step(self.h, [s.h for s in streams], xs, ys, n_blocks), "taches_pool_step")
+
+    def step_strided(self, stream_ptrs, x_ptrs, x_cstride, y_ptrs, y_cstride, n_blocks) -> None:
+        """Step with raw addresses (see taches_pool_step_strided)."""
+        _check(taches_pool_step_strided(self.h, stream_ptrs, x_ptrs, x_cstride, y_ptrs, y_cstride, n_blocks),
+               "taches_pool_step_strided")
 
     def set_tile(self, r: int) -> None:
         _check(taches_pool_set_tile(self.h, r), "taches_pool_set_tile")

@@ -235,3 +235,32 @@ def test_config2_full_size_sampled_parity():
     assert np.max(np.abs(y[idx] - ref)) <= 1e-5 * rms
     assert not np.any(y[spec.n_samples + L - 1:])
     s.close()
+
+
+@pytest.mark.parametrize("B", (32, 64, 128))
+@pytest.mark.parametrize("r", (4, 8, 12, 16))
+def test_short_blocks_staged_together_bitwise(B, r):
+    """One-wave tiles stage runs of up to 256/B short blocks that share an
+    IR as one unit; swaps inside a call (including runs of a single block)
+    split the runs.  Integer inputs: exact against the oracle.  Float
+    inputs: one-wave tiles equal two-wave tiles (one chunk per wave, no
+    grouping) and per-block calls bit for bit."""
+    swaps = [3, 4, 11, 20, 21, 22, 40]
+    sched = [(0, 0)] + [(b, (i + 1) % 2) for i, b in enumerate(swaps)]
+    L1, L2 = 700, 1900
+    n = 60 * B
+    nb = -(-(n + L2) // B) + 1
+    xi = W.signal_int(n, 71, 31)
+    irs_i = [W.signal_int(L1, 72, 31), W.signal_int(L2, 73, 31)]
+    ref = oracle_run(xi, irs_i, sched, B, L2, nb)
+    yi, info = gpu_multi_block(xi, irs_i, sched, B, L2, nb, tile=(r, 1))
+    assert (info.tile_r, info.tile_w) == (r, 1)
+    assert np.array_equal(yi, ref)
+    x = W.signal_gauss(n, 74)
+    irs = [W.impulse_response(L1, 75), W.impulse_response(L2, 76)]
+    y1, _ = gpu_multi_block(x, irs, sched, B, L2, nb, tile=(r, 1))
+    y2, _ = gpu_multi_block(x, irs, sched, B, L2, nb, tile=(r, 2))
+    yb, _ = gpu_per_block(x, irs, sched, B, L2, nb, tile=(r, 1))
+    assert np.array_equal(y1, y2)
+    assert np.array_equal(y1, yb)
+    assert rel_err(y1, oracle_run(x, irs, sched, B, L2, nb)) <= TOL

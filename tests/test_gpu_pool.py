@@ -221,3 +221,90 @@ def test_config4_reduced_parity():
     for (x, h, B, L), y in list(zip(specs, ys))[::6]:
         ref = oracle_run(x, [h], [(0, 0)], B, L, nb)[0]
         assert rel_err(y, ref) <= 1e-5
+
+
+def test_strided_multiblock_steps_from_planar_buffers():
+    """Mono and stereo streams read blocks k .. k+n-1 straight out of one
+    planar [2][N] buffer (channel stride N) and write slices of planar
+    [C][total] outputs through taches_pool_step_strided, with a different
+    block count per stream and step (drain steps with no input included);
+    each equals the stream processed alone, bit for bit."""
+    import torch
+    T = binding()
+    N = 200_000
+    bank = torch.from_numpy(np.stack([W.signal_gauss(N, 61), W.signal_gauss(N, 62)])).cuda()
+    shapes = [(1, 32, 300), (2, 64, 2500), (2, 256, 9000), (1, 512, 700), (2, 32, 5000), (1, 128, 64)]
+    steps = 9
+    counts = [[1 + (i * 3 + k) % 5 for k in range(steps)] for i in range(len(shapes))]
+    pool = T.Pool(len(shapes), 64 * GB, use_graph=True)
+    ss, offs, ys, irs, n_in = [], [], [], [], []
+    for i, (C, B, L) in enumerate(shapes):
+        s = T.Stream(B, L, channels=C, max_blocks_per_call=5)
+        h = W.impulse_response(L, 6000 + i)
+        s.set_ir(h)
+        assert pool.attach(s) == T.TACHES_OK
+        ss.append(s)
+        irs.append(h)
+        offs.append(1000 * i + 64 * (i % 3))
+        total = sum(counts[i])
+        n_in.append(total - 2)                     # the last two blocks drain with no input
+        ys.append(torch.full((C, total * B), float("nan"), device="cuda"))
+    done = [0] * len(ss)
+    for k in range(steps):
+        sp, xp, xcs, yp, ycs, nbs = [], [], [], [], [], []
+        for i, s in enumerate(ss):
+            B, nk = s.B, counts[i][k]
+            # a range never mixes input and drain blocks
+            if done[i] < n_in[i]:
+                nk = min(nk, n_in[i] - done[i])
+            sp.append(s.h)
+            xp.append(bank.data_ptr() + 4 * (offs[i] + done[i] * B) if done[i] < n_in[i] else 0)
+            xcs.append(N)
+            yp.append(ys[i].data_ptr() + 4 * done[i] * B)
+            ycs.append(ys[i].shape[1])
+            nbs.append(nk)
+            counts[i][k] = nk
+        pool.step_strided(np.array(sp, np.uint64), np.array(xp, np.uint64), np.array(xcs), np.array(yp, np.uint64),
+                          np.array(ycs), np.array(nbs, np.int32))
+        for i in range(len(ss)):
+            done[i] += counts[i][k]
+    pool.synchronize()
+    for i, (C, B, L) in enumerate(shapes):
+        nb = done[i]
+        x = np.zeros((C, nb * B), np.float32)
+        x[:, :n_in[i] * B] = bank[:C, offs[i]:offs[i] + n_in[i] * B].cpu().numpy()
+        s = T.Stream(B, L, channels=C, max_blocks_per_call=nb)
+        s.set_ir(irs[i])
+        xd = torch.from_numpy(x).cuda()
+        yd = torch.empty_like(xd)
+        s.process_blocks(xd, yd, nb)
+        s.synchronize()
+        got = ys[i][:, :nb * B].cpu().numpy()
+        assert np.array_equal(got, yd.cpu().numpy()), f"stream {i}"
+        if i < 2:
+            ref = oracle_run(x, [irs[i]], [(0, 0)], B, L, nb)
+            for c in range(C):
+                assert rel_err(got[c], ref[c]) <= 1e-5
+        s.close()
+    pool.close()
+    for s in ss:
+        s.close()
+
+
+def test_strided_step_rejects_short_channel_stride():
+    import torch
+    T = binding()
+    pool = T.Pool(1, 64 * GB)
+    s = T.Stream(64, 256, channels=2, max_blocks_per_call=4)
+    s.set_ir(W.impulse_response(256, 3))
+    assert pool.attach(s) == T.TACHES_OK
+    y = torch.empty((2, 4 * 64), device="cuda")
+    with pytest.raises(T.TachesError):
+        pool.step_strided(np.array([s.h], np.uint64), np.zeros(1, np.uint64), None, np.array([y.data_ptr()], np.uint64),
+                          np.array([100], np.int64), np.array([4], np.int32))
+    pool.step_strided(np.array([s.h], np.uint64), np.zeros(1, np.uint64), None, np.array([y.data_ptr()], np.uint64),
+                      np.array([256], np.int64), np.array([4], np.int32))
+    pool.synchronize()
+    assert s.info().blocks_done == 4
+    pool.close()
+    s.close()

@@ -44,9 +44,10 @@ def test_mix_equals_alone_and_oracle():
     keep = [r.rid for r in reqs[::4]]
     ex = GpuExecutor(max_streams=16, hbm_budget_bytes=1 << 34, keep_outputs=keep, ir_bank=8,
                      max_ir_len=8192)
-    sch = Scheduler(reqs, ex)
+    sch = Scheduler(reqs, ex, min_tick_s=0.005)   # ticks 5 ms apart: multi-block catch-up ranges
     st = sch.run_realtime(1.2 + 0.5 + 8192 / 48000 + 1.5)
     assert st["completed"] == st["admitted"] == len(reqs)
+    assert st["max_blocks_in_a_range"] > 1
     assert st["steps"] > 0 and "latency_ms_p99" in st
     assert any(len(sch.history[rid].swap_blocks) > 0 for rid in keep)
     checked = 0
@@ -77,6 +78,7 @@ def test_small_budget_queues_requests():
     def nbytes(B, C):
         cfg = T.taches_config_default(B, 4096)
         cfg.channels = C
+        cfg.max_blocks_per_call = GpuExecutor.DEFAULT_MAX_BLOCKS
         return T.taches_bytes_for(cfg)
     per_max = max(nbytes(r.block, r.channels) for r in reqs)
     per_min = min(nbytes(r.block, r.channels) for r in reqs)

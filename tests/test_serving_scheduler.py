@@ -13,10 +13,12 @@ from paper_2401_01607_amd.serving import AdmissionRefused, Scheduler
 class OracleExecutor:
     """Slots and a byte budget like the pool; outputs from the FP64 oracle."""
 
-    def __init__(self, max_streams, budget):
+    def __init__(self, max_streams, budget, max_blocks_per_step=1):
         self.max_streams, self.budget = max_streams, budget
+        self.max_blocks_per_step = max_blocks_per_step
         self.live, self.used, self.out, self.steps = {}, 0, {}, []
         self.active_counts = []
+        self.max_range = 0
 
     @staticmethod
     def bytes_for(req):
@@ -51,6 +53,8 @@ class OracleExecutor:
         self.steps.append(len(batch))
         self.active_counts.append(len(self.live))
         for h, req, k0, n in batch:
+            assert 1 <= n <= self.max_blocks_per_step
+            self.max_range = max(self.max_range, n)
             s, x, ys = self.live[h]
             for k in range(k0, k0 + n):
                 xb = x[:, k * req.block:(k + 1) * req.block]
@@ -68,12 +72,17 @@ def _reqs(n, rate, dur=(0.02, 0.08), L=(32, 600), seed=5, swap_rate=30.0):
     return W.config5_requests(horizon_s=n / rate, rate_hz=rate, seed=seed, dur=dur, lrange=L, swap_rate_hz=swap_rate)
 
 
-def test_every_request_completes_with_its_exact_output():
+@pytest.mark.parametrize("max_blocks,step_cost", [(1, 1e-4), (16, 4e-3)])
+def test_every_request_completes_with_its_exact_output(max_blocks, step_cost):
+    """Also with multi-block catch-up ranges: a range never runs past a due
+    IR swap or the end of the input, so swaps still land on the first block
+    starting at or after their time."""
     reqs = _reqs(30, 200.0)
-    ex = OracleExecutor(max_streams=8, budget=1 << 30)
-    sch = Scheduler(reqs, ex, step_cost_s=1e-4)
+    ex = OracleExecutor(max_streams=8, budget=1 << 30, max_blocks_per_step=max_blocks)
+    sch = Scheduler(reqs, ex, step_cost_s=step_cost)
     st = sch.run_simulated(10.0)
     assert st["admitted"] == st["completed"] == len(reqs)
+    assert (ex.max_range > 1) == (max_blocks > 1)
     for r in reqs:
         x, y = ex.out[r.rid]
         a = sch.history[r.rid]
