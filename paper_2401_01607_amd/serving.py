@@ -7,16 +7,29 @@ waits in a FIFO queue.  An admitted stream delivers one block of B samples
 every B / fs seconds (real-time pacing).  Each scheduler tick gathers every
 block that has arrived, over all admitted streams, into one batched step
 (one persistent launch through the library's pool), so requests that arrive
-while others are running join the next step.  IR changes requested during
-a stream apply to its next block (Abstract; Section 6).  When a stream's
-input ends, its temporal overflow (L - 1 samples, Section 4.1) is drained
-with zero-input blocks, then the stream retires and frees its slot and bytes.
+while others are running join the next step, and a stream that has fallen
+behind catches up with several blocks in one step.  IR changes requested
+during a stream apply to the first block that starts at or after the
+change (Abstract; Section 6).  When a stream's input ends, its temporal
+overflow (L - 1 samples, Section 4.1) is drained with zero-input blocks,
+paced like input blocks (silence keeps arriving at the sample rate until
+the tail has rung out), then the stream retires and frees its slot and
+bytes.
 
 Per block the scheduler records latency = time its output is ready minus
-time its last input sample arrived; the deadline is one block period.
+time its last input sample arrived (for a drain block, the time its last
+sample of silence would have arrived); the deadline is one block period.
 
 The Scheduler holds all the policy and is independent of the device: the
 executor it drives is GpuExecutor here (library pool) or a stub in tests.
+The per-stream state it scans every tick lives in numpy arrays, so a tick
+costs a fixed number of array operations plus Python work only for the
+streams that are admitted, swap IRs or retire in it.
+
+Executor interface: admit(req) -> int handle (raises AdmissionRefused),
+set_ir(handle, req, version), step(handles, k0, n) with int64 arrays (stream
+handles[i] processes blocks k0[i] .. k0[i]+n[i]-1; outputs ready on
+return), retire(handle, req), and an attribute max_blocks_per_step.
 """
 from __future__ import annotations
 
@@ -36,8 +49,9 @@ class AdmissionRefused(Exception):
 
 @dataclass
 class Active:
+    """Book-keeping of one admitted request (what tests and reports read)."""
     req: W.ServingRequest
-    handle: object
+    handle: int
     start_s: float              # admission time: the stream's first sample time
     n_in: int                   # input blocks
     n_drain: int                # zero-input blocks for the temporal overflow
@@ -49,21 +63,9 @@ class Active:
     def n_total(self) -> int:
         return self.n_in + self.n_drain
 
-    def block_ready_s(self, k: int, fs: float) -> float:
-        """Time the last sample of block k has arrived (drain blocks: at the
-        end of the input)."""
-        k_in = min(k, self.n_in - 1)
-        return self.start_s + (k_in + 1) * self.req.block / fs
-
-    def block_start_s(self, k: int, fs: float) -> float:
-        return self.start_s + k * self.req.block / fs
-
 
 @dataclass
 class Stats:
-    latencies_s: list = field(default_factory=list)    # per block (after warm-up)
-    deadlines_s: list = field(default_factory=list)
-    queue_waits_s: list = field(default_factory=list)
     admitted: int = 0
     completed: int = 0
     steps: int = 0
@@ -73,10 +75,21 @@ class Stats:
     max_active: int = 0
     refused_attempts: int = 0
     max_range: int = 0                                  # most blocks of one stream in one step
+    queue_waits_s: list = field(default_factory=list)
+    _lat: list = field(default_factory=list)            # per-tick arrays of block latencies (after warm-up)
+    _dl: list = field(default_factory=list)             # matching deadlines
+
+    @property
+    def latencies_s(self) -> np.ndarray:
+        return np.concatenate(self._lat) if self._lat else np.zeros(0)
+
+    @property
+    def deadlines_s(self) -> np.ndarray:
+        return np.concatenate(self._dl) if self._dl else np.zeros(0)
 
     def summary(self, wall_s: float) -> dict:
-        lat = np.array(self.latencies_s) * 1e3
-        dl = np.array(self.deadlines_s) * 1e3
+        lat = self.latencies_s * 1e3
+        dl = self.deadlines_s * 1e3
         out = {
             "admitted": self.admitted, "completed": self.completed, "steps": self.steps, "blocks": self.blocks,
             "max_active_streams": self.max_active, "wall_s": round(wall_s, 2),
@@ -97,6 +110,47 @@ class Stats:
         return out
 
 
+class _Table:
+    """Dense struct-of-arrays over the admitted streams (swap-remove)."""
+
+    FIELDS = (("start", np.float64), ("n_in", np.int64), ("n_total", np.int64), ("nxt", np.int64),
+              ("B", np.int64), ("C", np.int64), ("L", np.int64), ("swap_t", np.float64), ("handle", np.int64))
+
+    def __init__(self, cap: int = 1024):
+        self.n = 0
+        self.objs: list = []
+        for name, dt in self.FIELDS:
+            setattr(self, name, np.zeros(cap, dt))
+
+    def add(self, a: Active) -> None:
+        if self.n == self.start.size:
+            for name, dt in self.FIELDS:
+                old = getattr(self, name)
+                new = np.zeros(2 * old.size, dt)
+                new[:old.size] = old
+                setattr(self, name, new)
+        i = self.n
+        r = a.req
+        self.start[i], self.n_in[i], self.n_total[i], self.nxt[i] = a.start_s, a.n_in, a.n_total, 0
+        self.B[i], self.C[i], self.L[i] = r.block, r.channels, r.ir_len
+        self.swap_t[i] = r.swap_times_s[0] if r.swap_times_s else math.inf
+        self.handle[i] = a.handle
+        self.objs.append(a)
+        self.n += 1
+
+    def remove(self, i: int) -> Active:
+        last = self.n - 1
+        a = self.objs[i]
+        if i != last:
+            for name, _ in self.FIELDS:
+                arr = getattr(self, name)
+                arr[i] = arr[last]
+            self.objs[i] = self.objs[last]
+        self.objs.pop()
+        self.n -= 1
+        return a
+
+
 class Scheduler:
     """Admission, pacing, IR swaps, batching and retirement."""
 
@@ -104,7 +158,7 @@ class Scheduler:
                  warmup_s: float = 0.0, step_cost_s=None, min_tick_s: float = 0.0):
         self.pending = deque(sorted(requests, key=lambda r: r.arrival_s))
         self.queue: deque = deque()
-        self.active: dict = {}
+        self.tab = _Table()
         self.ex = executor
         self.fs = fs
         # blocks of one stream per step: the executor's limit unless given
@@ -120,11 +174,11 @@ class Scheduler:
         self.min_tick_s = min_tick_s
         self._last_step_s = -1e30
 
-    # -- one tick --------------------------------------------------------
-    def tick(self, now: float) -> bool:
-        """Advance to time `now`; returns True if a step was run."""
-        if now < self._last_step_s + self.min_tick_s:
-            return False
+    @property
+    def active(self) -> dict:
+        return {a.req.rid: a for a in self.tab.objs}
+
+    def _admit(self, now: float) -> None:
         while self.pending and self.pending[0].arrival_s <= now:
             self.queue.append(self.pending.popleft())
         while self.queue:
@@ -137,61 +191,99 @@ class Scheduler:
             self.queue.popleft()
             n_in = max(1, math.ceil(req.n_samples() / req.block))
             n_drain = math.ceil((req.ir_len - 1) / req.block)
-            self.active[req.rid] = Active(req, handle, now, n_in, n_drain)
+            self.tab.add(Active(req, int(handle), now, n_in, n_drain))
             self.stats.admitted += 1
             if req.arrival_s >= self.warmup_s:
                 self.stats.queue_waits_s.append(now - req.arrival_s)
-        self.stats.max_active = max(self.stats.max_active, len(self.active))
-        batch = []
-        for a in self.active.values():
-            if a.next_block >= a.n_total or a.block_ready_s(a.next_block, self.fs) > now:
-                continue
-            # IR swaps due by the start of this block apply to it
-            t_block = a.block_start_s(a.next_block, self.fs) - a.start_s
-            while a.ir_version < len(a.req.swap_times_s) and a.req.swap_times_s[a.ir_version] <= t_block \
-                    and a.next_block < a.n_in:
+        self.stats.max_active = max(self.stats.max_active, self.tab.n)
+
+    # -- one tick --------------------------------------------------------
+    def tick(self, now: float) -> bool:
+        """Advance to time `now`; returns True if a step was run."""
+        if now < self._last_step_s + self.min_tick_s:
+            return False
+        self._admit(now)
+        t, n_act = self.tab, self.tab.n
+        if n_act == 0:
+            return False
+        fs = self.fs
+        sl = slice(0, n_act)
+        start, n_in, n_total, nxt = t.start[sl], t.n_in[sl], t.n_total[sl], t.nxt[sl]
+        B = t.B[sl]
+        # blocks whose last sample (of input, or of silence while draining) has arrived
+        arrived = np.floor((now - start) * fs / B).astype(np.int64)
+        avail = np.minimum(np.maximum(arrived, 0), n_total)
+        ready = avail > nxt
+        if not ready.any():
+            return False
+        # IR swaps due by the start of a stream's next block apply to it
+        due = ready & (nxt < n_in) & (t.swap_t[sl] <= nxt * B / fs)
+        for i in np.nonzero(due)[0]:
+            a = t.objs[i]
+            k0 = int(nxt[i])
+            sw = a.req.swap_times_s
+            while a.ir_version < len(sw) and sw[a.ir_version] <= k0 * a.req.block / fs:
                 a.ir_version += 1
                 self.ex.set_ir(a.handle, a.req, a.ir_version)
-                a.swap_blocks.append(a.next_block)
-            # catch up on every block that has arrived, in one range that
-            # stops before the next due swap (it applies to the block that
-            # starts the next range) and at the end of the input (drain
-            # blocks have no input)
-            k0 = a.next_block
-            stop = a.n_in if k0 < a.n_in else a.n_total
-            next_swap = a.req.swap_times_s[a.ir_version] \
-                if k0 < a.n_in and a.ir_version < len(a.req.swap_times_s) else math.inf
-            n = 1
-            while n < self.max_blocks_per_step and k0 + n < stop \
-                    and a.block_ready_s(k0 + n, self.fs) <= now \
-                    and not (next_swap <= a.block_start_s(k0 + n, self.fs) - a.start_s):
-                n += 1
-            batch.append((a, k0, n))
-        if not batch:
-            return False
+                a.swap_blocks.append(k0)
+            t.swap_t[i] = sw[a.ir_version] if a.ir_version < len(sw) else math.inf
+        # one range per ready stream: every arrived block, at most
+        # max_blocks_per_step, ending before the block at which the next swap
+        # is due (it starts the next range) and at the end of the input
+        # (drain blocks have no input)
+        idx = np.nonzero(ready)[0]
+        k0 = nxt[idx].copy()
+        Bi = B[idx]
+        n_in_i = n_in[idx]
+        is_in = k0 < n_in_i
+        end = np.minimum(avail[idx], k0 + self.max_blocks_per_step)
+        end = np.where(is_in, np.minimum(end, n_in_i), end)
+        swt = t.swap_t[idx]
+        fin = is_in & np.isfinite(swt)
+        if fin.any():
+            ks = np.full(idx.size, np.iinfo(np.int64).max)
+            ks[fin] = np.maximum(k0[fin] + 1, np.ceil(swt[fin] * fs / Bi[fin] - 1e-9).astype(np.int64))
+            # the exact rule: the first block k with k * B / fs >= swap time
+            lo = fin & (ks - 1 > k0) & (swt <= (ks - 1) * Bi / fs)
+            ks[lo] -= 1
+            hi = fin & (swt > ks * Bi / fs)
+            ks[hi] += 1
+            end = np.minimum(end, ks)
+        n = end - k0
         self._last_step_s = now
         t0 = time.perf_counter()
-        self.ex.step([(a.handle, a.req, k0, n) for a, k0, n in batch])   # outputs ready on return
+        self.ex.step(t.handle[idx], k0, n)                  # outputs ready on return
         elapsed = time.perf_counter() - t0
         self.stats.busy_s += elapsed
         done_s = now + (elapsed if self.step_cost_s is None else self.step_cost_s)
         self.stats.steps += 1
-        for a, k0, n in batch:
-            for k in range(k0, k0 + n):
-                if a.block_ready_s(k, self.fs) >= self.warmup_s:
-                    self.stats.latencies_s.append(done_s - a.block_ready_s(k, self.fs))
-                    self.stats.deadlines_s.append(a.req.block / self.fs)
-                if k < a.n_in:
-                    self.stats.macs += a.req.block * a.req.ir_len * a.req.channels
-            self.stats.blocks += n
-            self.stats.max_range = max(self.stats.max_range, n)
-            a.next_block += n
-        for rid in [rid for rid, a in self.active.items() if a.next_block >= a.n_total]:
-            a = self.active.pop(rid)
+        self._record(done_s, start[idx], k0, n, Bi, is_in, t.L[idx], t.C[idx])
+        t.nxt[idx] = end
+        for i in sorted(np.nonzero(t.nxt[:t.n] >= t.n_total[:t.n])[0], reverse=True):
+            a = t.remove(int(i))
+            a.next_block = a.n_total
             self.ex.retire(a.handle, a.req)
-            self.history[rid] = a
+            self.history[a.req.rid] = a
             self.stats.completed += 1
         return True
+
+    def _record(self, done_s, start, k0, n, B, is_in, L, C) -> None:
+        """Latency of every block of the step's ranges (vectorized)."""
+        st = self.stats
+        tot = int(n.sum())
+        st.blocks += tot
+        st.max_range = max(st.max_range, int(n.max()))
+        st.macs += int(np.sum(np.where(is_in, n * B * L * C, 0)))
+        rng = np.repeat(np.arange(n.size), n)
+        j = np.arange(tot) - np.repeat(np.cumsum(n) - n, n)
+        k = k0[rng] + j
+        per = B[rng] / self.fs
+        # block k is complete at start + (k+1) B / fs
+        ready_s = start[rng] + (k + 1) * per
+        keep = ready_s >= self.warmup_s
+        if keep.any():
+            st._lat.append(done_s - ready_s[keep])
+            st._dl.append(per[keep])
 
     # -- drivers -----------------------------------------------------------
     def run_realtime(self, duration_s: float, clock=time.perf_counter, sleep=time.sleep) -> dict:
@@ -226,9 +318,11 @@ class Scheduler:
         cands = []
         if self.pending:
             cands.append(self.pending[0].arrival_s)
-        for a in self.active.values():
-            if a.next_block < a.n_total:
-                cands.append(a.block_ready_s(a.next_block, self.fs))
+        t = self.tab
+        if t.n:
+            sl = slice(0, t.n)
+            # the next block k of each stream is complete at start + (k + 1) B / fs
+            cands.append(float(np.min(t.start[sl] + (t.nxt[sl] + 1) * t.B[sl] / self.fs)))
         if not cands:
             return None
         # nothing can run before the minimum tick interval has passed
@@ -243,14 +337,15 @@ class GpuExecutor:
     on, its duration rounded up to whole blocks.  A step over blocks
     k0 .. k0+n-1 of a stream passes the bank slice that starts at block k0,
     with the bank's channel stride, so no input is copied; drain blocks have
-    no input.  IRs are built on the device from a seeded noise bank: tap n of
-    version v of request r is irbank[(r.seed + v) mod NB][n] *
-    exp(-6.91 n / L), normalised to unit L2 norm.  Outputs of the requests
-    listed in keep_outputs go to a [C][n_total*B] buffer per request, the
-    others to a scratch buffer reused by every step.  Retired streams are
-    reset and reused for later requests with the same (B, channels,
-    IR-length class); idle ones count against the HBM budget and are closed
-    when a new stream needs their bytes."""
+    no input.  IR version v of request r is the first L taps of row
+    (r.seed + v) mod NB of a bank of flat white-noise IRs (the paper's IR
+    shape, Section 5.1), each row of unit L2 norm over max_ir_len taps, so a
+    swap is one device-to-device copy.  Outputs of the requests listed in
+    keep_outputs go to a [C][n_total*B] buffer per request, the others to a
+    scratch buffer reused by every step.  Retired streams are reset and
+    reused for later requests with the same (B, channels, IR-length class);
+    idle ones count against the HBM budget and are closed when a new stream
+    needs their bytes."""
 
     BANK_SECONDS = 70.0
     DEFAULT_MAX_BLOCKS = 64
@@ -276,23 +371,28 @@ class GpuExecutor:
         self.live: dict = {}
         self.keep = set(keep_outputs)
         self.kept: dict = {}
-        self.slots_used = 0
         self.max_streams = max_streams
         self.budget = hbm_budget_bytes
         self.idle_bytes = 0          # recycled streams not attached (counted against the budget)
         self.scratch = torch.empty(1 << 20, device="cuda")
+        # per-handle arrays read by step(); handles are reused after retire
+        cap = max_streams
+        self.h_stream = np.zeros(cap, np.uint64)
+        self.h_x = np.zeros(cap, np.uint64)
+        self.h_y = np.zeros(cap, np.uint64)
+        self.h_ycs = np.zeros(cap, np.int64)
+        self.h_B = np.zeros(cap, np.int64)
+        self.h_C = np.zeros(cap, np.int64)
+        self.h_nin = np.zeros(cap, np.int64)
+        self.free_handles = list(range(cap - 1, -1, -1))
 
     @staticmethod
     def ir_class(L: int) -> int:
         return 1 << max(0, (L - 1).bit_length())
 
     def ir(self, req, version: int):
-        torch = self.torch
-        L = req.ir_len
-        base = self.irbank[(req.seed + version) % self.irbank.shape[0], :L]
-        env = torch.exp(-W.DECAY * torch.arange(L, device="cuda", dtype=torch.float64) / L)
-        v = base.double() * env
-        return (v / torch.linalg.vector_norm(v)).float().contiguous()
+        """IR version `version` of a request (a device view, FP32)."""
+        return self.irbank[(req.seed + version) % self.irbank.shape[0], :req.ir_len]
 
     @staticmethod
     def n_input_blocks(req) -> int:
@@ -307,10 +407,10 @@ class GpuExecutor:
         off = self.input_offset(req)
         return self.bank[:req.channels, off:off + self.n_input_blocks(req) * req.block]
 
-    def admit(self, req):
+    def admit(self, req) -> int:
         T = self.T
         key = (req.block, req.channels, min(self.ir_class(req.ir_len), self.max_ir_len))
-        if self.slots_used >= self.max_streams:
+        if not self.free_handles:
             raise AdmissionRefused("slots")
         lst = self.free.get(key)
         if lst:
@@ -341,57 +441,51 @@ class GpuExecutor:
         s.set_ir(self.ir(req, 0))
         n_in = self.n_input_blocks(req)
         n_total = n_in + math.ceil((req.ir_len - 1) / req.block)
+        h = self.free_handles.pop()
         y = None
         if req.rid in self.keep:
             y = self.torch.empty((req.channels, n_total * req.block), device="cuda")
-        x_addr = self.bank_addr + 4 * self.input_offset(req)
-        self.live[req.rid] = (s, x_addr, n_in, y, key)
-        self.slots_used += 1
-        return req.rid
+        self.live[h] = (s, y, key, req)
+        self.h_stream[h] = s.h
+        self.h_x[h] = self.bank_addr + 4 * self.input_offset(req)
+        self.h_y[h] = y.data_ptr() if y is not None else 0
+        self.h_ycs[h] = y.shape[1] if y is not None else 0
+        self.h_B[h], self.h_C[h], self.h_nin[h] = req.block, req.channels, n_in
+        return h
 
     def set_ir(self, handle, req, version: int):
         self.live[handle][0].set_ir(self.ir(req, version))
 
-    def step(self, batch) -> None:
-        n = len(batch)
-        sp = np.empty(n, np.uint64)
-        xp = np.zeros(n, np.uint64)
-        yp = np.empty(n, np.uint64)
-        ycs = np.zeros(n, np.int64)
-        nbs = np.empty(n, np.int32)
-        scratch_n = sum(req.channels * req.block * nb for h, req, k0, nb in batch if self.live[h][3] is None)
-        if scratch_n > self.scratch.numel():
-            self.scratch = self.torch.empty(scratch_n, device="cuda")
-        sa = self.scratch.data_ptr()
-        pos = 0
-        for i, (handle, req, k0, nb) in enumerate(batch):
-            s, x_addr, n_in, y, _ = self.live[handle]
-            B = req.block
-            sp[i] = s.h
-            if k0 < n_in:
-                xp[i] = x_addr + 4 * k0 * B
-            if y is not None:
-                yp[i] = y.data_ptr() + 4 * k0 * B
-                ycs[i] = y.shape[1]
-            else:
-                yp[i] = sa + 4 * pos
-                pos += req.channels * B * nb
-            nbs[i] = nb
-        self.pool.step_strided(sp, xp, np.full(n, self.bank_len, np.int64), yp, ycs, nbs)
+    def step(self, handles, k0, n) -> None:
+        B, C = self.h_B[handles], self.h_C[handles]
+        adv = (4 * k0 * B).astype(np.uint64)                # byte offset of block k0
+        xp = np.where(k0 < self.h_nin[handles], self.h_x[handles] + adv, np.uint64(0)).astype(np.uint64)
+        yk = self.h_y[handles]
+        kept = yk != 0
+        m = np.where(kept, 0, C * B * n)
+        need = int(m.sum())
+        if need > self.scratch.numel():
+            self.scratch = self.torch.empty(need, device="cuda")
+        off = (4 * (np.cumsum(m) - m)).astype(np.uint64)
+        yp = np.where(kept, yk + adv, np.uint64(self.scratch.data_ptr()) + off).astype(np.uint64)
+        self.pool.step_strided(self.h_stream[handles], xp, np.full(handles.size, self.bank_len, np.int64), yp,
+                               np.where(kept, self.h_ycs[handles], 0), n.astype(np.int32))
         self.pool.synchronize()
 
     def retire(self, handle, req):
-        s, x_addr, n_in, y, key = self.live.pop(handle)
+        s, y, key, _ = self.live.pop(handle)
         if y is not None:
             C, B = req.channels, req.block
+            n_in = int(self.h_nin[handle])
             xin = self.input_signal(req).cpu().numpy()
-            self.kept[handle] = (xin.reshape(C, n_in, B).transpose(1, 0, 2).copy(),
-                                 y.cpu().numpy().reshape(C, -1, B).transpose(1, 0, 2).copy())
+            self.kept[req.rid] = (xin.reshape(C, n_in, B).transpose(1, 0, 2).copy(),
+                                  y.cpu().numpy().reshape(C, -1, B).transpose(1, 0, 2).copy())
         self.pool.detach(s)
         s.reset()
         self.free.setdefault(key, []).append(s)
         self.idle_bytes += s.info().device_bytes
-        self.slots_used -= 1
+        self.h_stream[handle] = 0
+        self.free_handles.append(handle)
 
     def close(self):
         for s, *_ in self.live.values():

@@ -42,20 +42,22 @@ class OracleExecutor:
             raise AdmissionRefused("full")
         s = O.OracleStream(req.block, req.ir_len, req.channels)
         s.set_ir(self.ir(req, 0))
-        self.live[req.rid] = (s, self.signal(req), [])
+        self.live[req.rid] = (s, self.signal(req), [], req)
         self.used += b
         return req.rid
 
     def set_ir(self, h, req, v):
         self.live[h][0].set_ir(self.ir(req, v))
 
-    def step(self, batch):
-        self.steps.append(len(batch))
+    def step(self, handles, k0s, ns):
+        self.steps.append(len(handles))
         self.active_counts.append(len(self.live))
-        for h, req, k0, n in batch:
+        assert len(set(handles.tolist())) == len(handles)
+        for h, k0, n in zip(handles.tolist(), k0s.tolist(), ns.tolist()):
             assert 1 <= n <= self.max_blocks_per_step
             self.max_range = max(self.max_range, n)
-            s, x, ys = self.live[h]
+            s, x, ys, req = self.live[h]
+            assert len(ys) == k0, "ranges of a stream are consecutive"
             for k in range(k0, k0 + n):
                 xb = x[:, k * req.block:(k + 1) * req.block]
                 if xb.shape[1] < req.block:
@@ -63,7 +65,7 @@ class OracleExecutor:
                 ys.append(s.process(xb)[1])
 
     def retire(self, h, req):
-        s, x, ys = self.live.pop(h)
+        s, x, ys, _ = self.live.pop(h)
         self.out[h] = (x, np.concatenate(ys, axis=1))
         self.used -= self.bytes_for(req)
 
