@@ -32,6 +32,34 @@ sys.path.insert(0, ROOT)
 FP32_PEAK_TFLOPS = 157.3        # MI355X published FP32 vector peak
 HBM_PEAK_GBS = 8000.0
 
+# HBM traffic of the main kernel per launch, from two rocprofv3 --pmc runs of
+# this benchmark (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled
+# by what the same counter reads for a plain device copy of 1 GiB (FETCH_SIZE
+# reads half the bytes copied, WRITE_SIZE all of them).  Valid only for the
+# kernel source the counters were taken on (SHA-256 of k_gather.hip followed
+# by taches_internal.h); reported as null once that source has changed.
+TRAFFIC_COUNTERS = {
+    "kernel": "k_gather<16,4,float>",
+    "source_sha256": "536e4b288dbfd8f9ece02c2530cf795ecefb08ba7c84b74fc69b21e50fd5aa88",
+    "fetch_kib": 9993.9, "fetch_scale": 2.0,
+    "write_kib": 4006.0, "write_scale": 1.0,
+}
+
+
+def measured_traffic_bytes(kernel: str):
+    import hashlib
+    c = TRAFFIC_COUNTERS
+    if kernel != c["kernel"]:
+        return None
+    src = os.path.join(ROOT, "paper_2401_01607_amd", "csrc")
+    h = hashlib.sha256()
+    for f in ("k_gather.hip", "taches_internal.h"):
+        with open(os.path.join(src, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != c["source_sha256"]:
+        return None
+    return round(1024 * (c["fetch_kib"] * c["fetch_scale"] + c["write_kib"] * c["write_scale"]))
+
 
 def parse():
     p = argparse.ArgumentParser()
@@ -188,7 +216,7 @@ def main():
             "peak": FP32_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": round(achieved_tflops / FP32_PEAK_TFLOPS, 4),
-            "traffic": None,
+            "traffic": measured_traffic_bytes(f"k_gather<{main_tile[0]},{main_tile[1]},float>"),
             "kernel_ms": round(k_avg_s * 1e3, 4),
             "flops_per_launch": flops,
         },
@@ -352,7 +380,7 @@ def extra_c4_batched_vs_plain():
     for s in ss:
         s.close()
     # batched: one pool step per repetition, replayed from the pool's graph
-    timings = []
+    timings, dev_ms = [], []
     pool = T.Pool(512, 1 << 40, use_graph=True)
     for rep in range(4):
         ss = open_streams()
@@ -364,12 +392,14 @@ def extra_c4_batched_vs_plain():
         torch.cuda.synchronize()
         timings.append(time.perf_counter() - t0)
         info = pool.info()
+        dev_ms.append(info.last_device_ms)
         for s in ss:
             pool.detach(s)
             s.close()
     pool.close()
     timings = timings[1:]  # the first step also captures the graph
     t_batch = float(np.median(timings))
+    t_dev = float(np.median(dev_ms[1:])) / 1e3
     same = all(torch.equal(a, ys[i * 64]) for i, a in enumerate(alone))
     res["plain"] = {"ms": round(t_plain * 1e3, 2), "gmacs": round(macs / t_plain / 1e9, 1)}
     res["batched"] = {"ms": round(t_batch * 1e3, 2), "gmacs": round(macs / t_batch / 1e9, 1),
@@ -377,7 +407,10 @@ def extra_c4_batched_vs_plain():
                       "frac_of_fp32_peak": round(2 * macs / t_batch / 1e12 / FP32_PEAK_TFLOPS, 4),
                       "tile_r": info.last_r, "items": info.last_items, "workgroups": info.last_workgroups,
                       "plan_ms": round(info.last_plan_ms, 2), "imbalance": round(info.last_imbalance, 4),
-                      "graph_replays": int(info.graph_replays)}
+                      "graph_replays": int(info.graph_replays),
+                      "device_ms": round(t_dev * 1e3, 2),
+                      "device_tflops": round(2 * macs / t_dev / 1e12, 2),
+                      "device_frac_of_fp32_peak": round(2 * macs / t_dev / 1e12 / FP32_PEAK_TFLOPS, 4)}
     res["speedup_batched_over_plain"] = round(t_plain / t_batch, 2)
     res["batched_equals_alone_bitwise"] = bool(same)
     return res
@@ -395,6 +428,7 @@ def extra_c5_serving(duration_s=30.0, warmup_s=10.0):
     sch = Scheduler(reqs, ex, warmup_s=warmup_s)
     st = sch.run_realtime(duration_s)
     info = ex.pool.info()
+    st["gpu_busy_fraction"] = round(ex.device_s / st["wall_s"], 3)
     ex.close()
     st.update({"workload": "Poisson 200 streams/s, 10-60 s, mono/stereo, L log-U[512, 262144], swaps 0.5/s, "
                            "B from {32..512}, <= 4096 streams, 64 GiB budget, FP32, real-time 48 kHz",

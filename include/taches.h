@@ -249,6 +249,8 @@ typedef struct taches_pool_info {
   int64_t graph_replays;
   double last_plan_ms;      /* host time to plan the last step */
   double last_imbalance;    /* busiest workgroup's work / mean work */
+  double last_device_ms;    /* device time of the last step's batched launch
+                               (table copy + kernel); -1 until it has run */
 } taches_pool_info;
 
 int taches_pool_get_info(const taches_pool* p, taches_pool_info* out);

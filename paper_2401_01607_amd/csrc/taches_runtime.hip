@@ -339,14 +339,23 @@ int plan_call(taches_stream* s, const float* x_dev, int64_t x_cstride, float* y_
   int Lmax_call = 0;
   int64_t ext = 0;
   int cur = act;
-  for (int b = 0; b < n_blocks; ++b) {
-    if (sched && sched[b] >= 0) cur = sched[b];
-    if (b == 0) first_slot = cur;
-    else if (cur != first_slot) uniform = false;
+  if (!sched) {
+    // one IR for the whole call
+    first_slot = cur;
     if (x_dev && cur >= 0) {
-      const int L = s->slots[cur].L;
-      Lmax_call = std::max(Lmax_call, L);
-      ext = std::max<int64_t>(ext, (int64_t)b * B + B + L - 1);
+      Lmax_call = s->slots[cur].L;
+      ext = S + Lmax_call - 1;
+    }
+  } else {
+    for (int b = 0; b < n_blocks; ++b) {
+      if (sched[b] >= 0) cur = sched[b];
+      if (b == 0) first_slot = cur;
+      else if (cur != first_slot) uniform = false;
+      if (x_dev && cur >= 0) {
+        const int L = s->slots[cur].L;
+        Lmax_call = std::max(Lmax_call, L);
+        ext = std::max<int64_t>(ext, (int64_t)b * B + B + L - 1);
+      }
     }
   }
   const int64_t n_out = std::max<int64_t>(std::max<int64_t>(S, s->live), ext);
@@ -724,6 +733,8 @@ struct taches_pool {
   double last_plan_ms = 0.0;
   double last_imbalance = 0.0;
   uint64_t steps = 0;                             // step counter (duplicate detection)
+  hipEvent_t ev_beg = nullptr, ev_end = nullptr;  // device time of the last batched launch
+  bool timed = false;
 };
 
 namespace {
@@ -737,6 +748,33 @@ void pool_drop_graph(taches_pool* p) {
 }
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Indices of `items` ordered by work, largest first; equal works keep their
+// order (stable LSD radix sort, three 11-bit digits; a comparison sort for
+// works of 2^33 or more).
+template <typename ItemT, typename WorkOf>
+void sort_by_work_desc(const std::vector<ItemT>& items, std::vector<uint32_t>& order, WorkOf work_of) {
+  const size_t n = items.size();
+  order.resize(n);
+  for (size_t i = 0; i < n; ++i) order[i] = (uint32_t)i;
+  int64_t mx = 0;
+  for (const ItemT& it : items) mx = std::max(mx, work_of(it));
+  if (mx >= (int64_t(1) << 33)) {
+    std::stable_sort(order.begin(), order.end(),
+                     [&](uint32_t a, uint32_t b) { return work_of(items[a]) > work_of(items[b]); });
+    return;
+  }
+  std::vector<uint32_t> tmp(n);
+  std::vector<uint32_t> cnt(2049);
+  for (int pass = 0; pass < 3; ++pass) {
+    const int sh = 11 * pass;
+    std::fill(cnt.begin(), cnt.end(), 0u);
+    for (uint32_t i : order) cnt[2047 - ((work_of(items[i]) >> sh) & 2047) + 1] += 1;
+    for (int d = 0; d < 2048; ++d) cnt[d + 1] += cnt[d];
+    for (uint32_t i : order) tmp[cnt[2047 - ((work_of(items[i]) >> sh) & 2047)]++] = i;
+    order.swap(tmp);
+  }
+}
 
 int pool_reserve(taches_pool* p, size_t bytes) {
   if (bytes <= p->tab_cap) return TACHES_OK;
@@ -795,10 +833,14 @@ taches_pool* taches_pool_create(int32_t max_streams, int64_t hbm_budget_bytes, i
   p->device = device;
   if (hipSetDevice(device) != hipSuccess || hipStreamCreateWithFlags(&p->own, hipStreamNonBlocking) != hipSuccess ||
       hipStreamCreateWithFlags(&p->capture, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&p->tab_free, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&p->tab_free, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreate(&p->ev_beg) != hipSuccess || hipEventCreate(&p->ev_end) != hipSuccess) {
     fail(TACHES_EDEVICE, "pool stream/event creation failed");
     if (p->own) (void)hipStreamDestroy(p->own);
     if (p->capture) (void)hipStreamDestroy(p->capture);
+    if (p->tab_free) (void)hipEventDestroy(p->tab_free);
+    if (p->ev_beg) (void)hipEventDestroy(p->ev_beg);
+    if (p->ev_end) (void)hipEventDestroy(p->ev_end);
     delete p;
     return nullptr;
   }
@@ -814,6 +856,8 @@ int taches_pool_destroy(taches_pool* p) {
   (void)hipHostFree(p->tab_pin);
   (void)hipFree(p->tab_dev);
   if (p->tab_free) (void)hipEventDestroy(p->tab_free);
+  if (p->ev_beg) (void)hipEventDestroy(p->ev_beg);
+  if (p->ev_end) (void)hipEventDestroy(p->ev_end);
   (void)hipStreamDestroy(p->own);
   (void)hipStreamDestroy(p->capture);
   delete p;
@@ -891,6 +935,10 @@ int taches_pool_get_info(const taches_pool* p, taches_pool_info* out) {
   out->graph_replays = p->replays;
   out->last_plan_ms = p->last_plan_ms;
   out->last_imbalance = p->last_imbalance;
+  out->last_device_ms = -1.0;
+  float ms = 0.f;
+  if (p->timed && hipEventQuery(p->ev_end) == hipSuccess && hipEventElapsedTime(&ms, p->ev_beg, p->ev_end) == hipSuccess)
+    out->last_device_ms = ms;
   return TACHES_OK;
 }
 
@@ -907,6 +955,7 @@ int taches_pool_step_strided(taches_pool* p, int32_t n, taches_stream* const* st
   if (n == 0) return TACHES_OK;
   const auto t0 = std::chrono::steady_clock::now();
   const uint64_t mark = ++p->steps;
+  p->timed = false;
   for (int i = 0; i < n; ++i) {
     if (!streams[i] || streams[i]->pool != p) return fail(TACHES_EINVAL, "stream %d is not attached to this pool", i);
     if (streams[i]->step_mark == mark) return fail(TACHES_EINVAL, "stream listed twice in one step");
@@ -970,39 +1019,54 @@ int taches_pool_step_strided(taches_pool* p, int32_t n, taches_stream* const* st
     std::vector<int> owner(items.size());
     std::vector<int> count(nwg, 0);
     std::vector<int64_t> load(nwg, 0);
-    if (total_work >= 8 * max_work * (int64_t)nwg) {
+    const size_t n_items = items.size();
+    if (total_work >= 8 * max_work * (int64_t)nwg && n_items >= 16 * (size_t)nwg) {
       // many small items: cut the list, in stream and tile order, into nwg
       // runs of near-equal work (item i goes to the workgroup holding the
-      // middle of its work).  O(n); neighbouring tiles of a stream share
-      // most of their IR window, so a run keeps it in one XCD's L2.  No
-      // workgroup exceeds the mean by more than one item.
+      // middle of its work).  O(n), no sort; no workgroup exceeds the mean
+      // by more than one item, which is at most 1/8 of the mean here.
       int64_t before = 0;
-      for (size_t i = 0; i < items.size(); ++i) {
+      for (size_t i = 0; i < n_items; ++i) {
         const int64_t mid2 = 2 * before + items[i].work;   // twice the item's midpoint
         const int b = (int)std::min<int64_t>(nwg - 1, mid2 * nwg / (2 * total_work));
         owner[i] = b;
-        count[b] += 1;
         load[b] += items[i].work;
         before += items[i].work;
       }
     } else {
-      // largest item first onto the least-loaded workgroup
-      std::vector<size_t> order(items.size());
-      for (size_t i = 0; i < order.size(); ++i) order[i] = i;
-      std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return items[a].work > items[b].work; });
-      std::vector<std::pair<int64_t, int>> heap;
-      heap.reserve(nwg);
-      for (int b = 0; b < nwg; ++b) heap.push_back({0, b});
-      auto cmp = [](const std::pair<int64_t, int>& a, const std::pair<int64_t, int>& b) { return a.first > b.first; };
-      for (size_t i : order) {
-        std::pop_heap(heap.begin(), heap.end(), cmp);
-        heap.back().first += items[i].work;
-        owner[i] = heap.back().second;
-        count[owner[i]] += 1;
-        std::push_heap(heap.begin(), heap.end(), cmp);
+      std::vector<uint32_t> order;
+      sort_by_work_desc(items, order, [](const Item& it) { return it.work; });
+      if (n_items >= 8 * (size_t)nwg) {
+        // largest first, dealt out in serpentine order (0..nwg-1, nwg-1..0, ...)
+        for (size_t k = 0; k < n_items; ++k) {
+          const size_t row = k / nwg, col = k % nwg;
+          const int b = (int)((row & 1) ? nwg - 1 - col : col);
+          owner[order[k]] = b;
+          load[b] += items[order[k]].work;
+        }
+      } else {
+        // largest item first onto the least-loaded workgroup (LPT); the
+        // heap's top takes the item and sinks to its place in one pass
+        std::vector<std::pair<int64_t, int>> heap(nwg);
+        for (int b = 0; b < nwg; ++b) heap[b] = {0, b};
+        for (uint32_t i : order) {
+          heap[0].first += items[i].work;
+          owner[i] = heap[0].second;
+          size_t j = 0;
+          for (;;) {
+            const size_t l = 2 * j + 1, r = l + 1;
+            size_t m = j;
+            if (l < heap.size() && heap[l].first < heap[m].first) m = l;
+            if (r < heap.size() && heap[r].first < heap[m].first) m = r;
+            if (m == j) break;
+            std::swap(heap[j], heap[m]);
+            j = m;
+          }
+        }
+        for (auto& h : heap) load[h.second] = h.first;
       }
-      for (auto& h : heap) load[h.second] = h.first;
     }
+    for (size_t i = 0; i < n_items; ++i) count[owner[i]] += 1;
     int64_t mx = 0, sum = 0;
     for (int b = 0; b < nwg; ++b) {
       mx = std::max(mx, load[b]);
@@ -1042,6 +1106,7 @@ int taches_pool_step_strided(taches_pool* p, int32_t n, taches_stream* const* st
     const auto t1 = std::chrono::steady_clock::now();
     p->last_plan_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
     bool launched = false;
+    HIPCHK(hipEventRecord(p->ev_beg, p->stream));
     if (p->use_graph) {
       // capture [table copy -> batched kernel] once per (tile, workgroups,
       // table capacity); later steps only resize the copy and replay
@@ -1080,6 +1145,8 @@ int taches_pool_step_strided(taches_pool* p, int32_t n, taches_stream* const* st
       hipError_t e = taches::launch_gather_batched(p->tab_dev, nwg, r, p->stream);
       if (e != hipSuccess) return fail(TACHES_EDEVICE, "batched launch: %s", hipGetErrorString(e));
     }
+    HIPCHK(hipEventRecord(p->ev_end, p->stream));
+    p->timed = true;
     HIPCHK(hipEventRecord(p->tab_free, p->stream));
     p->tab_pending = true;
     p->last_items = (int)items.size();

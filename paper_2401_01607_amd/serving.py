@@ -375,6 +375,7 @@ class GpuExecutor:
         self.budget = hbm_budget_bytes
         self.idle_bytes = 0          # recycled streams not attached (counted against the budget)
         self.scratch = torch.empty(1 << 20, device="cuda")
+        self.device_s = 0.0          # device time of the batched launches so far
         # per-handle arrays read by step(); handles are reused after retire
         cap = max_streams
         self.h_stream = np.zeros(cap, np.uint64)
@@ -471,6 +472,9 @@ class GpuExecutor:
         self.pool.step_strided(self.h_stream[handles], xp, np.full(handles.size, self.bank_len, np.int64), yp,
                                np.where(kept, self.h_ycs[handles], 0), n.astype(np.int32))
         self.pool.synchronize()
+        dev = self.pool.info().last_device_ms
+        if dev > 0:
+            self.device_s += dev / 1e3
 
     def retire(self, handle, req):
         s, y, key, _ = self.live.pop(handle)

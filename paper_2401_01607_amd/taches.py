@@ -53,7 +53,8 @@ class taches_pool_info(ctypes.Structure):
                 ("budget_bytes", ctypes.c_int64), ("used_bytes", ctypes.c_int64),
                 ("last_items", ctypes.c_int32), ("last_workgroups", ctypes.c_int32),
                 ("last_r", ctypes.c_int32), ("pad_", ctypes.c_int32), ("graph_replays", ctypes.c_int64),
-                ("last_plan_ms", ctypes.c_double), ("last_imbalance", ctypes.c_double)]
+                ("last_plan_ms", ctypes.c_double), ("last_imbalance", ctypes.c_double),
+                ("last_device_ms", ctypes.c_double)]
 
 
 _vp, _i32, _i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64

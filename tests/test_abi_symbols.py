@@ -48,3 +48,33 @@ def test_config_default_and_bytes_need_no_gpu():
     assert b >= (65536 - 1 + 256) * 4 + 2 * 65536 * 4
     c.max_ir_len = 0
     assert T.taches_bytes_for(c) == -1
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libtaches.so not built")
+def test_binding_structs_match_the_header_layout(tmp_path):
+    """Compile the header with the host C compiler and compare every
+    struct's size and field offsets with the ctypes mirrors."""
+    import shutil
+    import subprocess
+    from paper_2401_01607_amd import taches as T
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    structs = {"taches_config": T.taches_config, "taches_info": T.taches_info,
+               "taches_pool_info": T.taches_pool_info}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "taches.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'  printf("{name} {fname} %zu\\n", offsetof({name}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    for line in filter(None, out):
+        name, field, val = line.split()
+        cls = structs[name]
+        want = ctypes.sizeof(cls) if field == "size" else getattr(cls, field).offset
+        assert int(val) == want, (name, field, int(val), want)
