@@ -158,6 +158,7 @@ def main():
 
     gmacs = macs / dt / 1e9
     flops = 2.0 * macs
+    fma_ceiling = T.taches_fp32_fma_ceiling(0)
     achieved_tflops = flops / k_avg_s / 1e12
 
     # ---- per-block latency, host-synchronous streaming call ----------------
@@ -219,6 +220,10 @@ def main():
             "traffic": measured_traffic_bytes(f"k_gather<{main_tile[0]},{main_tile[1]},float>"),
             "kernel_ms": round(k_avg_s * 1e3, 4),
             "flops_per_launch": flops,
+            # the unpacked-FMA issue ceiling measured on this device (the
+            # library is built without packed FP32, which the peak counts)
+            "fma_ceiling_tflops": round(fma_ceiling, 1),
+            "frac_of_fma_ceiling": round(achieved_tflops / fma_ceiling, 4) if fma_ceiling > 0 else None,
         },
         "block_latency_us": {
             "mode": "host-synchronous taches_process, host buffers, B=256, L=65536",

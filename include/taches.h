@@ -255,6 +255,15 @@ typedef struct taches_pool_info {
 
 int taches_pool_get_info(const taches_pool* p, taches_pool_info* out);
 
+/* ---- diagnostics -----------------------------------------------------------
+ *
+ * FP32 fused-multiply-add rate (TFLOP/s, 2 FLOP per FMA) that independent
+ * unpacked v_fmac_f32 chains reach on `device`, with no memory traffic: the
+ * issue ceiling of the FP32 gather kernels, which are built without packed
+ * FP32 instructions (the published vector peak counts packed FP32).  Runs
+ * for about 20 ms.  TACHES_EDEVICE on a HIP error. */
+int taches_fp32_fma_ceiling(int32_t device, double* tflops_out);
+
 #ifdef __cplusplus
 }
 #endif

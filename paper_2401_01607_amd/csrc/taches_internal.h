@@ -88,4 +88,8 @@ hipError_t launch_toeplitz(const GatherCall& call, bool tail_fp64, hipStream_t s
 bool split_supported(const taches_config& cfg);
 int split_cpad(int channels);
 
+// FP32 FMA issue ceiling of the device (k_diag.hip): TFLOP/s reached by
+// independent v_fmac_f32 chains.
+hipError_t measure_fmac_ceiling(int device, double* tflops);
+
 }  // namespace taches

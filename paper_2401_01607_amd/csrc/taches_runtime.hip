@@ -942,6 +942,13 @@ int taches_pool_get_info(const taches_pool* p, taches_pool_info* out) {
   return TACHES_OK;
 }
 
+int taches_fp32_fma_ceiling(int32_t device, double* tflops_out) {
+  if (!tflops_out) return fail(TACHES_EINVAL, "NULL argument");
+  hipError_t e = taches::measure_fmac_ceiling(device, tflops_out);
+  if (e != hipSuccess) return fail(TACHES_EDEVICE, "fma ceiling: %s", hipGetErrorString(e));
+  return TACHES_OK;
+}
+
 int taches_pool_step(taches_pool* p, int32_t n, taches_stream* const* streams, const float* const* x_dev,
                      float* const* y_dev, const int32_t* n_blocks) {
   return taches_pool_step_strided(p, n, streams, x_dev, nullptr, y_dev, nullptr, n_blocks);

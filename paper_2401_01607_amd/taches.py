@@ -89,6 +89,7 @@ _SIGS = {
     "taches_pool_use_graph": (ctypes.c_int, [_vp, _i32]),
     "taches_pool_synchronize": (ctypes.c_int, [_vp]),
     "taches_pool_get_info": (ctypes.c_int, [_vp, _P(taches_pool_info)]),
+    "taches_fp32_fma_ceiling": (ctypes.c_int, [_i32, _P(ctypes.c_double)]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(lib, _name)
@@ -267,6 +268,13 @@ def taches_pool_step_strided(p, streams, x_ptrs, x_cstride, y_ptrs, y_cstride, n
     if keep[0][0] is None or keep[3][0] is None:
         raise ValueError("streams and y_ptrs are required")
     return lib.taches_pool_step_strided(p, n, *[k[1] for k in keep])
+
+
+def taches_fp32_fma_ceiling(device: int = 0) -> float:
+    """TFLOP/s of unpacked FP32 FMA chains on the device (see the header)."""
+    v = ctypes.c_double()
+    _check(lib.taches_fp32_fma_ceiling(device, ctypes.byref(v)), "taches_fp32_fma_ceiling")
+    return v.value
 
 
 def taches_pool_set_hip_stream(p, stream: int) -> int:

@@ -78,3 +78,9 @@ def test_close_reopen_many_times():
         s.set_ir(np.ones(2048, np.float32))
         s.process(np.ones(64, np.float32))
         s.close()
+
+
+def test_fp32_fma_ceiling_is_positive_and_below_the_packed_peak():
+    from paper_2401_01607_amd import taches as T
+    v = T.taches_fp32_fma_ceiling(0)
+    assert 1.0 < v < 2 * 157.3
