@@ -280,7 +280,9 @@ __device__ __forceinline__ void chunk_store(const ChunkGeo& g, int lane, const P
 
 // One output tile of one channel of one call.  W waves share the tile; wave
 // w handles chunks w, w+W, ... of each round and the partial sums are added
-// to the accumulators in chunk order after every round.
+// to the accumulators in chunk order after every round.  Each wave keeps the
+// accumulators of R/W of a lane's R outputs (outputs w*R/W .. (w+1)*R/W - 1)
+// and adds only those partial sums, then writes those outputs.
 template <int R, int W, typename TailT>
 __device__ __forceinline__ void gather_tile(const GatherCall& d, int c, int tile) {
   constexpr int T = Geo<R>::T;
@@ -291,20 +293,22 @@ __device__ __forceinline__ void gather_tile(const GatherCall& d, int c, int tile
   const int pbuf = W * Geo<R>::WF;         // [W][64][R], used when W > 1
 
   const int n0 = tile * T;
-  const int nb = n0 + lane * R;
+  constexpr int Q = R / W;                 // accumulators this wave owns per lane
+  static_assert(Q * W == R, "W must divide R");
+  const int nq = n0 + lane * R + w * Q;    // the first of them
   TailT* ring = reinterpret_cast<TailT*>(d.ring) + (int64_t)c * d.ring_cstride;
 
-  TailT acc[R];
+  TailT acc[Q];
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const int n = nb + r;
+  for (int q = 0; q < Q; ++q) {
+    const int n = nq + q;
     TailT v = 0;
     if (n < d.live_in) {
       int slot = d.head + n;
       if (slot >= d.Rcap) slot -= d.Rcap;
       v = ring[slot];
     }
-    acc[r] = v;
+    acc[q] = v;
   }
 
   if (d.x != nullptr) {
@@ -379,14 +383,19 @@ __device__ __forceinline__ void gather_tile(const GatherCall& d, int c, int tile
         __syncthreads();
         const int nv = min(W, nch - base);
         for (int v = 0; v < nv; ++v) {
-          const int src = pbuf + (v * 64 + lane) * R;
+          const int src = pbuf + (v * 64 + lane) * R + w * Q;
+          if constexpr (Q % 4 == 0) {
 #pragma unroll
-          for (int r = 0; r < R; r += 4) {
-            const vf4 q = lds_read4(src + r);
-            acc[r] += (TailT)q.x;
-            acc[r + 1] += (TailT)q.y;
-            acc[r + 2] += (TailT)q.z;
-            acc[r + 3] += (TailT)q.w;
+            for (int q = 0; q < Q; q += 4) {
+              const vf4 t = lds_read4(src + q);
+              acc[q] += (TailT)t.x;
+              acc[q + 1] += (TailT)t.y;
+              acc[q + 2] += (TailT)t.z;
+              acc[q + 3] += (TailT)t.w;
+            }
+          } else {
+#pragma unroll
+            for (int q = 0; q < Q; ++q) acc[q] += (TailT)g_lds[src + q];
           }
         }
         __syncthreads();
@@ -395,19 +404,19 @@ __device__ __forceinline__ void gather_tile(const GatherCall& d, int c, int tile
     }
   }
 
-  if (w == 0) {
+  {
     float* yc = d.y + (int64_t)c * d.y_cstride;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int n = nb + r;
+    for (int q = 0; q < Q; ++q) {
+      const int n = nq + q;
       if (n < d.n_out) {
         int slot = d.head + n;
         if (slot >= d.Rcap) slot -= d.Rcap;
         if (n < d.S) {
-          yc[n] = (float)acc[r];
+          yc[n] = (float)acc[q];
           ring[slot] = (TailT)0;
         } else {
-          ring[slot] = acc[r];
+          ring[slot] = acc[q];
         }
       }
     }
