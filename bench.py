@@ -74,7 +74,7 @@ def parse():
                    help="only run a plain device copy of MB megabytes (HBM counter calibration)")
     p.add_argument("--no-extras", action="store_true",
                    help="skip the multichannel, batched and latency comparisons")
-    p.add_argument("--only", type=str, default="", help="run one extra section only (c1, c3, c4, c5)")
+    p.add_argument("--only", type=str, default="", help="run one extra section only (c1, c3, c4, c5, f4; f3 runs only when named)")
     p.add_argument("--device-warmup-s", type=float, default=1.5,
                    help="seconds of untimed steps before the warm-up steps (device clock ramp)")
     return p.parse_args()
@@ -452,10 +452,129 @@ def extra_c5_serving(duration_s=30.0, warmup_s=10.0):
     return st
 
 
+def extra_f4_zero_bypass():
+    """The main step's stream with every other 4 800-sample period silent
+    (exact zeros): chunks of zeros skip their multiply-adds (exact-zero
+    bypass).  Same call as the main step, timed with HIP events."""
+    import torch
+    from paper_2401_01607_amd import taches as T
+    from paper_2401_01607_amd import workloads as W
+    spec = W.config2()
+    B, L = spec.block, spec.max_ir_len
+    nb = spec.n_blocks()
+    sched = np.full(nb, -1, np.int32)
+    for b, k in spec.schedule:
+        sched[b] = k
+    full = np.zeros(nb * B, np.float32)
+    full[:spec.n_samples] = spec.x[0]
+    quiet = full.copy()
+    for p0 in range(4800, quiet.size, 9600):
+        quiet[p0:p0 + 4800] = 0
+    zero_blocks = int(sum(not quiet[b * B:(b + 1) * B].any() for b in range(nb)))
+    irs = [torch.from_numpy(h).cuda() for h in spec.irs]
+    res = {"workload": "main-step stream, every other 4800-sample period silent",
+           "silent_blocks": zero_blocks, "blocks": nb}
+    for name, xp in (("full", full), ("half_silent", quiet)):
+        x = torch.from_numpy(xp).cuda()[None]
+        y = torch.empty_like(x)
+        s = T.Stream(B, L, max_blocks_per_call=nb, ir_slots=2)
+        for k in range(2):
+            s.load_ir_slot(k, irs[k])
+        ts = []
+        for rep in range(8):
+            s.reset()
+            for k in range(2):
+                s.load_ir_slot(k, irs[k])
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            s.process_blocks(x, y, nb, sched)
+            e1.record()
+            torch.cuda.synchronize()
+            if rep >= 2:
+                ts.append(e0.elapsed_time(e1))
+        s.close()
+        res[name + "_ms"] = round(float(np.median(ts)), 4)
+    res["speedup"] = round(res["full_ms"] / res["half_silent_ms"], 2)
+    return res
+
+
+def extra_f3_capacity():
+    """Real-time capacity on one GPU, the counterpart of the paper's
+    real-time limit filter length (Section 5.1, Figs. 7-13; Table 2).
+    A: one mono stream, host-synchronous taches_process per block (host
+    buffers, PCIe round trip included): per-block time against the block
+    period B/fs for growing L; the longest real-time L is extrapolated
+    linearly from the longest L measured.  B: pools of N identical mono
+    streams advancing one block each per step (one batched launch, graph
+    replay): step time against the block period; the real-time stream count
+    is extrapolated linearly from the largest N."""
+    import torch
+    from paper_2401_01607_amd import taches as T
+    from paper_2401_01607_amd import workloads as W
+    fs = float(W.FS)
+    out = {"single_stream": [], "pool": []}
+    for B in (256, 8192):
+        for L in (1 << 16, 1 << 18, 1 << 20, 1 << 22):
+            s = T.Stream(B, L)
+            s.set_ir(W.impulse_response(L, 700 + L % 97))
+            x = W.signal_gauss(B, 701)[None]
+            y = np.zeros_like(x)
+            ts = []
+            for k in range(25):
+                t0 = time.perf_counter()
+                assert T.taches_process(s.h, x, y) == 0
+                ts.append(time.perf_counter() - t0)
+            s.close()
+            t = float(np.median(ts[5:]))
+            out["single_stream"].append({"B": B, "L": L, "ms_per_block": round(t * 1e3, 4),
+                                         "period_ms": round(B / fs * 1e3, 3), "real_time": t < B / fs,
+                                         "gmacs": round(B * L / t / 1e9, 1)})
+        last = out["single_stream"][-1]
+        out["single_stream_max_L_estimate_B%d" % B] = int(last["L"] * (B / fs) / (last["ms_per_block"] / 1e3))
+    for L, B in ((4096, 256), (65536, 256), (262144, 1024)):
+        h = torch.from_numpy(W.impulse_response(L, 702)).cuda()
+        xbank = torch.from_numpy(W.signal_gauss(B * 8192, 703)).cuda()
+        for N in (256, 1024, 4096):
+            pool = T.Pool(N, 1 << 42, use_graph=True)
+            ss = []
+            for i in range(N):
+                st = T.Stream(B, L)
+                st.set_ir(h)
+                assert pool.attach(st) == T.TACHES_OK
+                ss.append(st)
+            sp = np.array([st.h for st in ss], np.uint64)
+            xp = np.array([xbank.data_ptr() + 4 * B * (i % 8192) for i in range(N)], np.uint64)
+            ybuf = torch.empty(N * B, device="cuda")
+            yp = np.array([ybuf.data_ptr() + 4 * B * i for i in range(N)], np.uint64)
+            nbs = np.ones(N, np.int32)
+            ts, dev = [], []
+            for k in range(13):
+                t0 = time.perf_counter()
+                pool.step_strided(sp, xp, None, yp, None, nbs)
+                pool.synchronize()
+                if k >= 3:
+                    ts.append(time.perf_counter() - t0)
+                    dev.append(pool.info().last_device_ms)
+            for st in ss:
+                pool.detach(st)
+                st.close()
+            pool.close()
+            t = float(np.median(ts))
+            out["pool"].append({"L": L, "B": B, "streams": N, "step_ms": round(t * 1e3, 3),
+                                "device_ms": round(float(np.median(dev)), 3), "period_ms": round(B / fs * 1e3, 3),
+                                "real_time": t < B / fs, "gmacs": round(N * B * L / t / 1e9, 1)})
+        last = out["pool"][-1]
+        out["pool_max_streams_estimate_L%d_B%d" % (L, B)] = int(last["streams"] * (B / fs) /
+                                                                 (last["step_ms"] / 1e3))
+    return out
+
+
 def extras(args):
     out = {}
     sections = {"c1": extra_c1_latency, "c3": extra_c3_split_vs_fp32, "c4": extra_c4_batched_vs_plain,
-                "c5": extra_c5_serving}
+                "c5": extra_c5_serving, "f4": extra_f4_zero_bypass}
+    if args.only == "f3":
+        sections = {"f3": extra_f3_capacity}     # on request only: about a minute
     for name, fn in sections.items():
         if args.only and args.only != name:
             continue

@@ -147,6 +147,7 @@ struct ChunkGeo {
   int ck, nsub;
   BlockIR ir;
   bool reaches;
+  uint32_t nz;     // bit j: block j of the unit (or the single chunk, bit 0) has a nonzero sample
 };
 
 template <int R>
@@ -163,6 +164,7 @@ __device__ __forceinline__ ChunkGeo chunk_geo(const GatherCall& d, int ck, int n
   g.reaches = g.len > 0 && g.m_lo <= n0 + Geo<R>::T - 1 && m_hi + g.ir.L - 2 >= n0;
   g.ck = ck;
   g.nsub = 1;
+  g.nz = ~0u;
   return g;
 }
 
@@ -180,6 +182,7 @@ __device__ __forceinline__ ChunkGeo unit_geo(const GatherCall& d, int ck, int ck
     g.ck = ck;
     g.nsub = 0;
     g.reaches = false;
+    g.nz = 0u;
     return g;
   }
   if (kmax == 1) return chunk_geo<R>(d, ck, n0);
@@ -196,6 +199,7 @@ __device__ __forceinline__ ChunkGeo unit_geo(const GatherCall& d, int ck, int ck
   }
   g.ck = ck;
   g.nsub = e - ck;
+  g.nz = ~0u;
   g.m_lo = ck * d.B;
   g.len = g.nsub * d.B;
   g.len_pad = g.len;
@@ -256,6 +260,32 @@ __device__ __forceinline__ void chunk_load(const ChunkGeo& g, const float* __res
     const int s = lane + 64 * k;
     pf.xv[k] = s < g.len ? xc[g.m_lo + s] : 0.f;
   }
+}
+
+// Exact-zero bypass (the paper skips the tache of a zero input sample,
+// Section 3.2): while its samples are stored, the wave records which blocks
+// of the unit hold a nonzero sample.  A chunk of zeros adds only zero
+// products, so skipping its multiply-adds and its addition to the tail
+// leaves every output unchanged (up to the sign of an exact zero).
+template <int R>
+__device__ __forceinline__ uint32_t nonzero_blocks(const ChunkGeo& g, int lane, const Prefetch<R>& pf, int B) {
+  if (g.nsub <= 1) {
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < Prefetch<R>::XPL; ++k) any |= (lane + 64 * k < g.len) && pf.xv[k] != 0.f;
+    return __any(any) ? 1u : 0u;
+  }
+  uint32_t m = 0;
+  for (int j = 0; j < g.nsub; ++j) {
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < Prefetch<R>::XPL; ++k) {
+      const int s = lane + 64 * k;
+      any |= s >= j * B && s < (j + 1) * B && pf.xv[k] != 0.f;
+    }
+    if (__any(any)) m |= 1u << j;
+  }
+  return m;
 }
 
 template <int R>
@@ -329,6 +359,7 @@ __device__ __forceinline__ void gather_tile(const GatherCall& d, int c, int tile
       ChunkGeo gc = unit_geo<R>(d, c_first, c_end, kmax, n0);
       if (gc.reaches) {
         chunk_load<R>(gc, xc, n0, lane, pf);
+        gc.nz = nonzero_blocks<R>(gc, lane, pf, d.B);
         chunk_store<R>(gc, lane, pf, hs, xs);
       }
       ChunkGeo gn = unit_geo<R>(d, gc.ck + gc.nsub, c_end, kmax, n0);
@@ -341,6 +372,7 @@ __device__ __forceinline__ void gather_tile(const GatherCall& d, int c, int tile
           for (int j = 0; j < gc.nsub; ++j) {
             const int m0 = gc.m_lo + j * d.B;
             if (gc.nsub > 1 && !(m0 <= n0 + T - 1 && m0 + d.B + L - 2 >= n0)) continue;
+            if (!((gc.nz >> j) & 1u)) continue;
             float p[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) p[r] = 0.f;
@@ -349,7 +381,10 @@ __device__ __forceinline__ void gather_tile(const GatherCall& d, int c, int tile
             for (int r = 0; r < R; ++r) acc[r] += (TailT)p[r];
           }
         }
-        if (gn.reaches) chunk_store<R>(gn, lane, pf, hs, xs);
+        if (gn.reaches) {
+          gn.nz = nonzero_blocks<R>(gn, lane, pf, d.B);
+          chunk_store<R>(gn, lane, pf, hs, xs);
+        }
         gc = gn;
         gn = unit_geo<R>(d, gc.ck + gc.nsub, c_end, kmax, n0);
         if (gn.reaches) chunk_load<R>(gn, xc, n0, lane, pf);
@@ -362,6 +397,7 @@ __device__ __forceinline__ void gather_tile(const GatherCall& d, int c, int tile
     if (w < nch) gc = chunk_geo<R>(d, c_first + w, n0);
     if (gc.reaches) {
       chunk_load<R>(gc, xc, n0, lane, pf);
+      gc.nz = nonzero_blocks<R>(gc, lane, pf, d.B);
       chunk_store<R>(gc, lane, pf, hs, xs);
     }
     if (w + W < nch) gn = chunk_geo<R>(d, c_first + w + W, n0);
@@ -370,8 +406,11 @@ __device__ __forceinline__ void gather_tile(const GatherCall& d, int c, int tile
       float p[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) p[r] = 0.f;
-      if (gc.reaches) chunk_compute<R>(hs, xs, lane, gc.len_pad / R, 0, gc.len_pad / R, p);
-      if (gn.reaches) chunk_store<R>(gn, lane, pf, hs, xs);
+      if (gc.reaches && gc.nz) chunk_compute<R>(hs, xs, lane, gc.len_pad / R, 0, gc.len_pad / R, p);
+      if (gn.reaches) {
+        gn.nz = nonzero_blocks<R>(gn, lane, pf, d.B);
+        chunk_store<R>(gn, lane, pf, hs, xs);
+      }
       gc = gn;
       gn.reaches = false;
       if (base + 2 * W + w < nch) gn = chunk_geo<R>(d, c_first + base + 2 * W + w, n0);
@@ -437,8 +476,9 @@ __global__ __launch_bounds__(64 * W) void k_gather(GatherCall d, int n_tiles) {
 
 // Batched: one packed table (header, call descriptors, per-call tail type,
 // per-workgroup item ranges, work items).  Workgroup b walks items
-// [wg_begin[b], wg_begin[b+1]) of a host-built list (largest items first,
-// balanced over workgroups); each call's tail type is chosen per stream.
+// [wg_begin[b], wg_begin[b+1]) of a host-built list (balanced over
+// workgroups), each item a run of consecutive output tiles of one channel of
+// one call; each call's tail type is chosen per stream.
 template <int R>
 __global__ __launch_bounds__(64) void k_gather_batched(const unsigned char* __restrict__ table) {
   const BatchHeader hd = *reinterpret_cast<const BatchHeader*>(table);
@@ -451,11 +491,14 @@ __global__ __launch_bounds__(64) void k_gather_batched(const unsigned char* __re
   for (int it = it0; it < it1; ++it) {
     const WorkItem wi = items[it];
     const GatherCall d = calls[wi.call];
-    if (call_fp64[wi.call])
-      gather_tile<R, 1, double>(d, wi.channel, wi.tile);
-    else
-      gather_tile<R, 1, float>(d, wi.channel, wi.tile);
-    __syncthreads();
+    const bool f64 = call_fp64[wi.call] != 0;
+    for (int t = wi.tile; t < wi.tile + wi.count; ++t) {
+      if (f64)
+        gather_tile<R, 1, double>(d, wi.channel, t);
+      else
+        gather_tile<R, 1, float>(d, wi.channel, t);
+      __syncthreads();
+    }
   }
 }
 

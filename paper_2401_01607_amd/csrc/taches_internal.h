@@ -55,12 +55,13 @@ struct GatherCall {
   int32_t tile_order;    // gather path: 0 = XCD-grouped, 1 = center-out, 2 = launch order
 };
 
-// One unit of batched work: an output tile of one channel of one call.
+// One unit of batched work: output tiles tile .. tile+count-1 of one channel
+// of one call.
 struct WorkItem {
   int32_t call;    // index into the GatherCall table
   int32_t channel;
-  int32_t tile;    // output tile index (tile size fixed by the kernel's R)
-  int32_t pad_;
+  int32_t tile;    // first output tile (tile size fixed by the kernel's R)
+  int32_t count;   // number of consecutive tiles
 };
 
 // Kernel launchers (k_gather.hip).  r in {4, 8, 12, 16}, w in {1, 2, 4}.

@@ -990,31 +990,65 @@ int taches_pool_step_strided(taches_pool* p, int32_t n, taches_stream* const* st
   if (!gather_ids.empty()) {
     const int r = pool_pick_r(p, gcalls);
     const int64_t T = 64 * r;
-    // work items: (call, channel, tile) with their FMA count
+    // work items: runs of consecutive output tiles of one channel of one
+    // call, with their FMA count (plus the tail read/write)
     struct Item {
       WorkItem w;
       int64_t work;
     };
-    std::vector<Item> items;
     const int ng = (int)gather_ids.size();
+    auto tile_work = [T](const GatherCall& g, int64_t t) {
+      const int64_t n0 = t * T;
+      int64_t work = 4 * T;
+      if (g.x) {
+        const int64_t lo = std::max<int64_t>(0, n0 - (g.Lmax_call - 1));
+        const int64_t hi = std::min<int64_t>(g.S, n0 + T);
+        work += std::max<int64_t>(hi - lo, 0) * T;
+      }
+      return work;
+    };
+    const int per_cu = taches::gather_batched_waves_per_cu(r);
+    const int64_t wg_max = 256LL * per_cu;
+    int64_t n_tiles = 0, tiles_work = 0, tile_max = 1;
     for (int k = 0; k < ng; ++k) {
       const GatherCall& g = plans[gather_ids[k]].g;
       const int64_t nt = (g.n_out + T - 1) / T;
-      for (int c = 0; c < g.channels; ++c)
-        for (int64_t t = 0; t < nt; ++t) {
-          const int64_t n0 = t * T;
-          int64_t work = 4 * T;  // tail read/write
-          if (g.x) {
-            const int64_t lo = std::max<int64_t>(0, n0 - (g.Lmax_call - 1));
-            const int64_t hi = std::min<int64_t>(g.S, n0 + T);
-            work += std::max<int64_t>(hi - lo, 0) * T;
+      n_tiles += nt * g.channels;
+      for (int64_t t = 0; t < nt; ++t) {
+        const int64_t w = tile_work(g, t);
+        tiles_work += w * g.channels;
+        tile_max = std::max(tile_max, w);
+      }
+    }
+    // With very many small tiles (a step of one or a few blocks per stream
+    // touches every tail slot of every stream), consecutive tiles are merged
+    // into items of about 1/16 of a workgroup's share, so the table and its
+    // planning shrink; otherwise one item per tile.
+    const int64_t span_work = n_tiles > 64 * wg_max ? std::max(tile_max, tiles_work / (16 * wg_max)) : 0;
+    std::vector<Item> items;
+    items.reserve(span_work ? (size_t)(tiles_work / span_work + ng * 2 + 16) : (size_t)n_tiles);
+    for (int k = 0; k < ng; ++k) {
+      const GatherCall& g = plans[gather_ids[k]].g;
+      const int64_t nt = (g.n_out + T - 1) / T;
+      for (int c = 0; c < g.channels; ++c) {
+        int64_t t = 0;
+        while (t < nt) {
+          int64_t t1 = t + 1, w = tile_work(g, t);
+          if (span_work) {
+            while (t1 < nt && t1 - t < 65535) {
+              const int64_t w1 = tile_work(g, t1);
+              if (w + w1 > span_work) break;
+              w += w1;
+              ++t1;
+            }
           }
-          items.push_back({WorkItem{k, c, (int32_t)t, 0}, work});
+          items.push_back({WorkItem{k, c, (int32_t)t, (int32_t)(t1 - t)}, w});
+          t = t1;
         }
+      }
     }
     // persistent workgroups (one wave each): as many as stay resident, but
     // no more than leave each at least the largest item's work
-    const int per_cu = taches::gather_batched_waves_per_cu(r);
     int64_t total_work = 0, max_work = 1;
     for (const Item& it : items) {
       total_work += it.work;

@@ -264,3 +264,53 @@ def test_short_blocks_staged_together_bitwise(B, r):
     assert np.array_equal(y1, y2)
     assert np.array_equal(y1, yb)
     assert rel_err(y1, oracle_run(x, irs, sched, B, L2, nb)) <= TOL
+
+
+def _silence(x, B, seed):
+    """Zero about 40 % of the blocks, plus one run of several blocks."""
+    x = x.copy()
+    nb = -(-x.size // B)
+    rng = np.random.default_rng(seed)
+    for b in np.nonzero(rng.random(nb) < 0.4)[0]:
+        x[b * B:(b + 1) * B] = 0
+    x[3 * B:min(x.size, 9 * B + B // 2)] = 0
+    return x
+
+
+@pytest.mark.parametrize("B", (32, 64, 256, 300))
+@pytest.mark.parametrize("tile", [(16, 1), (16, 4), (4, 1), (12, 2)])
+def test_zero_blocks_are_bypassed_exactly(B, tile):
+    """Chunks whose samples are all zero skip their multiply-adds and their
+    addition to the tail (exact-zero bypass); outputs stay exact."""
+    L1, L2 = 900, 2100
+    n = 40 * B
+    nb = -(-(n + L2) // B) + 1
+    sched = [(0, 0), (7, 1), (20, 0), (21, 1)]
+    xi = _silence(W.signal_int(n, 81, 31), B, 82)
+    irs_i = [W.signal_int(L1, 83, 31), W.signal_int(L2, 84, 31)]
+    ref = oracle_run(xi, irs_i, sched, B, L2, nb)
+    yi, _ = gpu_multi_block(xi, irs_i, sched, B, L2, nb, tile=tile)
+    assert np.array_equal(yi, ref)
+    yb, _ = gpu_per_block(xi, irs_i, sched, B, L2, nb, tile=tile)
+    assert np.array_equal(yb, ref)
+    x = _silence(W.signal_gauss(n, 85), B, 86)
+    irs = [W.impulse_response(L1, 87), W.impulse_response(L2, 88)]
+    y, _ = gpu_multi_block(x, irs, sched, B, L2, nb, tile=tile)
+    assert rel_err(y, oracle_run(x, irs, sched, B, L2, nb)) <= TOL
+    y4, _ = gpu_multi_block(x, irs, sched, B, L2, nb, tile=(tile[0], 4))
+    assert np.array_equal(y, y4)
+
+
+def test_all_zero_input_gives_exact_zeros_and_keeps_the_tail():
+    """A silent block after a sound one: the tail keeps ringing exactly as
+    the oracle says, and an all-zero stream outputs exact zeros."""
+    B, L = 64, 3000
+    x = np.zeros(30 * B, np.float32)
+    nb = -(-(x.size + L) // B)
+    y, _ = gpu_multi_block(x, [W.impulse_response(L, 89)], [(0, 0)], B, L, nb)
+    assert not np.any(y)
+    x[5 * B + 7] = 1.0
+    h = W.impulse_response(L, 90)
+    y, _ = gpu_per_block(x, [h], [(0, 0)], B, L, nb)
+    d = 5 * B + 7
+    assert np.array_equal(y[0, d:d + L], h) and not np.any(y[0, :d]) and not np.any(y[0, d + L:])

@@ -308,3 +308,44 @@ def test_strided_step_rejects_short_channel_stride():
     assert s.info().blocks_done == 4
     pool.close()
     s.close()
+
+
+def test_many_tiles_are_merged_into_range_items_exactly():
+    """1024 streams x L = 131072 advancing one block per step: over 10^5
+    output tiles per step, merged into items of consecutive tiles; sampled
+    streams equal their solo runs bit for bit."""
+    import torch
+    T = binding()
+    N, B, L, steps = 1024, 64, 131072, 3
+    h = torch.from_numpy(W.impulse_response(L, 91)).cuda()
+    xbank = torch.from_numpy(W.signal_gauss(N * steps * B, 92)).cuda()
+    pool = T.Pool(N, 64 * GB, use_graph=True, tile_r=16)
+    ss = []
+    for i in range(N):
+        s = T.Stream(B, L)
+        s.set_ir(h)
+        assert pool.attach(s) == T.TACHES_OK
+        ss.append(s)
+    ys = torch.empty((steps, N, B), device="cuda")
+    sp = np.array([s.h for s in ss], np.uint64)
+    for k in range(steps):
+        xp = np.array([xbank.data_ptr() + 4 * B * (i * steps + k) for i in range(N)], np.uint64)
+        yp = np.array([ys[k, i].data_ptr() for i in range(N)], np.uint64)
+        pool.step_strided(sp, xp, None, yp, None, np.ones(N, np.int32))
+    pool.synchronize()
+    info = pool.info()
+    tiles = N * -(-(B + L - 1) // (64 * info.last_r))
+    assert 0 < info.last_items <= tiles // 3
+    for i in range(0, N, 67):
+        s = T.Stream(B, L)
+        s.set_ir(h)
+        y = torch.empty((steps, B), device="cuda")
+        for k in range(steps):
+            s.process_async(xbank[B * (i * steps + k):B * (i * steps + k + 1)], y[k])
+        s.synchronize()
+        assert torch.equal(y, ys[:, i]), f"stream {i}"
+        s.close()
+    for s in ss:
+        pool.detach(s)
+        s.close()
+    pool.close()
