@@ -20,7 +20,9 @@ Four forms of the same computation:
 
 Block-IR semantics everywhere: the IR used for the tache of input sample m is
 the one active for the block that holds m (the last one set before that
-block); taches keep the IR that produced them.
+block); taches keep the IR that produced them.  A schedule entry
+(block, ir, offset) sets the IR from sample ``offset`` of that block on
+(sample-accurate swap); (block, ir) means offset 0.
 """
 from __future__ import annotations
 
@@ -64,12 +66,14 @@ def lib():
         L.or_close.argtypes = [vp]
         L.or_set_ir.restype = i32
         L.or_set_ir.argtypes = [vp, vp, i32]
+        L.or_set_ir_at.restype = i32
+        L.or_set_ir_at.argtypes = [vp, vp, i32, i32]
         L.or_process.restype = i32
         L.or_process.argtypes = [vp, vp, vp]
         L.or_get_residue.restype = i32
         L.or_get_residue.argtypes = [vp, i32, vp]
         L.or_run_channel.restype = i32
-        L.or_run_channel.argtypes = [i32, i32, i32, vp, i64, i32, vp, vp, vp, vp]
+        L.or_run_channel.argtypes = [i32, i32, i32, vp, i64, i32, vp, vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -88,9 +92,10 @@ class OracleStream:
         if not self._h:
             raise ValueError("or_open failed")
 
-    def set_ir(self, h: np.ndarray) -> int:
+    def set_ir(self, h: np.ndarray, offset: int = 0) -> int:
+        """Queue h; it applies from sample ``offset`` of the next block."""
         h = np.ascontiguousarray(h, dtype=np.float32)
-        return lib().or_set_ir(self._h, _ptr(h), int(h.size))
+        return lib().or_set_ir_at(self._h, _ptr(h), int(h.size), int(offset))
 
     def process(self, x: np.ndarray):
         x = np.ascontiguousarray(np.asarray(x, dtype=np.float32).reshape(self.C, self.B))
@@ -115,13 +120,32 @@ class OracleStream:
             pass
 
 
-def _schedule_array(n_blocks: int, schedule) -> np.ndarray:
-    """ir_of_block[b] = IR index set before block b, -1 = no change."""
+def _entry(e):
+    """Schedule entry -> (block, ir, offset)."""
+    return (int(e[0]), int(e[1]), int(e[2]) if len(e) > 2 else 0)
+
+
+def _schedule_arrays(n_blocks: int, schedule):
+    """ir_of_block[b] = IR index set before block b (-1 = no change) and the
+    sample of block b it takes over at."""
     a = np.full(n_blocks, -1, dtype=np.int32)
-    for b, k in schedule:
+    off = np.zeros(n_blocks, dtype=np.int32)
+    for e in schedule:
+        b, k, o = _entry(e)
         if 0 <= b < n_blocks:
-            a[b] = k
-    return a
+            a[b], off[b] = k, o
+    return a, off
+
+
+def ir_of_sample(n_samples: int, schedule, block: int) -> np.ndarray:
+    """Index of the IR whose tache input sample m gets (-1 = none yet): the
+    schedule entry with the latest start b*B + offset at or before m."""
+    starts = sorted((b * block + o, k) for b, k, o in map(_entry, schedule))
+    out = np.full(n_samples, -1, dtype=np.int64)
+    for pos, k in starts:
+        if pos < n_samples:
+            out[pos:] = k
+    return out
 
 
 def run_channel(x: np.ndarray, irs, schedule, block: int, max_ir_len: int,
@@ -135,10 +159,10 @@ def run_channel(x: np.ndarray, irs, schedule, block: int, max_ir_len: int,
     irs32 = [np.ascontiguousarray(h, dtype=np.float32) for h in irs]
     ptrs = (ctypes.c_void_p * len(irs32))(*[h.ctypes.data for h in irs32])
     lens = np.array([h.size for h in irs32], dtype=np.int32)
-    sched = _schedule_array(n_blocks, schedule)
+    sched, offs = _schedule_arrays(n_blocks, schedule)
     y = np.zeros(n_blocks * block, dtype=np.float64)
     rc = lib().or_run_channel(block, max_ir_len, prec, _ptr(x), x.size, n_blocks,
-                              ctypes.cast(ptrs, ctypes.c_void_p), _ptr(lens), _ptr(sched), _ptr(y))
+                              ctypes.cast(ptrs, ctypes.c_void_p), _ptr(lens), _ptr(sched), _ptr(offs), _ptr(y))
     if rc != OR_OK:
         raise RuntimeError(f"oracle rc={rc}")
     return y
@@ -192,26 +216,19 @@ def _exact(v):
 
 
 def brute_force(x: np.ndarray, irs, schedule, block: int, n_out: int):
-    """y[n] = sum over m <= n of x[m] * h_{b(m)}[n - m], exactly.
+    """y[n] = sum over m <= n of x[m] * h_(IR of sample m)[n - m], exactly.
 
-    ``schedule``: list of (block, ir_index) pairs, as for the streaming calls.
-    Returns a list of exact numbers (int or Fraction)."""
+    ``schedule``: list of (block, ir_index[, offset]) entries, as for the
+    streaming calls.  Returns a list of exact numbers (int or Fraction)."""
     x = [_exact(v) for v in np.asarray(x, dtype=np.float32)]
     irs_e = [[_exact(v) for v in np.asarray(h, dtype=np.float32)] for h in irs]
-    n_blocks = -(-max(n_out, len(x)) // block)
-    act = []
-    cur = None
-    sched = dict(schedule)
-    for b in range(n_blocks):
-        if b in sched:
-            cur = sched[b]
-        act.append(cur)
+    act = ir_of_sample(len(x), schedule, block)
     y = []
     for n in range(n_out):
         acc = 0
         for m in range(0, min(n, len(x) - 1) + 1):
-            k = act[m // block]
-            if k is None:
+            k = int(act[m])
+            if k < 0:
                 continue
             h = irs_e[k]
             j = n - m
@@ -230,14 +247,7 @@ def sampled_outputs(x: np.ndarray, irs, schedule, block: int, idx) -> np.ndarray
     the input window with the reversed IR per active-IR segment)."""
     x = np.asarray(x, dtype=np.float32).astype(np.float64)
     irs64 = [np.asarray(h, dtype=np.float32).astype(np.float64) for h in irs]
-    n_blocks = -(-x.size // block)
-    sched = _schedule_array(n_blocks, schedule)
-    act = np.empty(n_blocks, dtype=np.int64)
-    cur = -1
-    for b in range(n_blocks):
-        if sched[b] >= 0:
-            cur = sched[b]
-        act[b] = cur
+    act = ir_of_sample(x.size, schedule, block)
     out = np.zeros(len(idx), dtype=np.float64)
     for t, n in enumerate(idx):
         n = int(n)
@@ -246,7 +256,7 @@ def sampled_outputs(x: np.ndarray, irs, schedule, block: int, idx) -> np.ndarray
         if hi < lo:
             continue
         m = np.arange(lo, hi + 1)
-        ks = act[m // block]
+        ks = act[m]
         acc = 0.0
         for k in np.unique(ks):
             if k < 0:

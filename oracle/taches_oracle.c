@@ -9,7 +9,9 @@
  * taches.  With an impulse response that can change between blocks, the
  * tache of each sample uses the IR that is active when that sample is
  * consumed; taches already in the residue keep ringing with the IR that
- * produced them (Abstract; Section 6).
+ * produced them (Abstract; Section 6).  A queued IR may also take over at a
+ * given sample of the next block (the "even sample-by-sample" update of
+ * Section 6): the taches of that block's earlier samples use the old IR.
  *
  * How (Section 4.2, algorithm TachesAlgorithm, buffer form): a circular
  * residue r of Lmax slots and an index p.  For each input sample, in input
@@ -51,6 +53,7 @@ typedef struct or_stream {
   int La;                /* active IR length, 0 = none yet */
   float *pending;        /* [Lmax] */
   int Lp;                /* pending IR length, 0 = none */
+  int off_p;             /* sample of the next block from which the pending IR applies */
 } or_stream;
 
 or_stream *or_open(int B, int Lmax, int C, int prec) {
@@ -75,14 +78,19 @@ void or_close(or_stream *s) {
   free(s->r64); free(s->r32); free(s->active); free(s->pending); free(s);
 }
 
-/* Queue an IR; it becomes active at the next or_process call.  The last IR
+/* Queue an IR; it becomes active at sample `offset` (0 <= offset < B) of the
+ * next or_process call: samples before it keep the current IR.  The last IR
  * set before a call wins. */
-int or_set_ir(or_stream *s, const float *h, int L) {
-  if (!s || !h || L < 1 || L > s->Lmax) return OR_EINVAL;
+int or_set_ir_at(or_stream *s, const float *h, int L, int offset) {
+  if (!s || !h || L < 1 || L > s->Lmax || offset < 0 || offset >= s->B) return OR_EINVAL;
   memcpy(s->pending, h, (size_t)L * sizeof(float));
   s->Lp = L;
+  s->off_p = offset;
   return OR_OK;
 }
+
+/* Queue an IR for the whole next block. */
+int or_set_ir(or_stream *s, const float *h, int L) { return or_set_ir_at(s, h, L, 0); }
 
 /* Scatter one tache into one channel's residue, emit, clear, (caller advances). */
 static double tache_step64(double *r, int Lmax, int p, double e0, const float *h, int L) {
@@ -117,31 +125,33 @@ static float tache_step32(float *r, int Lmax, int p, float e0, const float *h, i
  * Returns OR_ENOIR (y untouched) if no IR was ever set. */
 int or_process(or_stream *s, const float *x, double *y) {
   if (!s || !x || !y) return OR_EINVAL;
-  if (s->Lp > 0) {                       /* the queued IR takes effect here */
+  const int B = s->B, Lmax = s->Lmax;
+  int sw = B;                            /* first sample that uses the queued IR */
+  if (s->Lp > 0) sw = s->off_p;
+  if (sw == 0) {                         /* the queued IR takes effect here */
     float *t = s->active; s->active = s->pending; s->pending = t;
     s->La = s->Lp; s->Lp = 0;
+    sw = B;
   }
-  if (s->La == 0) return OR_ENOIR;
-  const int B = s->B, Lmax = s->Lmax, L = s->La;
+  if (s->La == 0) return OR_ENOIR;       /* no IR for the block's first sample */
   int p0 = s->p;
   for (int c = 0; c < s->C; ++c) {       /* channels are independent */
     int p = p0;
     const float *xc = x + (size_t)c * B;
     double *yc = y + (size_t)c * B;
-    if (s->prec == OR_FP64) {
-      double *r = s->r64 + (size_t)c * Lmax;
-      for (int n = 0; n < B; ++n) {
-        yc[n] = tache_step64(r, Lmax, p, (double)xc[n], s->active, L);
-        p = (p + 1 == Lmax) ? 0 : p + 1;
-      }
-    } else {
-      float *r = s->r32 + (size_t)c * Lmax;
-      int fused = (s->prec == OR_FP32_FMA);
-      for (int n = 0; n < B; ++n) {
-        yc[n] = (double)tache_step32(r, Lmax, p, xc[n], s->active, L, fused);
-        p = (p + 1 == Lmax) ? 0 : p + 1;
-      }
+    for (int n = 0; n < B; ++n) {
+      const float *h = n < sw ? s->active : s->pending;
+      const int L = n < sw ? s->La : s->Lp;
+      if (s->prec == OR_FP64)
+        yc[n] = tache_step64(s->r64 + (size_t)c * Lmax, Lmax, p, (double)xc[n], h, L);
+      else
+        yc[n] = (double)tache_step32(s->r32 + (size_t)c * Lmax, Lmax, p, xc[n], h, L, s->prec == OR_FP32_FMA);
+      p = (p + 1 == Lmax) ? 0 : p + 1;
     }
+  }
+  if (sw < B) {                          /* the queued IR took over inside the block */
+    float *t = s->active; s->active = s->pending; s->pending = t;
+    s->La = s->Lp; s->Lp = 0;
   }
   s->p = (int)(((long)p0 + B) % Lmax);
   return OR_OK;
@@ -161,12 +171,13 @@ int or_get_residue(const or_stream *s, int c, double *out) {
 
 /* Whole-signal driver for one channel of one stream: n_blocks blocks of B
  * samples from x (zero beyond n_x), IR schedule given as ir_of_block[b] =
- * index into (irs, lens) of the IR set before block b (-1 = no change).
+ * index into (irs, lens) of the IR set before block b (-1 = no change),
+ * taking over at sample off_of_block[b] of block b (NULL = at its start).
  * Writes n_blocks*B outputs into y.  Used to run many channels/streams from
  * parallel host threads; it calls only the functions above. */
 int or_run_channel(int B, int Lmax, int prec, const float *x, long n_x, int n_blocks,
                    const float *const *irs, const int *lens, const int *ir_of_block,
-                   double *y) {
+                   const int *off_of_block, double *y) {
   or_stream *s = or_open(B, Lmax, 1, prec);
   if (!s) return OR_ENOMEM;
   float *xb = (float *)malloc((size_t)B * sizeof(float));
@@ -174,7 +185,7 @@ int or_run_channel(int B, int Lmax, int prec, const float *x, long n_x, int n_bl
   int rc = OR_OK;
   for (int b = 0; b < n_blocks && rc == OR_OK; ++b) {
     int k = ir_of_block[b];
-    if (k >= 0) rc = or_set_ir(s, irs[k], lens[k]);
+    if (k >= 0) rc = or_set_ir_at(s, irs[k], lens[k], off_of_block ? off_of_block[b] : 0);
     if (rc != OR_OK) break;
     for (int i = 0; i < B; ++i) {
       long m = (long)b * B + i;

@@ -30,14 +30,15 @@ def impl_o2(x, irs, schedule, B, Lmax, n_out):
     return impl_o1(x, irs, schedule, B, Lmax, n_out, prec=O.OR_FP32_FMA)
 
 
-def _active_of_sample(schedule, B, n):
-    act = {}
-    cur = None
-    sched = dict(schedule)
-    for b in range(-(-n // B) + 1):
-        if b in sched:
-            cur = sched[b]
-        act[b] = cur
+def _active_of_sample(schedule, B, n, ignore_offsets=False):
+    """IR index of each input sample 0 .. n-1 (None before the first IR): a
+    schedule entry (block, ir[, offset]) applies from sample block*B + offset
+    on; a later entry overrides."""
+    act = [None] * n
+    for e in sorted(schedule, key=lambda e: e[0] * B + (0 if ignore_offsets or len(e) < 3 else e[2])):
+        start = e[0] * B + (0 if ignore_offsets or len(e) < 3 else e[2])
+        for m in range(max(start, 0), n):
+            act[m] = e[1]
     return act
 
 
@@ -48,7 +49,7 @@ def impl_o3(x, irs, schedule, B, Lmax, n_out):
     zero = np.zeros(1, np.float32)
 
     def h_of(n):
-        k = act[n // B]
+        k = act[n]
         return zero if k is None else irs[k]
     return O.vector_form(xx, h_of)[:n_out]
 
@@ -58,16 +59,18 @@ def _vector_mutant(kind):
     def impl(x, irs, schedule, B, Lmax, n_out):
         xx = np.zeros(n_out, dtype=np.float32)
         xx[: min(len(x), n_out)] = np.asarray(x, np.float32)[:n_out]
-        act = _active_of_sample(schedule, B, n_out)
+        act = _active_of_sample(schedule, B, n_out, ignore_offsets=(kind == "offset_ignored"))
         if kind == "swap_late":          # IR taken from the previous block
-            act = {b: act.get(b - 1, act[0]) if b > 0 else act[0] for b in act}
+            act = [act[max(m - B, 0)] for m in range(n_out)]
         if kind == "swap_early":         # IR taken from the next block
-            act = {b: act.get(b + 1, act[b]) for b in act}
+            act = [act[min(m + B, n_out - 1)] for m in range(n_out)]
+        if kind == "offset_late":        # a swap takes over one sample late
+            act = [act[max(m - 1, 0)] for m in range(n_out)]
         Nh = max(len(h) for h in irs)
         r = np.zeros(Nh + 1, np.float64)
         s = []
         for n in range(n_out):
-            k = act[n // B]
+            k = act[n]
             h = np.zeros(1) if k is None else np.asarray(irs[k], np.float64)
             if kind == "drop_last_tap":
                 h = h[:-1]
@@ -94,7 +97,7 @@ def _vector_mutant(kind):
 
 
 MUTANTS = ["swap_late", "swap_early", "drop_last_tap", "sign", "rotated", "reversed_ir",
-           "emit_after_shift", "shift_right"]
+           "emit_after_shift", "shift_right", "offset_late", "offset_ignored"]
 
 
 # ---------------------------------------------------------------------------
@@ -236,8 +239,55 @@ def pin_commutativity(impl):
     return np.array_equal(a, b)
 
 
+def pin_sample_swap_decomposition(impl):
+    """Sample-accurate swap (Section 6: the IR may change even sample by
+    sample): an IR set to take over at sample o of block b gives
+    y = conv(x*1[m<p], h_old) + conv(x*1[m>=p], h_new), p = b*B + o, exactly;
+    moving the swap by one sample changes y."""
+    B, n = 5, 30
+    x = W.signal_int(n, 24)
+    ha, hb = W.signal_int(6, 25), W.signal_int(4, 26)
+    n_out = n + 6 - 1
+
+    def conv(v, h):
+        out = np.zeros(n_out)
+        c = np.convolve(v, h.astype(np.float64))
+        out[: c.size] = c
+        return out
+    for blk, o in ((2, 0), (2, 1), (2, 3), (3, B - 1), (1, 2)):
+        p = blk * B + o
+        x1 = x.astype(np.float64).copy()
+        x1[p:] = 0
+        x2 = x.astype(np.float64) - x1
+        want = conv(x1, ha) + conv(x2, hb)
+        if not np.array_equal(impl(x, [ha, hb], [(0, 0), (blk, 1, o)], B, 6, n_out), want):
+            return False
+        for q in (p - 1, p + 1):
+            if np.array_equal(impl(x, [ha, hb], [(0, 0), (q // B, 1, q % B)], B, 6, n_out), want):
+                return False
+    return True
+
+
+def pin_brute_force_sample_swaps(impl):
+    """Exact equality with Eq. (4) (integers) under schedules whose swaps
+    take over inside blocks, including several swaps and unequal lengths."""
+    cases = [(17, 40, 6, 3, 4, [(2, 1), (5, 3), (7, 0)]), (18, 33, 2, 5, 7, [(1, 6), (3, 2)]),
+             (19, 21, 4, 4, 1, [(3, 0), (9, 0)]), (20, 26, 9, 1, 5, [(1, 4), (2, 4), (4, 1)])]
+    for seed, n, L1, L2, B, swaps in cases:
+        x = W.signal_int(n, seed)
+        irs = [W.signal_int(L1, seed + 1), W.signal_int(L2, seed + 2)]
+        sched = [(0, 0)] + [(b, (i + 1) % 2, o) for i, (b, o) in enumerate(swaps)]
+        Lmax = max(L1, L2)
+        n_out = n + Lmax + B
+        ref = np.array([float(v) for v in O.brute_force(x, irs, sched, B, n_out)])
+        if not np.array_equal(impl(x, irs, sched, B, Lmax, n_out), ref):
+            return False
+    return True
+
+
 PINS = [pin_golden_fig5, pin_golden_swap, pin_brute_force, pin_impulse, pin_overflow,
-        pin_swap_decomposition, pin_linearity_shift, pin_commutativity]
+        pin_swap_decomposition, pin_linearity_shift, pin_commutativity, pin_sample_swap_decomposition,
+        pin_brute_force_sample_swaps]
 
 
 @pytest.mark.parametrize("pin", PINS, ids=lambda p: p.__name__)
@@ -391,3 +441,32 @@ def test_sampled_outputs_match_full_oracle():
     s = O.sampled_outputs(spec.x[0], spec.irs, spec.schedule, 256, idx)
     mag = O.abs_bound_weights(spec.x[0], spec.irs, spec.schedule, 256, 3000)
     assert np.all(np.abs(s - y[idx]) <= 1e-12 * mag[idx] + 1e-300)
+
+
+def test_sample_swap_per_block_calls_equal_schedule_run():
+    """set_ir(h, offset) between two blocks equals the scheduled whole-signal
+    run bit for bit; a swap at offset 0 equals the block swap."""
+    B, L = 16, 40
+    x = W.signal_gauss(10 * B, 27)
+    ha, hb = W.impulse_response(L, 28), W.impulse_response(30, 29)
+    sched = [(0, 0), (3, 1, 5), (6, 0, 15), (8, 1, 0)]
+    ref = impl_o1(x, [ha, hb], sched, B, L, 10 * B)
+    s = O.OracleStream(B, L, 1)
+    ys = []
+    for b in range(10):
+        for e in sched:
+            if e[0] == b:
+                s.set_ir([ha, hb][e[1]], e[2] if len(e) > 2 else 0)
+        ys.append(s.process(x[b * B:(b + 1) * B])[1][0])
+    assert np.array_equal(np.concatenate(ys), ref)
+    assert np.array_equal(impl_o1(x, [ha, hb], [(0, 0), (3, 1, 0)], B, L, 10 * B),
+                          impl_o1(x, [ha, hb], [(0, 0), (3, 1)], B, L, 10 * B))
+
+
+def test_swap_inside_the_first_block_without_an_ir_is_enoir():
+    s = O.OracleStream(8, 8, 1)
+    assert s.set_ir(np.ones(4, np.float32), 3) == 0
+    rc, _ = s.process(np.ones(8, np.float32))
+    assert rc == O.OR_ENOIR
+    assert s.set_ir(np.ones(4, np.float32), 8) == O.OR_EINVAL
+    assert s.set_ir(np.ones(4, np.float32), -1) == O.OR_EINVAL
