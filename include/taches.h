@@ -120,6 +120,17 @@ int taches_set_ir(taches_stream* s, const float* h, int32_t L);
  * handle's stream has passed this point). */
 int taches_set_ir_device(taches_stream* s, const float* h_dev, int32_t L);
 
+/* Sample-accurate swap (the IR may change "even sample by sample", Section
+ * 6): like taches_set_ir, but the new IR takes over at sample `offset`
+ * (0 <= offset < B) of the next processed block; that block's samples
+ * before `offset` keep the current IR's taches, and its later samples and
+ * all later blocks use the new one.  offset 0 is taches_set_ir.  h on the
+ * device if h_on_device is nonzero.  TACHES_EINVAL for an offset out of
+ * range, or an offset > 0 on a SPLIT_BF16 stream (not supported there); the
+ * next process call returns TACHES_ENOIR if no IR is active for the samples
+ * before `offset`. */
+int taches_set_ir_at(taches_stream* s, const float* h, int32_t L, int32_t offset, int32_t h_on_device);
+
 /* Load h[0..L) into IR slot `slot` (0 <= slot < ir_slots) for use by an IR
  * schedule of taches_process_blocks.  h_on_device selects host or device
  * memory for h.  Loading the active slot is allowed: the copy is ordered
@@ -146,6 +157,16 @@ int taches_process_async(taches_stream* s, const float* x_dev, float* y_dev);
  * calls of taches_process_async bit for bit. */
 int taches_process_blocks(taches_stream* s, const float* x_dev, float* y_dev, int32_t n_blocks,
                           const int32_t* ir_slot_of_block);
+
+/* taches_process_blocks with sample-accurate swaps: offset_of_block (host,
+ * n_blocks entries, or NULL for all 0) gives, for every block b with
+ * ir_slot_of_block[b] >= 0, the sample of block b (0 <= offset < B) from
+ * which that slot takes over.  Equals the same schedule applied block by
+ * block with taches_set_ir_at, bit for bit.  TACHES_EINVAL if offsets are
+ * given without a schedule, an offset is out of range, or the stream is
+ * SPLIT_BF16 and an offset is > 0. */
+int taches_process_blocks_at(taches_stream* s, const float* x_dev, float* y_dev, int32_t n_blocks,
+                             const int32_t* ir_slot_of_block, const int32_t* offset_of_block);
 
 /* ---- state ------------------------------------------------------------- */
 

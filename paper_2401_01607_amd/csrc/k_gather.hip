@@ -153,13 +153,23 @@ struct ChunkGeo {
 template <int R>
 __device__ __forceinline__ ChunkGeo chunk_geo(const GatherCall& d, int ck, int n0) {
   ChunkGeo g;
-  const int b = ck / d.cpb;
-  const int i = ck - b * d.cpb;
-  g.m_lo = b * d.B + (i * d.B) / d.cpb;
-  const int m_hi = b * d.B + ((i + 1) * d.B) / d.cpb;
-  g.len = m_hi - g.m_lo;
+  int m_hi;
+  if (d.ctab) {
+    // an IR takes over inside some block: chunks come from the table
+    const int32_t* cd = d.ctab + (d.n_blocks + 1) + 3 * ck;
+    g.m_lo = cd[0];
+    g.len = cd[1];
+    m_hi = g.m_lo + g.len;
+    g.ir = d.irs[cd[2]];
+  } else {
+    const int b = ck / d.cpb;
+    const int i = ck - b * d.cpb;
+    g.m_lo = b * d.B + (i * d.B) / d.cpb;
+    m_hi = b * d.B + ((i + 1) * d.B) / d.cpb;
+    g.len = m_hi - g.m_lo;
+    g.ir = d.irs ? d.irs[b] : d.ir0;
+  }
   g.len_pad = (g.len + R - 1) / R * R;
-  g.ir = d.irs ? d.irs[b] : d.ir0;
   // the chunk's taches cover outputs [m_lo, m_hi - 1 + L - 1]
   g.reaches = g.len > 0 && g.m_lo <= n0 + Geo<R>::T - 1 && m_hi + g.ir.L - 2 >= n0;
   g.ck = ck;
@@ -346,15 +356,19 @@ __device__ __forceinline__ void gather_tile(const GatherCall& d, int c, int tile
     const int lo = n0 - (d.Lmax_call - 1);
     const int b_first = lo <= 0 ? 0 : lo / d.B;
     const int b_last = min(d.n_blocks - 1, (n0 + T - 1) / d.B);
-    const int c_first = b_first * d.cpb;
-    const int nch = b_first <= b_last ? (b_last - b_first + 1) * d.cpb : 0;
+    int c_first = b_first * d.cpb;
+    int nch = b_first <= b_last ? (b_last - b_first + 1) * d.cpb : 0;
+    if (d.ctab && b_first <= b_last) {
+      c_first = d.ctab[b_first];
+      nch = d.ctab[b_last + 1] - c_first;
+    }
     // `gc` is staged in LDS, `gn` (the wave's next unit) is in registers.
     // A wave's LDS region is private and LDS operations of one wave complete
     // in program order, so storing `gn` after computing `gc` needs no
     // barrier.
     Prefetch<R> pf;
     if constexpr (W == 1) {
-      const int kmax = (d.cpb == 1 && d.B % R == 0) ? max(1, CHUNK_MAX / d.B) : 1;
+      const int kmax = (!d.ctab && d.cpb == 1 && d.B % R == 0) ? max(1, CHUNK_MAX / d.B) : 1;
       const int c_end = c_first + nch;
       ChunkGeo gc = unit_geo<R>(d, c_first, c_end, kmax, n0);
       if (gc.reaches) {

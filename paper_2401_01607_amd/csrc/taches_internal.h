@@ -35,7 +35,12 @@ struct GatherCall {
   const float* x;        // [C][x_cstride] planar input, nullptr = all zero
   float* y;              // [C][y_cstride] planar output
   void* ring;            // [C][ring_cstride] tail (float or double)
-  const BlockIR* irs;    // per-block IR table (device), nullptr = ir0 for all
+  const BlockIR* irs;    // per-block IR table (device), nullptr = ir0 for all;
+                         // with ctab: one entry per IR slot
+  const int32_t* ctab;   // chunk table (device) when an IR takes over inside a
+                         // block, nullptr = regular chunks: first chunk of each
+                         // block [n_blocks + 1], then {first sample, length,
+                         // slot} per chunk
   BlockIR ir0;
   int64_t x_cstride, y_cstride, ring_cstride;
   int32_t S;             // input samples of the call = n_blocks * B

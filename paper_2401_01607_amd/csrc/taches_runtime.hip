@@ -51,6 +51,22 @@ int64_t ring_slots_for(const taches_config& c) {
 
 bool is_split(const taches_config& c) { return c.precision == TACHES_PREC_SPLIT_BF16; }
 
+// Per-call table (device, filled per call when needed): one BlockIR per block
+// when the IR changes between blocks; when an IR takes over inside a block,
+// one BlockIR per slot followed by the chunk table: the first chunk of each
+// block [n_blocks + 1], then {first sample, length, slot} per chunk (a block
+// cut by a swap has at most one chunk more than ceil(B / CHUNK_MAX)).
+int64_t max_chunks_per_call(const taches_config& c) {
+  return (int64_t)c.max_blocks_per_call * ((c.block_size + taches::CHUNK_MAX - 1) / taches::CHUNK_MAX + 1);
+}
+
+int64_t irtab_bytes(const taches_config& c) {
+  const int64_t per_block = (int64_t)c.max_blocks_per_call * (int64_t)sizeof(BlockIR);
+  const int64_t chunked = (int64_t)c.ir_slots * (int64_t)sizeof(BlockIR) +
+                          4 * ((int64_t)c.max_blocks_per_call + 1 + 3 * max_chunks_per_call(c));
+  return std::max(per_block, chunked);
+}
+
 // channels stored per tail slot: the split path pads to its MFMA width
 int64_t ring_channels(const taches_config& c) { return is_split(c) ? taches::split_cpad(c.channels) : c.channels; }
 
@@ -96,6 +112,7 @@ struct taches_stream {
   void* ring = nullptr;
   std::vector<IrSlot> slots;
   int active = -1, pending = -1;
+  int pending_off = 0;                            // sample of the next block where `pending` takes over
   int head = 0, live = 0;
   int64_t blocks_done = 0;
   hipStream_t own = nullptr, stream = nullptr;
@@ -180,7 +197,7 @@ int stream_init(taches_stream* s) {
   const size_t blk = (size_t)c.channels * c.block_size * 4;
   if ((rc = dev_alloc(s, &s->x_dev, blk))) return rc;
   if ((rc = dev_alloc(s, &s->y_dev, blk))) return rc;
-  const size_t tab = (size_t)c.max_blocks_per_call * sizeof(BlockIR);
+  const size_t tab = (size_t)irtab_bytes(c);
   if ((rc = dev_alloc(s, &s->irtab_dev, tab))) return rc;
   HIPCHK(hipEventCreateWithFlags(&s->irtab_ev, hipEventDisableTiming));
   if (is_split(c)) {
@@ -306,58 +323,89 @@ struct CallPlan {
 };
 
 // Validate a call and build its descriptor.  Uploads the per-block IR table
-// when the IR changes inside the call.  Nothing is launched.
+// when the IR changes inside the call (and the chunk table when an IR takes
+// over inside a block).  Nothing is launched.
 // Channel strides of 0 mean packed channels (stride n_blocks * B).
+// sched[b] >= 0: slot set before block b, taking over at sample offs[b] of
+// it (offs NULL: at its start).
 int plan_call(taches_stream* s, const float* x_dev, int64_t x_cstride, float* y_dev, int64_t y_cstride, int n_blocks,
-              const int32_t* sched, CallPlan* out) {
+              const int32_t* sched, const int32_t* offs, CallPlan* out) {
   const taches_config& c = s->cfg;
   if (n_blocks < 1 || n_blocks > c.max_blocks_per_call)
     return fail(TACHES_EINVAL, "n_blocks %d outside [1, %d]", n_blocks, c.max_blocks_per_call);
   if (!y_dev) return fail(TACHES_EINVAL, "y is NULL");
+  const int B = c.block_size;
   {
-    const int64_t S = (int64_t)n_blocks * c.block_size;
+    const int64_t S = (int64_t)n_blocks * B;
     if (x_cstride == 0) x_cstride = S;
     if (y_cstride == 0) y_cstride = S;
     if (c.channels > 1 && (x_cstride < S || y_cstride < S))
       return fail(TACHES_EINVAL, "channel stride (x %lld, y %lld) shorter than the call's %lld samples",
                   (long long)x_cstride, (long long)y_cstride, (long long)S);
   }
-  // resolve the IR of every block: a pending set_ir applies first, then the schedule
-  const int act = s->pending >= 0 ? s->pending : s->active;
   if (sched) {
     for (int b = 0; b < n_blocks; ++b) {
       const int k = sched[b];
       if (k < -1 || k >= c.ir_slots) return fail(TACHES_EINVAL, "schedule entry %d: slot %d", b, k);
       if (k >= 0 && s->slots[k].L == 0) return fail(TACHES_ENOIR, "schedule entry %d: slot %d holds no IR", b, k);
+      if (k >= 0 && offs && (offs[b] < 0 || offs[b] >= B))
+        return fail(TACHES_EINVAL, "schedule entry %d: offset %d outside [0, %d)", b, offs[b], B);
     }
   }
-  if (x_dev && act < 0 && !(sched && sched[0] >= 0)) return fail(TACHES_ENOIR, "no impulse response set");
-  const int B = c.block_size;
-  const int64_t S = (int64_t)n_blocks * B;
-  bool uniform = true;
-  int first_slot = -1;
-  int Lmax_call = 0;
-  int64_t ext = 0;
-  int cur = act;
-  if (!sched) {
-    // one IR for the whole call
-    first_slot = cur;
-    if (x_dev && cur >= 0) {
-      Lmax_call = s->slots[cur].L;
-      ext = S + Lmax_call - 1;
+  // IR set before block b (a pending set_ir applies to block 0 unless the
+  // schedule sets it) and the sample of the block it takes over at
+  auto entry = [&](int b, int* k, int* off) {
+    *k = -1;
+    *off = 0;
+    if (sched && sched[b] >= 0) {
+      *k = sched[b];
+      *off = offs ? offs[b] : 0;
+    } else if (b == 0 && s->pending >= 0) {
+      *k = s->pending;
+      *off = s->pending_off;
     }
-  } else {
-    for (int b = 0; b < n_blocks; ++b) {
-      if (sched[b] >= 0) cur = sched[b];
-      if (b == 0) first_slot = cur;
-      else if (cur != first_slot) uniform = false;
-      if (x_dev && cur >= 0) {
-        const int L = s->slots[cur].L;
-        Lmax_call = std::max(Lmax_call, L);
-        ext = std::max<int64_t>(ext, (int64_t)b * B + B + L - 1);
+  };
+  // resolve every block: IR ir0 from its start, and ir1 from sample `off` on
+  // when an IR takes over inside the block
+  const int64_t S = (int64_t)n_blocks * B;
+  bool uniform = true, intra = false;
+  int first_slot = -1, Lmax_call = 0;
+  int64_t ext = 0;
+  int cur = s->active;
+  for (int b = 0; b < n_blocks; ++b) {
+    int k, off;
+    entry(b, &k, &off);
+    int ir0 = cur, ir1 = -1;
+    if (k >= 0 && off == 0) ir0 = k;
+    if (k >= 0 && off > 0) ir1 = k;
+    if (k >= 0) cur = k;
+    if (x_dev && ir0 < 0) return fail(TACHES_ENOIR, "no impulse response set for block %d", b);
+    if (b == 0) first_slot = ir0;
+    if (ir0 != first_slot || ir1 >= 0) uniform = false;
+    if (ir1 >= 0) intra = true;
+    if (x_dev) {
+      const int L0 = s->slots[ir0].L;
+      Lmax_call = std::max(Lmax_call, L0);
+      ext = std::max<int64_t>(ext, (int64_t)b * B + (ir1 >= 0 ? off : B) + L0 - 1);
+      if (ir1 >= 0) {
+        const int L1 = s->slots[ir1].L;
+        Lmax_call = std::max(Lmax_call, L1);
+        ext = std::max<int64_t>(ext, (int64_t)b * B + B + L1 - 1);
       }
     }
+    if (!sched && b == 0 && n_blocks > 1) {
+      // no schedule: blocks 1 .. n-1 all use `cur`
+      if (x_dev) {
+        const int L = s->slots[cur].L;
+        Lmax_call = std::max(Lmax_call, L);
+        ext = std::max<int64_t>(ext, S + L - 1);
+      }
+      if (cur != first_slot) uniform = false;
+      break;
+    }
   }
+  if (intra && x_dev && is_split(c))
+    return fail(TACHES_EINVAL, "an IR taking over inside a block needs FP32 precision");
   const int64_t n_out = std::max<int64_t>(std::max<int64_t>(S, s->live), ext);
   if (n_out > s->Rcap) return fail(TACHES_EINVAL, "call needs %lld tail slots, ring has %d", (long long)n_out, s->Rcap);
 
@@ -397,25 +445,66 @@ int plan_call(taches_stream* s, const float* x_dev, int64_t x_cstride, float* y_
     g.ir0 = ir_of(first_slot);
   } else {
     if (!s->irtab_pin) {
-      int rc = host_alloc(&s->irtab_pin, (size_t)c.max_blocks_per_call * sizeof(BlockIR));
+      int rc = host_alloc(&s->irtab_pin, (size_t)irtab_bytes(c));
       if (rc != TACHES_OK) return rc;
     }
     if (s->irtab_pending) {
       HIPCHK(hipEventSynchronize(s->irtab_ev));
       s->irtab_pending = false;
     }
-    int k = act;
-    for (int b = 0; b < n_blocks; ++b) {
-      if (sched[b] >= 0) k = sched[b];
-      s->irtab_pin[b] = ir_of(k);
+    size_t bytes;
+    if (!intra) {
+      int k = s->active;
+      for (int b = 0; b < n_blocks; ++b) {
+        int e, off;
+        entry(b, &e, &off);
+        if (e >= 0) k = e;
+        s->irtab_pin[b] = ir_of(k);
+      }
+      bytes = (size_t)n_blocks * sizeof(BlockIR);
+    } else {
+      // slot table, then the chunk table: each IR segment of a block is cut
+      // into ceil(len / CHUNK_MAX) near-equal chunks (a block without a swap
+      // inside gets exactly the chunks of the regular geometry)
+      for (int k = 0; k < c.ir_slots; ++k) s->irtab_pin[k] = ir_of(k);
+      int32_t* bc0 = reinterpret_cast<int32_t*>(s->irtab_pin + c.ir_slots);
+      int32_t* cd = bc0 + (n_blocks + 1);
+      int nc = 0;
+      auto cut = [&](int b, int a, int e, int k) {
+        const int n = (e - a + taches::CHUNK_MAX - 1) / taches::CHUNK_MAX;
+        for (int i = 0; i < n; ++i) {
+          const int lo = b * B + a + (i * (e - a)) / n;
+          const int hi = b * B + a + ((i + 1) * (e - a)) / n;
+          cd[3 * nc] = lo;
+          cd[3 * nc + 1] = hi - lo;
+          cd[3 * nc + 2] = k;
+          ++nc;
+        }
+      };
+      int k = s->active;
+      for (int b = 0; b < n_blocks; ++b) {
+        int e, off;
+        entry(b, &e, &off);
+        bc0[b] = nc;
+        if (e >= 0 && off > 0) {
+          cut(b, 0, off, k);
+          cut(b, off, B, e);
+        } else {
+          if (e >= 0) k = e;
+          cut(b, 0, B, k);
+        }
+        if (e >= 0) k = e;
+      }
+      bc0[n_blocks] = nc;
+      bytes = (size_t)c.ir_slots * sizeof(BlockIR) + 4 * ((size_t)n_blocks + 1 + 3 * (size_t)nc);
+      g.ctab = reinterpret_cast<const int32_t*>(s->irtab_dev + c.ir_slots);
     }
-    HIPCHK(hipMemcpyAsync(s->irtab_dev, s->irtab_pin, (size_t)n_blocks * sizeof(BlockIR), hipMemcpyHostToDevice,
-                          s->stream));
+    HIPCHK(hipMemcpyAsync(s->irtab_dev, s->irtab_pin, bytes, hipMemcpyHostToDevice, s->stream));
     HIPCHK(hipEventRecord(s->irtab_ev, s->stream));
     s->irtab_pending = true;
     g.irs = s->irtab_dev;
   }
-  out->next_active = cur >= 0 ? cur : act;
+  out->next_active = cur;
   out->S = S;
   out->n_out = n_out;
   out->n_blocks = n_blocks;
@@ -425,6 +514,7 @@ int plan_call(taches_stream* s, const float* x_dev, int64_t x_cstride, float* y_
 void commit_call(taches_stream* s, const CallPlan& p) {
   s->active = p.next_active;
   s->pending = -1;
+  s->pending_off = 0;
   s->head = (int)((s->head + p.S) % s->Rcap);
   s->live = (int)(p.n_out - p.S);
   s->blocks_done += p.n_blocks;
@@ -464,10 +554,11 @@ int launch_call(taches_stream* s, CallPlan& p) {
   return TACHES_OK;
 }
 
-int process_common(taches_stream* s, const float* x_dev, float* y_dev, int n_blocks, const int32_t* sched) {
+int process_common(taches_stream* s, const float* x_dev, float* y_dev, int n_blocks, const int32_t* sched,
+                   const int32_t* offs = nullptr) {
   if (s->pool) return fail(TACHES_EBUSY, "stream is attached to a pool; use taches_pool_step");
   CallPlan p;
-  int rc = plan_call(s, x_dev, 0, y_dev, 0, n_blocks, sched, &p);
+  int rc = plan_call(s, x_dev, 0, y_dev, 0, n_blocks, sched, offs, &p);
   if (rc != TACHES_OK) return rc;
   rc = launch_call(s, p);
   if (rc != TACHES_OK) return rc;
@@ -541,10 +632,14 @@ int taches_synchronize(taches_stream* s) {
   return TACHES_OK;
 }
 
-static int set_ir_common(taches_stream* s, const float* h, int32_t L, bool on_device) {
+static int set_ir_common(taches_stream* s, const float* h, int32_t L, bool on_device, int32_t offset = 0) {
   if (!s) return fail(TACHES_EINVAL, "stream is NULL");
   if (!h) return fail(TACHES_EINVAL, "h is NULL");
   if (L < 1 || L > s->cfg.max_ir_len) return fail(TACHES_EINVAL, "L=%d outside [1, %d]", L, s->cfg.max_ir_len);
+  if (offset < 0 || offset >= s->cfg.block_size)
+    return fail(TACHES_EINVAL, "offset %d outside [0, %d)", offset, s->cfg.block_size);
+  if (offset > 0 && is_split(s->cfg))
+    return fail(TACHES_EINVAL, "an IR taking over inside a block needs FP32 precision");
   int slot = s->pending;
   if (slot < 0) {
     for (int k = 0; k < (int)s->slots.size(); ++k)
@@ -556,10 +651,15 @@ static int set_ir_common(taches_stream* s, const float* h, int32_t L, bool on_de
   int rc = load_slot(s, slot, h, L, on_device);
   if (rc != TACHES_OK) return rc;
   s->pending = slot;
+  s->pending_off = offset;
   return TACHES_OK;
 }
 
 int taches_set_ir(taches_stream* s, const float* h, int32_t L) { return set_ir_common(s, h, L, false); }
+
+int taches_set_ir_at(taches_stream* s, const float* h, int32_t L, int32_t offset, int32_t h_on_device) {
+  return set_ir_common(s, h, L, h_on_device != 0, offset);
+}
 
 int taches_set_ir_device(taches_stream* s, const float* h_dev, int32_t L) { return set_ir_common(s, h_dev, L, true); }
 
@@ -568,7 +668,10 @@ int taches_load_ir_slot(taches_stream* s, int32_t slot, const float* h, int32_t 
   if (slot < 0 || slot >= (int)s->slots.size()) return fail(TACHES_EINVAL, "slot %d outside [0, %zu)", slot, s->slots.size());
   if (!h) return fail(TACHES_EINVAL, "h is NULL");
   if (L < 1 || L > s->cfg.max_ir_len) return fail(TACHES_EINVAL, "L=%d outside [1, %d]", L, s->cfg.max_ir_len);
-  if (slot == s->pending) s->pending = -1;
+  if (slot == s->pending) {
+    s->pending = -1;
+    s->pending_off = 0;
+  }
   return load_slot(s, slot, h, L, h_on_device != 0);
 }
 
@@ -606,6 +709,13 @@ int taches_process_blocks(taches_stream* s, const float* x_dev, float* y_dev, in
   return process_common(s, x_dev, y_dev, n_blocks, ir_slot_of_block);
 }
 
+int taches_process_blocks_at(taches_stream* s, const float* x_dev, float* y_dev, int32_t n_blocks,
+                             const int32_t* ir_slot_of_block, const int32_t* offset_of_block) {
+  if (!s) return fail(TACHES_EINVAL, "stream is NULL");
+  if (offset_of_block && !ir_slot_of_block) return fail(TACHES_EINVAL, "offsets given without a schedule");
+  return process_common(s, x_dev, y_dev, n_blocks, ir_slot_of_block, offset_of_block);
+}
+
 int taches_get_info(const taches_stream* s, taches_info* out) {
   if (!s || !out) return fail(TACHES_EINVAL, "NULL argument");
   std::memset(out, 0, sizeof *out);
@@ -633,7 +743,7 @@ int64_t taches_bytes_for(const taches_config* cfg) {
   b += 2 * xs_bytes(*cfg);
   b += (int64_t)cfg->ir_slots * cfg->max_ir_len * (cfg->precision == TACHES_PREC_SPLIT_BF16 ? 8 : 4);
   b += 2 * (int64_t)cfg->channels * cfg->block_size * 4;
-  b += (int64_t)cfg->max_blocks_per_call * (int64_t)sizeof(BlockIR);
+  b += irtab_bytes(*cfg);
   return b;
 }
 
@@ -972,7 +1082,7 @@ int taches_pool_step_strided(taches_pool* p, int32_t n, taches_stream* const* st
   std::vector<CallPlan> plans(n);
   for (int i = 0; i < n; ++i) {
     int rc = plan_call(streams[i], x_dev ? x_dev[i] : nullptr, x_cstride ? x_cstride[i] : 0, y_dev[i],
-                       y_cstride ? y_cstride[i] : 0, n_blocks[i], nullptr, &plans[i]);
+                       y_cstride ? y_cstride[i] : 0, n_blocks[i], nullptr, nullptr, &plans[i]);
     if (rc != TACHES_OK) return rc;
   }
   // split-precision streams run their own MFMA kernel on the pool's stream

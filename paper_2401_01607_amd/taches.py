@@ -69,10 +69,12 @@ _SIGS = {
     "taches_synchronize": (ctypes.c_int, [_vp]),
     "taches_set_ir": (ctypes.c_int, [_vp, _vp, _i32]),
     "taches_set_ir_device": (ctypes.c_int, [_vp, _vp, _i32]),
+    "taches_set_ir_at": (ctypes.c_int, [_vp, _vp, _i32, _i32, _i32]),
     "taches_load_ir_slot": (ctypes.c_int, [_vp, _i32, _vp, _i32, _i32]),
     "taches_process": (ctypes.c_int, [_vp, _vp, _vp]),
     "taches_process_async": (ctypes.c_int, [_vp, _vp, _vp]),
     "taches_process_blocks": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp]),
+    "taches_process_blocks_at": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp, _vp]),
     "taches_get_info": (ctypes.c_int, [_vp, _P(taches_info)]),
     "taches_bytes_for": (_i64, [_P(taches_config)]),
     "taches_read_tail": (ctypes.c_int, [_vp, _i32, _vp, _i32]),
@@ -157,6 +159,15 @@ def taches_set_ir_device(s, h_dev) -> int:
     return lib.taches_set_ir_device(s, _dev_ptr(h_dev), int(h_dev.numel()))
 
 
+def taches_set_ir_at(s, h, offset: int) -> int:
+    """h: host array or CUDA tensor; it takes over at sample ``offset`` of
+    the next processed block."""
+    if isinstance(h, torch.Tensor):
+        return lib.taches_set_ir_at(s, _dev_ptr(h), int(h.numel()), int(offset), 1)
+    h = np.ascontiguousarray(h, dtype=np.float32)
+    return lib.taches_set_ir_at(s, _host_ptr(h), int(h.size), int(offset), 0)
+
+
 def taches_load_ir_slot(s, slot: int, h) -> int:
     if isinstance(h, torch.Tensor):
         return lib.taches_load_ir_slot(s, slot, _dev_ptr(h), int(h.numel()), 1)
@@ -180,6 +191,19 @@ def taches_process_blocks(s, x_dev, y_dev, n_blocks: int, ir_slot_of_block=None)
             raise ValueError("ir_slot_of_block must have n_blocks entries")
     return lib.taches_process_blocks(s, _dev_ptr(x_dev), _dev_ptr(y_dev), n_blocks,
                                      None if sched is None else _host_ptr(sched))
+
+
+def taches_process_blocks_at(s, x_dev, y_dev, n_blocks: int, ir_slot_of_block, offset_of_block=None) -> int:
+    sched = np.ascontiguousarray(ir_slot_of_block, dtype=np.int32)
+    if sched.size != n_blocks:
+        raise ValueError("ir_slot_of_block must have n_blocks entries")
+    offs = None
+    if offset_of_block is not None:
+        offs = np.ascontiguousarray(offset_of_block, dtype=np.int32)
+        if offs.size != n_blocks:
+            raise ValueError("offset_of_block must have n_blocks entries")
+    return lib.taches_process_blocks_at(s, _dev_ptr(x_dev), _dev_ptr(y_dev), n_blocks, _host_ptr(sched),
+                                        None if offs is None else _host_ptr(offs))
 
 
 def taches_get_info(s) -> taches_info:
@@ -328,8 +352,11 @@ class Stream:
     def C(self) -> int:
         return self.cfg.channels
 
-    def set_ir(self, h) -> None:
-        if isinstance(h, torch.Tensor):
+    def set_ir(self, h, offset: int = 0) -> None:
+        """Queue h for the next block, taking over at sample ``offset`` of it."""
+        if offset:
+            _check(taches_set_ir_at(self.h, h, offset), "taches_set_ir_at")
+        elif isinstance(h, torch.Tensor):
             _check(taches_set_ir_device(self.h, h), "taches_set_ir_device")
         else:
             _check(taches_set_ir(self.h, h), "taches_set_ir")
@@ -346,8 +373,12 @@ class Stream:
     def process_async(self, x_dev, y_dev) -> None:
         _check(taches_process_async(self.h, x_dev, y_dev), "taches_process_async")
 
-    def process_blocks(self, x_dev, y_dev, n_blocks: int, ir_slot_of_block=None) -> None:
-        _check(taches_process_blocks(self.h, x_dev, y_dev, n_blocks, ir_slot_of_block), "taches_process_blocks")
+    def process_blocks(self, x_dev, y_dev, n_blocks: int, ir_slot_of_block=None, offset_of_block=None) -> None:
+        if offset_of_block is not None:
+            _check(taches_process_blocks_at(self.h, x_dev, y_dev, n_blocks, ir_slot_of_block, offset_of_block),
+                   "taches_process_blocks_at")
+        else:
+            _check(taches_process_blocks(self.h, x_dev, y_dev, n_blocks, ir_slot_of_block), "taches_process_blocks")
 
     def info(self) -> taches_info:
         return taches_get_info(self.h)

@@ -29,12 +29,12 @@ def gpu_per_block(x, irs, schedule, B, Lmax, n_blocks, tail=0, tile=None, host_i
     s = T.Stream(B, Lmax, channels=C, tail=tail, precision=precision)
     if tile:
         s.set_tile(*tile)
-    sched = dict(schedule)
+    sched = {e[0]: (e[1], e[2] if len(e) > 2 else 0) for e in schedule}
     if host_io:
         ys = []
         for b in range(n_blocks):
             if b in sched:
-                s.set_ir(irs[sched[b]])
+                s.set_ir(irs[sched[b][0]], sched[b][1])
             ys.append(s.process(xp[:, b * B:(b + 1) * B]))
         y = np.concatenate(ys, axis=1)
     else:
@@ -42,7 +42,7 @@ def gpu_per_block(x, irs, schedule, B, Lmax, n_blocks, tail=0, tile=None, host_i
         yb = torch.empty_like(xb)
         for b in range(n_blocks):
             if b in sched:
-                s.set_ir(irs[sched[b]])
+                s.set_ir(irs[sched[b][0]], sched[b][1])
             s.process_async(xb[b], yb[b])
         s.synchronize()
         y = yb.cpu().numpy().transpose(1, 0, 2).reshape(C, n_blocks * B)
@@ -67,15 +67,18 @@ def gpu_multi_block(x, irs, schedule, B, Lmax, n_blocks, tail=0, tile=None, call
     for k, h in enumerate(irs):
         s.load_ir_slot(k, h)
     sched = np.full(n_blocks, -1, dtype=np.int32)
-    for b, k in schedule:
-        if b < n_blocks:
-            sched[b] = k
+    offs = np.zeros(n_blocks, dtype=np.int32)
+    for e in schedule:
+        if e[0] < n_blocks:
+            sched[e[0]] = e[1]
+            offs[e[0]] = e[2] if len(e) > 2 else 0
+    use_offs = bool(np.any(offs))
     outs = []
     for c0 in range(0, n_blocks, per):
         nb = min(per, n_blocks - c0)
         xd = torch.from_numpy(np.ascontiguousarray(xp[:, c0 * B:(c0 + nb) * B])).cuda()
         yd = torch.empty_like(xd)
-        s.process_blocks(xd, yd, nb, sched[c0:c0 + nb])
+        s.process_blocks(xd, yd, nb, sched[c0:c0 + nb], offs[c0:c0 + nb] if use_offs else None)
         outs.append(yd)
     if drain_x_null:
         yd = torch.empty((C, drain_x_null * B), dtype=torch.float32, device="cuda")

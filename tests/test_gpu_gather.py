@@ -314,3 +314,74 @@ def test_all_zero_input_gives_exact_zeros_and_keeps_the_tail():
     y, _ = gpu_per_block(x, [h], [(0, 0)], B, L, nb)
     d = 5 * B + 7
     assert np.array_equal(y[0, d:d + L], h) and not np.any(y[0, :d]) and not np.any(y[0, d + L:])
+
+
+SAMPLE_SWAP_CASES = [
+    # B, L1, L2, swaps as (block, offset)
+    (64, 500, 1300, [(3, 1), (5, 63), (6, 0), (9, 17)]),
+    (300, 700, 1200, [(2, 150), (3, 299), (5, 1)]),      # two chunks per block, cut anywhere
+    (513, 2000, 64, [(1, 256), (2, 257), (4, 5)]),       # three chunks per block
+    (32, 100, 2500, [(4, 16), (5, 16), (7, 31)]),        # short blocks (grouped staging off)
+]
+
+
+@pytest.mark.parametrize("case", SAMPLE_SWAP_CASES, ids=[f"B{c[0]}" for c in SAMPLE_SWAP_CASES])
+@pytest.mark.parametrize("tile", [None, (16, 1), (16, 4), (4, 2)])
+def test_sample_accurate_swap_bitwise(case, tile):
+    """An IR taking over at sample o of a block: integer inputs match the
+    oracle exactly, per-block calls (taches_set_ir_at) and multi-block calls
+    (taches_process_blocks_at) alike."""
+    B, L1, L2, swaps = case
+    sched = [(0, 0)] + [(b, (i + 1) % 2, o) for i, (b, o) in enumerate(swaps)]
+    Lmax = max(L1, L2)
+    n = 12 * B
+    nb = -(-(n + Lmax) // B) + 1
+    x = W.signal_int(n, 93, 31)
+    irs = [W.signal_int(L1, 94, 31), W.signal_int(L2, 95, 31)]
+    ref = oracle_run(x, irs, sched, B, Lmax, nb)
+    y1, _ = gpu_per_block(x, irs, sched, B, Lmax, nb, tile=tile)
+    assert np.array_equal(y1, ref)
+    y2, _ = gpu_multi_block(x, irs, sched, B, Lmax, nb, tile=tile)
+    assert np.array_equal(y2, ref)
+    y3, _ = gpu_multi_block(x, irs, sched, B, Lmax, nb, tile=tile, calls=3)
+    assert np.array_equal(y3, ref)
+
+
+def test_sample_accurate_swap_float_modes_agree():
+    """Float inputs: per-block and multi-block calls give the same bits and
+    stay within the tolerance of the FP64 oracle; moving the swap by one
+    sample changes the output."""
+    B, L = 256, 6000
+    x = W.signal_gauss(30 * B, 96)
+    irs = [W.impulse_response(L, 97), W.impulse_response(L, 98)]
+    sched = [(0, 0), (4, 1, 100), (9, 0, 255), (15, 1, 1)]
+    nb = -(-(x.size + L) // B)
+    ref = oracle_run(x, irs, sched, B, L, nb)
+    y1, _ = gpu_per_block(x, irs, sched, B, L, nb)
+    y2, _ = gpu_multi_block(x, irs, sched, B, L, nb)
+    assert np.array_equal(y1, y2)
+    assert rel_err(y1, ref) <= TOL
+    moved = [(0, 0), (4, 1, 101), (9, 0, 255), (15, 1, 1)]
+    assert rel_err(y1, oracle_run(x, irs, moved, B, L, nb)) > 1e-3
+
+
+def test_sample_accurate_swap_errors():
+    from tests.gpu_harness import binding
+    T = binding()
+    s = T.Stream(64, 128)
+    h = W.impulse_response(100, 99)
+    with pytest.raises(T.TachesError):
+        s.set_ir(h, 64)
+    with pytest.raises(T.TachesError):
+        s.set_ir(h, -1)
+    s.set_ir(h, 5)                      # no IR before sample 5 of the first block
+    with pytest.raises(T.TachesError) as e:
+        s.process(np.ones(64, np.float32))
+    assert e.value.status == T.TACHES_ENOIR
+    s.set_ir(h)
+    s.process(np.ones(64, np.float32))
+    s.close()
+    sp = T.Stream(64, 128, precision=1)
+    with pytest.raises(T.TachesError):
+        sp.set_ir(h, 3)
+    sp.close()

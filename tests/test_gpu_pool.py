@@ -349,3 +349,33 @@ def test_many_tiles_are_merged_into_range_items_exactly():
         pool.detach(s)
         s.close()
     pool.close()
+
+
+def test_sample_accurate_swap_on_attached_stream():
+    """taches_set_ir_at on a stream attached to a pool applies at its next
+    step, from the given sample: equals the oracle exactly (integers)."""
+    import torch
+    T = binding()
+    B, L, nb = 128, 900, 12
+    x = W.signal_int(nb * B, 101, 31)
+    ha, hb = W.signal_int(L, 102, 31), W.signal_int(400, 103, 31)
+    pool = T.Pool(2, 64 * GB, use_graph=True)
+    s = T.Stream(B, L, max_blocks_per_call=4)
+    s.set_ir(ha)
+    assert pool.attach(s) == T.TACHES_OK
+    xd = torch.from_numpy(x).cuda()
+    ys = []
+    for k, n in enumerate((4, 3, 4, 1)):
+        if k == 2:
+            s.set_ir(hb, 77)            # takes over at sample 77 of the first block of step 2
+        y = torch.empty(n * B, device="cuda")
+        done = sum((4, 3, 4, 1)[:k])
+        pool.step([s], [xd[done * B:(done + n) * B][None]], [y[None]], [n])
+        ys.append(y)
+    pool.synchronize()
+    got = torch.cat(ys).cpu().numpy()
+    ref = oracle_run(x, [ha, hb], [(0, 0), (7, 1, 77)], B, L, nb)[0]
+    assert np.array_equal(got, ref)
+    pool.detach(s)
+    s.close()
+    pool.close()
