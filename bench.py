@@ -74,7 +74,7 @@ def parse():
                    help="only run a plain device copy of MB megabytes (HBM counter calibration)")
     p.add_argument("--no-extras", action="store_true",
                    help="skip the multichannel, batched and latency comparisons")
-    p.add_argument("--only", type=str, default="", help="run one extra section only (c1, c3, c4, c5, f4; f3 runs only when named)")
+    p.add_argument("--only", type=str, default="", help="run one extra section only (c1, c3, c4, c5, f2, f4; f3 runs only when named)")
     p.add_argument("--device-warmup-s", type=float, default=1.5,
                    help="seconds of untimed steps before the warm-up steps (device clock ramp)")
     return p.parse_args()
@@ -569,10 +569,38 @@ def extra_f3_capacity():
     return out
 
 
+def extra_f2_offline():
+    """Off-line whole-signal convolution (taches_convolve, one call over all
+    blocks and the temporal overflow): the main step's signal with IR_A
+    (no swaps), and a short input (0.1 s) with a long IR (2^22 taps) with
+    and without exchanging the roles of input and IR."""
+    import torch
+    from paper_2401_01607_amd import taches as T
+    from paper_2401_01607_amd import workloads as W
+    res = {}
+    cases = (("signal_10s_ir_65536", W.signal_gauss(480_000, 201), W.impulse_response(65_536, 202), (False,)),
+             ("signal_0.1s_ir_4M", W.signal_gauss(4_800, 205), W.impulse_response(1 << 22, 206), (False, True)))
+    for name, x, h, swaps in cases:
+        xd = torch.from_numpy(x).cuda()
+        hd = torch.from_numpy(h).cuda()
+        yd = torch.empty(x.size + h.size - 1, device="cuda")
+        for swap in swaps:
+            ts = []
+            for rep in range(4):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                assert T.taches_convolve(xd, hd, yd, role_swap=swap) == T.TACHES_OK
+                ts.append(time.perf_counter() - t0)
+            t = float(np.median(ts[1:]))
+            res[name + ("_roles_exchanged" if swap else "")] = {
+                "ms": round(t * 1e3, 3), "gmacs": round(x.size * h.size / t / 1e9, 1)}
+    return res
+
+
 def extras(args):
     out = {}
     sections = {"c1": extra_c1_latency, "c3": extra_c3_split_vs_fp32, "c4": extra_c4_batched_vs_plain,
-                "c5": extra_c5_serving, "f4": extra_f4_zero_bypass}
+                "c5": extra_c5_serving, "f2": extra_f2_offline, "f4": extra_f4_zero_bypass}
     if args.only == "f3":
         sections = {"f3": extra_f3_capacity}     # on request only: about a minute
     for name, fn in sections.items():

@@ -168,6 +168,24 @@ int taches_process_blocks(taches_stream* s, const float* x_dev, float* y_dev, in
 int taches_process_blocks_at(taches_stream* s, const float* x_dev, float* y_dev, int32_t n_blocks,
                              const int32_t* ir_slot_of_block, const int32_t* offset_of_block);
 
+/* ---- off-line mode ---------------------------------------------------------
+ *
+ * Whole-signal convolution, the paper's measured setting (files convolved
+ * off-line, Section 5.1): y = x * h for `channels` channels sharing h, one
+ * launch of the same kernels over all blocks plus the temporal overflow.
+ * x_dev: [channels][nx] planar device buffer; h_dev: nh device taps;
+ * y_dev: [channels][nx + nh - 1] planar device buffer (written in full).
+ * precision: TACHES_PREC_FP32 or TACHES_PREC_SPLIT_BF16.  role_swap != 0
+ * with one channel and nh > nx exchanges the roles of input and IR (Section
+ * 3.2, Fig. 6): the shorter operand becomes the IR, so min(nx, nh) taches
+ * of max(nx, nh) taps are scattered; the result is the same convolution up
+ * to rounding order.  Runs on
+ * hip_stream (NULL = HIP's null stream) of `device`, allocates its work
+ * buffers itself and returns when y is written.  TACHES_EINVAL for NULL
+ * buffers or bad sizes, TACHES_ENOMEM, TACHES_EDEVICE. */
+int taches_convolve(const float* x_dev, int64_t nx, int32_t channels, const float* h_dev, int32_t nh, float* y_dev,
+                    int32_t precision, int32_t role_swap, int32_t device, void* hip_stream);
+
 /* ---- state ------------------------------------------------------------- */
 
 typedef struct taches_info {

@@ -709,6 +709,71 @@ int taches_process_blocks(taches_stream* s, const float* x_dev, float* y_dev, in
   return process_common(s, x_dev, y_dev, n_blocks, ir_slot_of_block);
 }
 
+int taches_convolve(const float* x_dev, int64_t nx, int32_t channels, const float* h_dev, int32_t nh, float* y_dev,
+                    int32_t precision, int32_t role_swap, int32_t device, void* hip_stream) {
+  if (!x_dev || !h_dev || !y_dev) return fail(TACHES_EINVAL, "NULL buffer");
+  if (nx < 1 || nh < 1 || channels < 1) return fail(TACHES_EINVAL, "nx, nh and channels must be >= 1");
+  // exchanging the roles (Section 3.2, Fig. 6) needs one channel: with C
+  // channels sharing h, x would become C different IRs
+  const bool swap = role_swap != 0 && channels == 1 && (int64_t)nh > nx;
+  const float* sig = swap ? h_dev : x_dev;
+  const float* ir = swap ? x_dev : h_dev;
+  const int64_t ns = swap ? nh : nx;
+  const int64_t L = swap ? nx : nh;
+  const int64_t n_out = nx + nh - 1;
+  const int B = 256;
+  // the input blocks in one call, then the temporal overflow drained with
+  // zero input in a second (no input samples to walk)
+  const int64_t n_in = (ns + B - 1) / B;
+  const int64_t n_drain = (n_out - n_in * B + B - 1) / B;   // may be <= 0
+  const int64_t nblk = n_in + std::max<int64_t>(n_drain, 0);
+  if (nblk > INT32_MAX || L > INT32_MAX) return fail(TACHES_EINVAL, "signal too long");
+  taches_config cfg;
+  taches_config_default(&cfg, B, (int32_t)L);
+  cfg.channels = channels;
+  cfg.max_blocks_per_call = (int32_t)std::max<int64_t>(n_in, n_drain);
+  cfg.precision = precision;
+  cfg.device = device;
+  if (validate(&cfg) != TACHES_OK) return TACHES_EINVAL;
+  taches_stream* s = taches_open_ex(&cfg);
+  if (!s) return TACHES_ENOMEM;
+  int rc = taches_set_hip_stream(s, hip_stream);
+  float *xp = nullptr, *yp = nullptr;
+  const size_t xrow = (size_t)n_in * B * 4, yrow = (size_t)nblk * B * 4;
+  if (rc == TACHES_OK) rc = set_ir_common(s, ir, (int32_t)L, true);
+  if (rc == TACHES_OK && hipMalloc((void**)&xp, xrow * channels) != hipSuccess) rc = fail(TACHES_ENOMEM, "input buffer");
+  if (rc == TACHES_OK && hipMalloc((void**)&yp, yrow * channels) != hipSuccess) rc = fail(TACHES_ENOMEM, "output buffer");
+  if (rc == TACHES_OK) {
+    // zero-padded input [C][n_in*B]; the output is cut back to nx + nh - 1
+    hipError_t e = hipMemsetAsync(xp, 0, xrow * channels, s->stream);
+    if (e == hipSuccess)
+      e = hipMemcpy2DAsync(xp, xrow, sig, (size_t)ns * 4, (size_t)ns * 4, channels, hipMemcpyDeviceToDevice, s->stream);
+    if (e != hipSuccess) rc = fail(TACHES_EDEVICE, "input copy: %s", hipGetErrorString(e));
+  }
+  // the input call writes [C][n_in*B] into a packed buffer, the drain its
+  // [C][n_drain*B]; both are then copied out channel by channel
+  float* yd = yp + (size_t)channels * n_in * B;
+  if (rc == TACHES_OK) rc = process_common(s, xp, yp, (int)n_in, nullptr);
+  if (rc == TACHES_OK && n_drain > 0) rc = process_common(s, nullptr, yd, (int)n_drain, nullptr);
+  if (rc == TACHES_OK) {
+    const int64_t first = std::min<int64_t>(n_in * B, n_out);
+    hipError_t e = hipMemcpy2DAsync(y_dev, (size_t)n_out * 4, yp, xrow, (size_t)first * 4, channels,
+                                    hipMemcpyDeviceToDevice, s->stream);
+    if (e == hipSuccess && n_out > first)
+      e = hipMemcpy2DAsync(y_dev + first, (size_t)n_out * 4, yd, (size_t)n_drain * B * 4, (size_t)(n_out - first) * 4,
+                           channels, hipMemcpyDeviceToDevice, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) rc = fail(TACHES_EDEVICE, "output copy: %s", hipGetErrorString(e));
+  }
+  (void)hipStreamSynchronize(s->stream);
+  (void)hipFree(xp);
+  (void)hipFree(yp);
+  std::string keep = g_err;
+  (void)taches_close(s);
+  g_err = keep;
+  return rc;
+}
+
 int taches_process_blocks_at(taches_stream* s, const float* x_dev, float* y_dev, int32_t n_blocks,
                              const int32_t* ir_slot_of_block, const int32_t* offset_of_block) {
   if (!s) return fail(TACHES_EINVAL, "stream is NULL");
