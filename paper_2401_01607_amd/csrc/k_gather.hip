@@ -493,7 +493,9 @@ __global__ __launch_bounds__(64 * W) void k_gather(GatherCall d, int n_tiles) {
 // [wg_begin[b], wg_begin[b+1]) of a host-built list (balanced over
 // workgroups), each item a run of consecutive output tiles of one channel of
 // one call; each call's tail type is chosen per stream.
-template <int R>
+// MIXED: some calls keep an FP64 tail (both tail types compiled in);
+// otherwise the FP32-tail code alone, which needs fewer registers.
+template <int R, bool MIXED>
 __global__ __launch_bounds__(64) void k_gather_batched(const unsigned char* __restrict__ table) {
   const BatchHeader hd = *reinterpret_cast<const BatchHeader*>(table);
   const GatherCall* __restrict__ calls = reinterpret_cast<const GatherCall*>(table + hd.off_calls);
@@ -504,13 +506,17 @@ __global__ __launch_bounds__(64) void k_gather_batched(const unsigned char* __re
   const int it0 = wg_begin[b], it1 = wg_begin[b + 1];
   for (int it = it0; it < it1; ++it) {
     const WorkItem wi = items[it];
-    const GatherCall d = calls[wi.call];
-    const bool f64 = call_fp64[wi.call] != 0;
+    const GatherCall& d = calls[wi.call];   // read in place (a local copy would spill)
+    const bool f64 = MIXED && call_fp64[wi.call] != 0;
     for (int t = wi.tile; t < wi.tile + wi.count; ++t) {
-      if (f64)
-        gather_tile<R, 1, double>(d, wi.channel, t);
-      else
+      if constexpr (MIXED) {
+        if (f64)
+          gather_tile<R, 1, double>(d, wi.channel, t);
+        else
+          gather_tile<R, 1, float>(d, wi.channel, t);
+      } else {
         gather_tile<R, 1, float>(d, wi.channel, t);
+      }
       __syncthreads();
     }
   }
@@ -539,9 +545,12 @@ hipError_t launch_r(const GatherCall& call, bool fp64, int w, hipStream_t st) {
 }
 
 template <int R>
-hipError_t launch_batched_r(const unsigned char* table_dev, int n_wg, hipStream_t st) {
+hipError_t launch_batched_r(const unsigned char* table_dev, int n_wg, bool mixed, hipStream_t st) {
   constexpr int shmem = lds_bytes<R, 1>();
-  hipLaunchKernelGGL(k_gather_batched<R>, dim3(n_wg), dim3(64), shmem, st, table_dev);
+  if (mixed)
+    hipLaunchKernelGGL((k_gather_batched<R, true>), dim3(n_wg), dim3(64), shmem, st, table_dev);
+  else
+    hipLaunchKernelGGL((k_gather_batched<R, false>), dim3(n_wg), dim3(64), shmem, st, table_dev);
   return hipGetLastError();
 }
 
@@ -558,26 +567,32 @@ hipError_t launch_gather(const GatherCall& call, bool tail_fp64, int r, int w, h
   }
 }
 
-int gather_batched_waves_per_cu(int r) {
+template <int R>
+int batched_occupancy(bool mixed) {
   int n = 0;
-  hipError_t e = hipErrorInvalidValue;
-  switch (r) {
-    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gather_batched<4>, 64, lds_bytes<4, 1>()); break;
-    case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gather_batched<8>, 64, lds_bytes<8, 1>()); break;
-    case 12: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gather_batched<12>, 64, lds_bytes<12, 1>()); break;
-    case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gather_batched<16>, 64, lds_bytes<16, 1>()); break;
-    default: break;
-  }
+  const hipError_t e =
+      mixed ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gather_batched<R, true>, 64, lds_bytes<R, 1>())
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gather_batched<R, false>, 64, lds_bytes<R, 1>());
   return (e == hipSuccess && n > 0) ? n : 8;
 }
 
-hipError_t launch_gather_batched(const unsigned char* table_dev, int n_wg, int r, hipStream_t st) {
+int gather_batched_waves_per_cu(int r, bool mixed) {
+  switch (r) {
+    case 4: return batched_occupancy<4>(mixed);
+    case 8: return batched_occupancy<8>(mixed);
+    case 12: return batched_occupancy<12>(mixed);
+    case 16: return batched_occupancy<16>(mixed);
+    default: return 8;
+  }
+}
+
+hipError_t launch_gather_batched(const unsigned char* table_dev, int n_wg, int r, bool mixed, hipStream_t st) {
   if (n_wg <= 0) return hipSuccess;
   switch (r) {
-    case 4: return launch_batched_r<4>(table_dev, n_wg, st);
-    case 8: return launch_batched_r<8>(table_dev, n_wg, st);
-    case 12: return launch_batched_r<12>(table_dev, n_wg, st);
-    case 16: return launch_batched_r<16>(table_dev, n_wg, st);
+    case 4: return launch_batched_r<4>(table_dev, n_wg, mixed, st);
+    case 8: return launch_batched_r<8>(table_dev, n_wg, mixed, st);
+    case 12: return launch_batched_r<12>(table_dev, n_wg, mixed, st);
+    case 16: return launch_batched_r<16>(table_dev, n_wg, mixed, st);
     default: return hipErrorInvalidValue;
   }
 }

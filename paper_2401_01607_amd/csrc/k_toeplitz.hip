@@ -123,7 +123,11 @@ __device__ __forceinline__ void rev_load(const BlockIR& ir, int top, int tid, Re
   }
 }
 
-template <typename TailT>
+// Wave layout: the workgroup's MT x cpad result is cut into 4 wave tiles of
+// NM*32 rows x NN*32 channels.  Every K-step a wave reads NM A fragments
+// (LDS) and NN pairs of B fragments (global, hi and lo) and issues 3*NM*NN
+// MFMAs, so taller wave tiles (NM = 2) halve the global B traffic per MFMA.
+template <typename TailT, int NM, int NN>
 __global__ __launch_bounds__(256) void k_toeplitz(GatherCall d, int n_tiles) {
   __shared__ __attribute__((aligned(16))) uint16_t cp_hi[8 * CP_LEN];
   __shared__ __attribute__((aligned(16))) uint16_t cp_lo[8 * CP_LEN];
@@ -138,24 +142,31 @@ __global__ __launch_bounds__(256) void k_toeplitz(GatherCall d, int n_tiles) {
   const int n0 = tile * MT;
   const int cpad = d.cpad;
   TailT* ring = reinterpret_cast<TailT*>(d.ring);
-
-  // accumulators: two 32x32 result tiles (channels 0-31, 32-63); lane l holds
-  // column l%32 and rows 8*(q/4) + 4*(l/32) + q%4 of its wave's 32 rows
-  TailT acc[2][16];
+  // this wave's tile: rows r0 .. r0 + 32*NM - 1, channels c0 .. c0 + 32*NN - 1
+  constexpr int WN = 64 / (32 * NN) > 0 ? 64 / (32 * NN) : 1;   // wave columns for 64 channels
+  const int wn = (cpad == 64) ? w % WN : 0;
+  const int wm = (cpad == 64) ? w / WN : w;
+  const int r0 = 32 * NM * wm;
+  const int c0 = 32 * NN * wn;
+  // accumulators: NM x NN 32x32 result tiles; lane l holds column l%32 and
+  // rows 8*(q/4) + 4*(l/32) + q%4 of each tile
+  TailT acc[NM][NN][16];
 #pragma unroll
-  for (int nt = 0; nt < 2; ++nt)
+  for (int mt = 0; mt < NM; ++mt)
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int n = n0 + 32 * w + 8 * (q >> 2) + 4 * kg + (q & 3);
-      const int c = 32 * nt + i;
-      TailT v = 0;
-      if (n < d.live_in && c < cpad) {
-        int slot = d.head + n;
-        if (slot >= d.Rcap) slot -= d.Rcap;
-        v = ring[(int64_t)slot * cpad + c];
+    for (int nt = 0; nt < NN; ++nt)
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int n = n0 + r0 + 32 * mt + 8 * (q >> 2) + 4 * kg + (q & 3);
+        const int c = c0 + 32 * nt + i;
+        TailT v = 0;
+        if (n < d.live_in && c < cpad) {
+          int slot = d.head + n;
+          if (slot >= d.Rcap) slot -= d.Rcap;
+          v = ring[(int64_t)slot * cpad + c];
+        }
+        acc[mt][nt][q] = v;
       }
-      acc[nt][q] = v;
-    }
 
   RevPrefetch pf;
   bool pf_valid = false;
@@ -224,35 +235,42 @@ __global__ __launch_bounds__(256) void k_toeplitz(GatherCall d, int n_tiles) {
         pf_valid = true;
         break;
       }
-      f32x16 p0 = {}, p1 = {};
+      f32x16 p[NM][NN];
+#pragma unroll
+      for (int mt = 0; mt < NM; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NN; ++nt) p[mt][nt] = f32x16{};
       const uint16_t* xh = d.xs_hi + ((int64_t)ck * 32) * cpad * 8;
       const uint16_t* xl = d.xs_lo + ((int64_t)ck * 32) * cpad * 8;
       const int ksteps = chp >> 4;
-      // B fragments (8 samples of channel 32*nt + i, k-group 2t + kg) are
-      // loaded two K-steps ahead into a ring of three register buffers
-      BFrag bf[3];
-      auto load_b = [&](int t, BFrag& f) {
-        const int64_t xo = ((int64_t)(2 * t + kg) * cpad + i) * 8;
-        f.h0 = *reinterpret_cast<const bf16x8*>(xh + xo);
-        f.l0 = *reinterpret_cast<const bf16x8*>(xl + xo);
-        if (cpad > 32) {
-          f.h1 = *reinterpret_cast<const bf16x8*>(xh + xo + 32 * 8);
-          f.l1 = *reinterpret_cast<const bf16x8*>(xl + xo + 32 * 8);
+      // B fragments (8 samples of channel c0 + 32*nt + i, k-group 2t + kg)
+      // are loaded two K-steps ahead into a ring of three register buffers
+      struct BF {
+        bf16x8 h[NN], l[NN];
+      };
+      BF bf[3];
+      auto load_b = [&](int t, BF& f) {
+        const int64_t xo = ((int64_t)(2 * t + kg) * cpad + c0 + i) * 8;
+#pragma unroll
+        for (int nt = 0; nt < NN; ++nt) {
+          f.h[nt] = *reinterpret_cast<const bf16x8*>(xh + xo + nt * 32 * 8);
+          f.l[nt] = *reinterpret_cast<const bf16x8*>(xl + xo + nt * 32 * 8);
         }
       };
-      auto kstep = [&](int t, const BFrag& f) {
-        // A fragment: taps for rows n0+32w+i and samples m_lo+16t+8kg+j
-        const int a = MT - 1 - 32 * w - i + 16 * t + 8 * kg;
-        const int aoff = (a & 7) * CP_LEN + (a & ~7);
-        const bf16x8 ah = *reinterpret_cast<const bf16x8*>(cp_hi + aoff);
-        const bf16x8 al = *reinterpret_cast<const bf16x8*>(cp_lo + aoff);
-        p0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, f.h0, p0, 0, 0, 0);
-        p0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, f.l0, p0, 0, 0, 0);
-        p0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, f.h0, p0, 0, 0, 0);
-        if (cpad > 32) {
-          p1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, f.h1, p1, 0, 0, 0);
-          p1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, f.l1, p1, 0, 0, 0);
-          p1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, f.h1, p1, 0, 0, 0);
+      auto kstep = [&](int t, const BF& f) {
+#pragma unroll
+        for (int mt = 0; mt < NM; ++mt) {
+          // A fragment: taps for rows n0+r0+32mt+i and samples m_lo+16t+8kg+j
+          const int a = MT - 1 - r0 - 32 * mt - i + 16 * t + 8 * kg;
+          const int aoff = (a & 7) * CP_LEN + (a & ~7);
+          const bf16x8 ah = *reinterpret_cast<const bf16x8*>(cp_hi + aoff);
+          const bf16x8 al = *reinterpret_cast<const bf16x8*>(cp_lo + aoff);
+#pragma unroll
+          for (int nt = 0; nt < NN; ++nt) {
+            p[mt][nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, f.h[nt], p[mt][nt], 0, 0, 0);
+            p[mt][nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, f.l[nt], p[mt][nt], 0, 0, 0);
+            p[mt][nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, f.h[nt], p[mt][nt], 0, 0, 0);
+          }
         }
       };
       if (ksteps == KC / 16) {
@@ -270,30 +288,33 @@ __global__ __launch_bounds__(256) void k_toeplitz(GatherCall d, int n_tiles) {
         }
       }
 #pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        acc[0][q] += (TailT)p0[q];
-        acc[1][q] += (TailT)p1[q];
-      }
+      for (int mt = 0; mt < NM; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NN; ++nt)
+#pragma unroll
+          for (int q = 0; q < 16; ++q) acc[mt][nt][q] += (TailT)p[mt][nt][q];
     }
   }
 
 #pragma unroll
-  for (int nt = 0; nt < 2; ++nt)
+  for (int mt = 0; mt < NM; ++mt)
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int n = n0 + 32 * w + 8 * (q >> 2) + 4 * kg + (q & 3);
-      const int c = 32 * nt + i;
-      if (n < d.n_out && c < cpad) {
-        int slot = d.head + n;
-        if (slot >= d.Rcap) slot -= d.Rcap;
-        if (n < d.S) {
-          if (c < d.channels) d.y[(int64_t)c * d.y_cstride + n] = (float)acc[nt][q];
-          ring[(int64_t)slot * cpad + c] = (TailT)0;
-        } else {
-          ring[(int64_t)slot * cpad + c] = acc[nt][q];
+    for (int nt = 0; nt < NN; ++nt)
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int n = n0 + r0 + 32 * mt + 8 * (q >> 2) + 4 * kg + (q & 3);
+        const int c = c0 + 32 * nt + i;
+        if (n < d.n_out && c < cpad) {
+          int slot = d.head + n;
+          if (slot >= d.Rcap) slot -= d.Rcap;
+          if (n < d.S) {
+            if (c < d.channels) d.y[(int64_t)c * d.y_cstride + n] = (float)acc[mt][nt][q];
+            ring[(int64_t)slot * cpad + c] = (TailT)0;
+          } else {
+            ring[(int64_t)slot * cpad + c] = acc[mt][nt][q];
+          }
         }
       }
-    }
 }
 
 }  // namespace
@@ -320,10 +341,20 @@ hipError_t launch_toeplitz(const GatherCall& call, bool tail_fp64, hipStream_t s
     if (e != hipSuccess) return e;
   }
   const int n_tiles = (call.n_out + MT - 1) / MT;
-  if (tail_fp64)
-    hipLaunchKernelGGL(k_toeplitz<double>, dim3(n_tiles), dim3(256), 0, st, call, n_tiles);
-  else
-    hipLaunchKernelGGL(k_toeplitz<float>, dim3(n_tiles), dim3(256), 0, st, call, n_tiles);
+  // 32 channels: one 32x32 tile per wave; 64 channels: 32 rows x 64 channels
+  // per wave (64 x 32 wave tiles need one wave per SIMD and ran no faster)
+  const bool wide = call.cpad > 32;
+  if (tail_fp64) {
+    if (wide)
+      hipLaunchKernelGGL((k_toeplitz<double, 1, 2>), dim3(n_tiles), dim3(256), 0, st, call, n_tiles);
+    else
+      hipLaunchKernelGGL((k_toeplitz<double, 1, 1>), dim3(n_tiles), dim3(256), 0, st, call, n_tiles);
+  } else {
+    if (wide)
+      hipLaunchKernelGGL((k_toeplitz<float, 1, 2>), dim3(n_tiles), dim3(256), 0, st, call, n_tiles);
+    else
+      hipLaunchKernelGGL((k_toeplitz<float, 1, 1>), dim3(n_tiles), dim3(256), 0, st, call, n_tiles);
+  }
   return hipGetLastError();
 }
 

@@ -77,12 +77,13 @@ hipError_t launch_gather(const GatherCall& call, bool tail_fp64, int r, int w, h
 struct BatchHeader {
   int32_t off_calls, off_fp64, off_wgb, off_items;
 };
-hipError_t launch_gather_batched(const unsigned char* table_dev, int n_wg, int r, hipStream_t st);
+// mixed: some calls of the table keep an FP64 tail.
+hipError_t launch_gather_batched(const unsigned char* table_dev, int n_wg, int r, bool mixed, hipStream_t st);
 
 inline int tile_outputs(int r) { return 64 * r; }
 
 // Resident one-wave workgroups per CU of the batched gather kernel.
-int gather_batched_waves_per_cu(int r);
+int gather_batched_waves_per_cu(int r, bool mixed);
 
 // IR staging for the split-BF16 path (k_toeplitz.hip): hi = RN_bf16(h),
 // lo = RN_bf16(h - hi), bit patterns stored as uint16.

@@ -902,6 +902,7 @@ struct taches_pool {
   hipGraphExec_t exec = nullptr;
   hipGraphNode_t copy_node = nullptr;
   int graph_r = 0, graph_nwg = 0;
+  bool graph_mixed = false;
   size_t graph_cap = 0;
   int64_t replays = 0;
   int last_items = 0, last_wg = 0, last_r = 0;
@@ -977,14 +978,14 @@ int pool_reserve(taches_pool* p, size_t bytes) {
 // Longer tiles need fewer LDS reads per FMA; the largest one that still
 // leaves about four items per resident workgroup keeps the greedy balance
 // tight.
-int pool_pick_r(const taches_pool* p, const std::vector<const GatherCall*>& calls) {
+int pool_pick_r(const taches_pool* p, const std::vector<const GatherCall*>& calls, bool mixed) {
   if (p->force_r) return p->force_r;
   static const int rs[4] = {16, 12, 8, 4};
   for (int r : rs) {
     const int64_t T = 64 * r;
     int64_t items = 0;
     for (const GatherCall* g : calls) items += (int64_t)g->channels * ((g->n_out + T - 1) / T);
-    if (items >= 4LL * 256 * taches::gather_batched_waves_per_cu(r)) return r;
+    if (items >= 4LL * 256 * taches::gather_batched_waves_per_cu(r, mixed)) return r;
   }
   return 4;
 }
@@ -1163,7 +1164,9 @@ int taches_pool_step_strided(taches_pool* p, int32_t n, taches_stream* const* st
     }
   }
   if (!gather_ids.empty()) {
-    const int r = pool_pick_r(p, gcalls);
+    bool mixed = false;   // some stream keeps an FP64 tail
+    for (int i : gather_ids) mixed |= streams[i]->tail_fp64;
+    const int r = pool_pick_r(p, gcalls, mixed);
     const int64_t T = 64 * r;
     // work items: runs of consecutive output tiles of one channel of one
     // call, with their FMA count (plus the tail read/write)
@@ -1182,7 +1185,7 @@ int taches_pool_step_strided(taches_pool* p, int32_t n, taches_stream* const* st
       }
       return work;
     };
-    const int per_cu = taches::gather_batched_waves_per_cu(r);
+    const int per_cu = taches::gather_batched_waves_per_cu(r, mixed);
     const int64_t wg_max = 256LL * per_cu;
     int64_t n_tiles = 0, tiles_work = 0, tile_max = 1;
     for (int k = 0; k < ng; ++k) {
@@ -1326,11 +1329,12 @@ int taches_pool_step_strided(taches_pool* p, int32_t n, taches_stream* const* st
     if (p->use_graph) {
       // capture [table copy -> batched kernel] once per (tile, workgroups,
       // table capacity); later steps only resize the copy and replay
-      if (!p->exec || p->graph_r != r || p->graph_nwg != nwg || p->graph_cap != p->tab_cap) {
+      if (!p->exec || p->graph_r != r || p->graph_nwg != nwg || p->graph_cap != p->tab_cap ||
+          p->graph_mixed != mixed) {
         pool_drop_graph(p);
         HIPCHK(hipStreamBeginCapture(p->capture, hipStreamCaptureModeThreadLocal));
         hipError_t e1 = hipMemcpyAsync(p->tab_dev, p->tab_pin, p->tab_cap, hipMemcpyHostToDevice, p->capture);
-        hipError_t e2 = taches::launch_gather_batched(p->tab_dev, nwg, r, p->capture);
+        hipError_t e2 = taches::launch_gather_batched(p->tab_dev, nwg, r, mixed, p->capture);
         hipError_t e3 = hipStreamEndCapture(p->capture, &p->graph);
         if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess)
           return fail(TACHES_EDEVICE, "graph capture failed: %s", hipGetErrorString(e1 != hipSuccess ? e1 : e2 != hipSuccess ? e2 : e3));
@@ -1345,6 +1349,7 @@ int taches_pool_step_strided(taches_pool* p, int32_t n, taches_stream* const* st
           if (ty == hipGraphNodeTypeMemcpy) p->copy_node = nd;
         }
         p->graph_r = r;
+        p->graph_mixed = mixed;
         p->graph_nwg = nwg;
         p->graph_cap = p->tab_cap;
       }
@@ -1358,7 +1363,7 @@ int taches_pool_step_strided(taches_pool* p, int32_t n, taches_stream* const* st
     }
     if (!launched) {
       HIPCHK(hipMemcpyAsync(p->tab_dev, p->tab_pin, bytes, hipMemcpyHostToDevice, p->stream));
-      hipError_t e = taches::launch_gather_batched(p->tab_dev, nwg, r, p->stream);
+      hipError_t e = taches::launch_gather_batched(p->tab_dev, nwg, r, mixed, p->stream);
       if (e != hipSuccess) return fail(TACHES_EDEVICE, "batched launch: %s", hipGetErrorString(e));
     }
     HIPCHK(hipEventRecord(p->ev_end, p->stream));
