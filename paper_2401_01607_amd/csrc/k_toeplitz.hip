@@ -38,12 +38,13 @@ struct BFrag {
   bf16x8 h0, l0, h1, l1;  // hi/lo B fragments of the two 32-channel tiles
 };
 
-constexpr int MT = 128;                    // output slots per workgroup (4 waves x 32)
+constexpr int MT = 128;                    // output slots per workgroup (MT / 32 waves x 32 rows)
+constexpr int NT = 2 * MT;                 // threads per workgroup
 constexpr int KC = CHUNK_MAX;              // longest chunk (samples)
 constexpr int CP_LEN = MT + KC + 16;       // elements per shifted copy (>= MT + KC + 7)
 constexpr int REV_LEN = CP_LEN + 16;       // reversed window staged once per chunk
-constexpr int REV_PER_THREAD = (REV_LEN + 255) / 256;
-static_assert(CP_LEN % 8 == 0 && 2 * (CP_LEN / 8) <= 256, "copy-building needs one group per thread");
+constexpr int REV_PER_THREAD = (REV_LEN + NT - 1) / NT;
+static_assert(CP_LEN % 8 == 0 && 2 * (CP_LEN / 8) <= NT, "copy-building needs one group per thread");
 
 // Round an FP32 value to the nearest BF16 (ties to even); returns the bits.
 __device__ __forceinline__ uint16_t bf16_rn(float v) {
@@ -116,8 +117,8 @@ struct RevPrefetch {
 __device__ __forceinline__ void rev_load(const BlockIR& ir, int top, int tid, RevPrefetch& pf) {
 #pragma unroll
   for (int j = 0; j < REV_PER_THREAD; ++j) {
-    const int hidx = top - (tid + 256 * j);
-    const bool ok = tid + 256 * j < REV_LEN && hidx >= 0 && hidx < ir.L;
+    const int hidx = top - (tid + NT * j);
+    const bool ok = tid + NT * j < REV_LEN && hidx >= 0 && hidx < ir.L;
     pf.hi[j] = ok ? ir.h_hi[hidx] : (uint16_t)0;
     pf.lo[j] = ok ? ir.h_lo[hidx] : (uint16_t)0;
   }
@@ -128,7 +129,7 @@ __device__ __forceinline__ void rev_load(const BlockIR& ir, int top, int tid, Re
 // (LDS) and NN pairs of B fragments (global, hi and lo) and issues 3*NM*NN
 // MFMAs, so taller wave tiles (NM = 2) halve the global B traffic per MFMA.
 template <typename TailT, int NM, int NN>
-__global__ __launch_bounds__(256) void k_toeplitz(GatherCall d, int n_tiles) {
+__global__ __launch_bounds__(NT) void k_toeplitz(GatherCall d, int n_tiles) {
   __shared__ __attribute__((aligned(16))) uint16_t cp_hi[8 * CP_LEN];
   __shared__ __attribute__((aligned(16))) uint16_t cp_lo[8 * CP_LEN];
   __shared__ __attribute__((aligned(16))) uint16_t rev_hi[REV_LEN];
@@ -171,6 +172,22 @@ __global__ __launch_bounds__(256) void k_toeplitz(GatherCall d, int n_tiles) {
   RevPrefetch pf;
   bool pf_valid = false;
   int pf_ck = -1;
+  // B fragments (8 samples of channel c0 + 32*nt + i, k-group 2t + kg) go
+  // through a ring of three register buffers, two K-steps ahead; the first
+  // two K-steps of a chunk are loaded during the previous chunk's tail
+  struct BF {
+    bf16x8 h[NN], l[NN];
+  };
+  BF bf[3];
+  int b_pre = -1;   // chunk whose K-steps 0 and 1 are already in bf[0], bf[1]
+  auto load_b_at = [&](int chunk, int t, BF& f) {
+    const int64_t xo = (((int64_t)chunk * 32 + 2 * t + kg) * cpad + c0 + i) * 8;
+#pragma unroll
+    for (int nt = 0; nt < NN; ++nt) {
+      f.h[nt] = *reinterpret_cast<const bf16x8*>(d.xs_hi + xo + nt * 32 * 8);
+      f.l[nt] = *reinterpret_cast<const bf16x8*>(d.xs_lo + xo + nt * 32 * 8);
+    }
+  };
   if (d.x != nullptr) {
     const int lo = n0 - (d.Lmax_call - 1);
     const int b_first = lo <= 0 ? 0 : lo / d.B;
@@ -190,7 +207,7 @@ __global__ __launch_bounds__(256) void k_toeplitz(GatherCall d, int n_tiles) {
       if (!pf_valid || pf_ck != ck) rev_load(ir, n0 - m_lo + MT - 1, tid, pf);
 #pragma unroll
       for (int j = 0; j < REV_PER_THREAD; ++j) {
-        const int u = tid + 256 * j;
+        const int u = tid + NT * j;
         if (u < REV_LEN) {
           rev_hi[u] = pf.hi[j];
           rev_lo[u] = pf.lo[j];
@@ -223,69 +240,98 @@ __global__ __launch_bounds__(256) void k_toeplitz(GatherCall d, int n_tiles) {
         }
       }
       __syncthreads();
-      // 3) prefetch the next reaching chunk's window during this chunk's MFMAs
+      // 3) the next reaching chunk: its window is prefetched into registers
+      //    after this chunk's last B loads are issued (the load counter is
+      //    in order, so earlier it would delay this chunk's first K-steps)
       pf_valid = false;
+      int nx_ck = -1, nx_top = 0, nx_len = 0;
+      BlockIR nx_ir{};
       for (int k2 = k + 1; k2 < nch; ++k2) {
         int m2, len2, b2;
         chunk_span(d, c_first + k2, m2, len2, b2);
         const BlockIR ir2 = d.irs ? d.irs[b2] : d.ir0;
         if (len2 <= 0 || m2 > n0 + MT - 1 || m2 + len2 + ir2.L - 2 < n0) continue;
-        rev_load(ir2, n0 - m2 + MT - 1, tid, pf);
-        pf_ck = c_first + k2;
-        pf_valid = true;
+        nx_ck = c_first + k2;
+        nx_top = n0 - m2 + MT - 1;
+        nx_len = len2;
+        nx_ir = ir2;
         break;
       }
+      auto prefetch_next = [&]() {
+        if (nx_ck >= 0) {
+          rev_load(nx_ir, nx_top, tid, pf);
+          pf_ck = nx_ck;
+          pf_valid = true;
+        }
+      };
       f32x16 p[NM][NN];
 #pragma unroll
       for (int mt = 0; mt < NM; ++mt)
 #pragma unroll
         for (int nt = 0; nt < NN; ++nt) p[mt][nt] = f32x16{};
-      const uint16_t* xh = d.xs_hi + ((int64_t)ck * 32) * cpad * 8;
-      const uint16_t* xl = d.xs_lo + ((int64_t)ck * 32) * cpad * 8;
       const int ksteps = chp >> 4;
-      // B fragments (8 samples of channel c0 + 32*nt + i, k-group 2t + kg)
-      // are loaded two K-steps ahead into a ring of three register buffers
-      struct BF {
-        bf16x8 h[NN], l[NN];
+      auto load_b = [&](int t, BF& f) { load_b_at(ck, t, f); };
+      // A fragments: taps for rows n0+r0+32mt+i and samples m_lo+16t+8kg+j
+      struct AF {
+        bf16x8 h[NM], l[NM];
       };
-      BF bf[3];
-      auto load_b = [&](int t, BF& f) {
-        const int64_t xo = ((int64_t)(2 * t + kg) * cpad + c0 + i) * 8;
-#pragma unroll
-        for (int nt = 0; nt < NN; ++nt) {
-          f.h[nt] = *reinterpret_cast<const bf16x8*>(xh + xo + nt * 32 * 8);
-          f.l[nt] = *reinterpret_cast<const bf16x8*>(xl + xo + nt * 32 * 8);
-        }
-      };
-      auto kstep = [&](int t, const BF& f) {
+      auto load_a = [&](int t, AF& af) {
 #pragma unroll
         for (int mt = 0; mt < NM; ++mt) {
-          // A fragment: taps for rows n0+r0+32mt+i and samples m_lo+16t+8kg+j
           const int a = MT - 1 - r0 - 32 * mt - i + 16 * t + 8 * kg;
           const int aoff = (a & 7) * CP_LEN + (a & ~7);
-          const bf16x8 ah = *reinterpret_cast<const bf16x8*>(cp_hi + aoff);
-          const bf16x8 al = *reinterpret_cast<const bf16x8*>(cp_lo + aoff);
-#pragma unroll
-          for (int nt = 0; nt < NN; ++nt) {
-            p[mt][nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, f.h[nt], p[mt][nt], 0, 0, 0);
-            p[mt][nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, f.l[nt], p[mt][nt], 0, 0, 0);
-            p[mt][nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, f.h[nt], p[mt][nt], 0, 0, 0);
-          }
+          af.h[mt] = *reinterpret_cast<const bf16x8*>(cp_hi + aoff);
+          af.l[mt] = *reinterpret_cast<const bf16x8*>(cp_lo + aoff);
         }
       };
+      auto mfmas = [&](const AF& af, const BF& f) {
+#pragma unroll
+        for (int mt = 0; mt < NM; ++mt)
+#pragma unroll
+          for (int nt = 0; nt < NN; ++nt) {
+            p[mt][nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af.h[mt], f.h[nt], p[mt][nt], 0, 0, 0);
+            p[mt][nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af.h[mt], f.l[nt], p[mt][nt], 0, 0, 0);
+            p[mt][nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af.l[mt], f.h[nt], p[mt][nt], 0, 0, 0);
+          }
+      };
+      auto kstep = [&](int t, const BF& f) {
+        AF af;
+        load_a(t, af);
+        mfmas(af, f);
+      };
       if (ksteps == KC / 16) {
-        load_b(0, bf[0]);
-        load_b(1, bf[1]);
+        // The scheduling barriers keep each K-step's loads ahead of the
+        // previous steps' MFMAs: without them the compiler sinks every load
+        // to just before its first use and each K-step waits for memory.
+        if (b_pre != ck) {
+          load_b(0, bf[0]);
+          load_b(1, bf[1]);
+        }
+        // A fragments come from LDS one K-step ahead (two-slot ring)
+        AF af[2];
+        load_a(0, af[0]);
 #pragma unroll
         for (int t = 0; t < KC / 16; ++t) {
           if (t + 2 < KC / 16) load_b(t + 2, bf[(t + 2) % 3]);
-          kstep(t, bf[t % 3]);
+          if (t == KC / 16 - 3) prefetch_next();
+          if (t + 1 < KC / 16) load_a(t + 1, af[(t + 1) % 2]);
+          __builtin_amdgcn_sched_barrier(0);
+          mfmas(af[t % 2], bf[t % 3]);
+          __builtin_amdgcn_sched_barrier(0);
         }
       } else {
         for (int t = 0; t < ksteps; ++t) {
           load_b(t, bf[0]);
           kstep(t, bf[0]);
         }
+        prefetch_next();
+      }
+      // the next chunk's first two K-steps fly during the fold and staging
+      b_pre = -1;
+      if (nx_ck >= 0 && nx_len == KC) {
+        load_b_at(nx_ck, 0, bf[0]);
+        load_b_at(nx_ck, 1, bf[1]);
+        b_pre = nx_ck;
       }
 #pragma unroll
       for (int mt = 0; mt < NM; ++mt)
@@ -341,19 +387,20 @@ hipError_t launch_toeplitz(const GatherCall& call, bool tail_fp64, hipStream_t s
     if (e != hipSuccess) return e;
   }
   const int n_tiles = (call.n_out + MT - 1) / MT;
-  // 32 channels: one 32x32 tile per wave; 64 channels: 32 rows x 64 channels
-  // per wave (64 x 32 wave tiles need one wave per SIMD and ran no faster)
+  // 32 channels: one 32x32 tile per wave; 64 channels: 64 rows x 32 channels
+  // per wave (each B fragment then feeds twice as many MFMAs: the vector
+  // memory traffic of the B fragments is what bounds this loop)
   const bool wide = call.cpad > 32;
   if (tail_fp64) {
     if (wide)
-      hipLaunchKernelGGL((k_toeplitz<double, 1, 2>), dim3(n_tiles), dim3(256), 0, st, call, n_tiles);
+      hipLaunchKernelGGL((k_toeplitz<double, 2, 1>), dim3(n_tiles), dim3(NT), 0, st, call, n_tiles);
     else
-      hipLaunchKernelGGL((k_toeplitz<double, 1, 1>), dim3(n_tiles), dim3(256), 0, st, call, n_tiles);
+      hipLaunchKernelGGL((k_toeplitz<double, 1, 1>), dim3(n_tiles), dim3(NT), 0, st, call, n_tiles);
   } else {
     if (wide)
-      hipLaunchKernelGGL((k_toeplitz<float, 1, 2>), dim3(n_tiles), dim3(256), 0, st, call, n_tiles);
+      hipLaunchKernelGGL((k_toeplitz<float, 2, 1>), dim3(n_tiles), dim3(NT), 0, st, call, n_tiles);
     else
-      hipLaunchKernelGGL((k_toeplitz<float, 1, 1>), dim3(n_tiles), dim3(256), 0, st, call, n_tiles);
+      hipLaunchKernelGGL((k_toeplitz<float, 1, 1>), dim3(n_tiles), dim3(NT), 0, st, call, n_tiles);
   }
   return hipGetLastError();
 }
