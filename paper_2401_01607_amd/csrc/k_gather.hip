@@ -30,6 +30,8 @@ namespace {
 // All LDS data lives in one dynamic array indexed by 32-bit float offsets.
 extern __shared__ __attribute__((aligned(16))) float g_lds[];
 typedef float vf4 __attribute__((ext_vector_type(4)));
+typedef float vf4u __attribute__((ext_vector_type(4))) __attribute__((aligned(4)));
+
 
 __device__ __forceinline__ vf4 lds_read4(int off) { return *reinterpret_cast<const vf4*>(&g_lds[off]); }
 __device__ __forceinline__ void lds_write4(int off, vf4 v) { *reinterpret_cast<vf4*>(&g_lds[off]) = v; }
@@ -156,18 +158,18 @@ __device__ __forceinline__ ChunkGeo chunk_geo(const GatherCall& d, int ck, int n
   int m_hi;
   if (d.ctab) {
     // an IR takes over inside some block: chunks come from the table
-    const int32_t* cd = d.ctab + (d.n_blocks + 1) + 3 * ck;
+    const GLB int32_t* cd = gr(d.ctab) + (d.n_blocks + 1) + 3 * ck;
     g.m_lo = cd[0];
     g.len = cd[1];
     m_hi = g.m_lo + g.len;
-    g.ir = d.irs[cd[2]];
+    g.ir = load_ir(d.irs, cd[2]);
   } else {
     const int b = ck / d.cpb;
     const int i = ck - b * d.cpb;
     g.m_lo = b * d.B + (i * d.B) / d.cpb;
     m_hi = b * d.B + ((i + 1) * d.B) / d.cpb;
     g.len = m_hi - g.m_lo;
-    g.ir = d.irs ? d.irs[b] : d.ir0;
+    g.ir = d.irs ? load_ir(d.irs, b) : d.ir0;
   }
   g.len_pad = (g.len + R - 1) / R * R;
   // the chunk's taches cover outputs [m_lo, m_hi - 1 + L - 1]
@@ -196,12 +198,12 @@ __device__ __forceinline__ ChunkGeo unit_geo(const GatherCall& d, int ck, int ck
     return g;
   }
   if (kmax == 1) return chunk_geo<R>(d, ck, n0);
-  g.ir = d.irs ? d.irs[ck] : d.ir0;
+  g.ir = d.irs ? load_ir(d.irs, ck) : d.ir0;
   int e = min(ck + kmax, ck_end);
   if (d.irs) {
     for (int b = ck + 1; b < e; ++b) {
-      const BlockIR o = d.irs[b];
-      if (o.h != g.ir.h || o.L != g.ir.L) {
+      const GLB BlockIR* o = gr(d.irs) + b;
+      if (o->h != g.ir.h || o->L != g.ir.L) {
         e = b;
         break;
       }
@@ -218,11 +220,7 @@ __device__ __forceinline__ ChunkGeo unit_geo(const GatherCall& d, int ck, int ck
 }
 
 // 16-byte load from a 4-byte-aligned global address.
-__device__ __forceinline__ float4 load4(const float* p) {
-  float4 v;
-  __builtin_memcpy(&v, p, sizeof v);
-  return v;
-}
+__device__ __forceinline__ vf4u load4(const GLB float* p) { return *reinterpret_cast<const GLB vf4u*>(p); }
 
 // One chunk's staged data on its way from global memory to LDS: each lane
 // holds two R-tap rows of the IR window (rows lane and lane + 64) and up to
@@ -238,11 +236,11 @@ struct Prefetch {
 // Row r of the staged window holds taps base + r*R .. base + r*R + R - 1,
 // base = n0 - m_lo - len_pad + 1; taps outside [0, L) are zero.
 template <int R>
-__device__ __forceinline__ void chunk_load(const ChunkGeo& g, const float* __restrict__ xc, int n0, int lane,
+__device__ __forceinline__ void chunk_load(const ChunkGeo& g, const GLB float* __restrict__ xc, int n0, int lane,
                                            Prefetch<R>& pf) {
   const int base = n0 - g.m_lo - g.len_pad + 1;
   const int rows = (Geo<R>::T + g.len_pad) / R;
-  const float* __restrict__ h = g.ir.h;
+  const GLB float* __restrict__ h = gr(g.ir.h);
   const int L = g.ir.L;
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
@@ -251,7 +249,7 @@ __device__ __forceinline__ void chunk_load(const ChunkGeo& g, const float* __res
     if (row < rows && j0 >= 0 && j0 + R <= L) {
 #pragma unroll
       for (int e = 0; e < R; e += 4) {
-        const float4 q = load4(h + j0 + e);
+        const vf4u q = load4(h + j0 + e);
         pf.hrow[k][e] = q.x;
         pf.hrow[k][e + 1] = q.y;
         pf.hrow[k][e + 2] = q.z;
@@ -336,7 +334,7 @@ __device__ __forceinline__ void gather_tile(const GatherCall& d, int c, int tile
   constexpr int Q = R / W;                 // accumulators this wave owns per lane
   static_assert(Q * W == R, "W must divide R");
   const int nq = n0 + lane * R + w * Q;    // the first of them
-  TailT* ring = reinterpret_cast<TailT*>(d.ring) + (int64_t)c * d.ring_cstride;
+  GLB TailT* ring = gw(reinterpret_cast<TailT*>(d.ring)) + (int64_t)c * d.ring_cstride;
 
   TailT acc[Q];
 #pragma unroll
@@ -352,15 +350,15 @@ __device__ __forceinline__ void gather_tile(const GatherCall& d, int c, int tile
   }
 
   if (d.x != nullptr) {
-    const float* __restrict__ xc = d.x + (int64_t)c * d.x_cstride;
+    const GLB float* __restrict__ xc = gr(d.x) + (int64_t)c * d.x_cstride;
     const int lo = n0 - (d.Lmax_call - 1);
     const int b_first = lo <= 0 ? 0 : lo / d.B;
     const int b_last = min(d.n_blocks - 1, (n0 + T - 1) / d.B);
     int c_first = b_first * d.cpb;
     int nch = b_first <= b_last ? (b_last - b_first + 1) * d.cpb : 0;
     if (d.ctab && b_first <= b_last) {
-      c_first = d.ctab[b_first];
-      nch = d.ctab[b_last + 1] - c_first;
+      c_first = gr(d.ctab)[b_first];
+      nch = gr(d.ctab)[b_last + 1] - c_first;
     }
     // `gc` is staged in LDS, `gn` (the wave's next unit) is in registers.
     // A wave's LDS region is private and LDS operations of one wave complete
@@ -458,7 +456,7 @@ __device__ __forceinline__ void gather_tile(const GatherCall& d, int c, int tile
   }
 
   {
-    float* yc = d.y + (int64_t)c * d.y_cstride;
+    GLB float* yc = gw(d.y) + (int64_t)c * d.y_cstride;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const int n = nq + q;

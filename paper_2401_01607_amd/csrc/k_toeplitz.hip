@@ -119,8 +119,8 @@ __device__ __forceinline__ void rev_load(const BlockIR& ir, int top, int tid, Re
   for (int j = 0; j < REV_PER_THREAD; ++j) {
     const int hidx = top - (tid + NT * j);
     const bool ok = tid + NT * j < REV_LEN && hidx >= 0 && hidx < ir.L;
-    pf.hi[j] = ok ? ir.h_hi[hidx] : (uint16_t)0;
-    pf.lo[j] = ok ? ir.h_lo[hidx] : (uint16_t)0;
+    pf.hi[j] = ok ? gr(ir.h_hi)[hidx] : (uint16_t)0;
+    pf.lo[j] = ok ? gr(ir.h_lo)[hidx] : (uint16_t)0;
   }
 }
 
@@ -198,7 +198,7 @@ __global__ __launch_bounds__(NT) void k_toeplitz(GatherCall d, int n_tiles) {
       const int ck = c_first + k;
       int m_lo, len, b;
       chunk_span(d, ck, m_lo, len, b);
-      const BlockIR ir = d.irs ? d.irs[b] : d.ir0;
+      const BlockIR ir = d.irs ? load_ir(d.irs, b) : d.ir0;
       if (len <= 0 || m_lo > n0 + MT - 1 || m_lo + len + ir.L - 2 < n0) continue;  // uniform
       const int chp = (len + 15) & ~15;
       __syncthreads();  // the previous chunk's reads of the copies are done
@@ -249,7 +249,7 @@ __global__ __launch_bounds__(NT) void k_toeplitz(GatherCall d, int n_tiles) {
       for (int k2 = k + 1; k2 < nch; ++k2) {
         int m2, len2, b2;
         chunk_span(d, c_first + k2, m2, len2, b2);
-        const BlockIR ir2 = d.irs ? d.irs[b2] : d.ir0;
+        const BlockIR ir2 = d.irs ? load_ir(d.irs, b2) : d.ir0;
         if (len2 <= 0 || m2 > n0 + MT - 1 || m2 + len2 + ir2.L - 2 < n0) continue;
         nx_ck = c_first + k2;
         nx_top = n0 - m2 + MT - 1;

@@ -25,6 +25,27 @@ struct BlockIR {
   int32_t pad_;
 };
 
+// Device memory reached through pointers loaded from memory (call tables,
+// per-block IR tables) would otherwise be accessed with flat instructions,
+// which also count against the LDS wait counter: every LDS wait of a kernel's
+// inner loop would then wait for its global prefetches too.  The kernels
+// therefore access global memory through global-address-space pointers.
+#define GLB __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ const GLB T* gr(const T* p) { return (const GLB T*)p; }
+template <typename T>
+__device__ __forceinline__ GLB T* gw(T* p) { return (GLB T*)p; }
+__device__ __forceinline__ BlockIR load_ir(const BlockIR* tab, int i) {
+  const GLB BlockIR* e = gr(tab) + i;
+  BlockIR r;
+  r.h = e->h;
+  r.h_hi = e->h_hi;
+  r.h_lo = e->h_lo;
+  r.L = e->L;
+  r.pad_ = 0;
+  return r;
+}
+
 // One stream-call of the gather kernels: n_blocks blocks of one stream.
 //  Outputs n in [0, n_out) are computed relative to the slot at `head`:
 //    acc(n) = tail(n) [if n < live_in] + the partial sums of every chunk of
