@@ -216,7 +216,7 @@ int taches_read_tail(taches_stream* s, int32_t channel, double* out, int32_t n);
  * a stream for a new input. */
 int taches_reset(taches_stream* s);
 
-/* Force the gather tile shape (R outputs per lane in {4, 8, 12, 16}, W waves
+/* Force the gather tile shape (R outputs per lane in {4, 8, 12, 14, 16}, W waves
  * per output tile in {1, 2, 4}); 0, 0 = automatic choice per call. */
 int taches_set_tile(taches_stream* s, int32_t r, int32_t w);
 

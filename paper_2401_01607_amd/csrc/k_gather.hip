@@ -18,10 +18,12 @@
 // needs and the chunk's len input samples are staged in LDS (per wave),
 // loaded into registers one chunk ahead.  A
 // lane keeps two R-tap windows of h in registers; for each group of R input
-// samples it loads one new window (R/4 ds_read_b128) and the group's R
-// input samples (uniform ds_read_b128 broadcasts), then issues R*R FMAs.
-// The LDS copy of h pads every R-float row so that the lanes' 16-byte
-// window reads fall in distinct banks.
+// samples it loads one new window (ds_read_b128, plus one ds_read_b64 when
+// R is not a multiple of 4) and the group's R input samples (uniform
+// broadcasts of the same widths), then issues R*R FMAs.  R is even.  The LDS
+// copy of h pads every R-float row so that the lanes' 16-byte window reads
+// fall in distinct banks; each group of R input samples starts on a 16-byte
+// boundary.
 #include "taches_internal.h"
 
 namespace taches {
@@ -33,21 +35,58 @@ typedef float vf4 __attribute__((ext_vector_type(4)));
 typedef float vf4u __attribute__((ext_vector_type(4))) __attribute__((aligned(4)));
 
 
+typedef float vf2 __attribute__((ext_vector_type(2)));
+typedef float vf2u __attribute__((ext_vector_type(2))) __attribute__((aligned(4)));
+
 __device__ __forceinline__ vf4 lds_read4(int off) { return *reinterpret_cast<const vf4*>(&g_lds[off]); }
 __device__ __forceinline__ void lds_write4(int off, vf4 v) { *reinterpret_cast<vf4*>(&g_lds[off]) = v; }
+__device__ __forceinline__ vf2 lds_read2(int off) { return *reinterpret_cast<const vf2*>(&g_lds[off]); }
+__device__ __forceinline__ void lds_write2(int off, vf2 v) { *reinterpret_cast<vf2*>(&g_lds[off]) = v; }
 
 template <int R>
 struct Geo {
-  static_assert(R % 4 == 0, "R must be a multiple of 4");
+  static_assert(R % 2 == 0 && R >= 4, "R must be even");
   static constexpr int T = 64 * R;                           // outputs per wave tile
   static constexpr int LP = (CHUNK_MAX + R - 1) / R * R;     // longest padded chunk
   static constexpr int NW = T + LP;                          // staged taps (max)
+  static constexpr int R4 = (R + 3) / 4 * 4;                 // R rounded up to 16 bytes
   // floats per R-tap window row in LDS: an odd number of 16-byte units, so
   // the 16-byte reads of consecutive lanes hit distinct banks
-  static constexpr int ROW = (R / 4) % 2 == 1 ? R : R + 4;
+  static constexpr int ROW = (R4 / 4) % 2 == 1 ? R4 : R4 + 4;
   static constexpr int HF = (NW / R) * ROW;                  // LDS floats for h
-  static constexpr int WF = HF + LP;                         // + input samples
+  static constexpr int XG = R4;                              // LDS floats per group of R samples
+  static constexpr int WF = HF + (LP / R) * XG;              // + input samples
 };
+
+// R consecutive floats of LDS starting at a 16-byte-aligned offset.
+template <int R>
+__device__ __forceinline__ void lds_read_row(int off, float (&v)[R]) {
+#pragma unroll
+  for (int j = 0; j < R; j += 4) {
+    if (j + 4 <= R) {
+      const vf4 q = lds_read4(off + j);
+      v[j] = q.x;
+      v[j + 1] = q.y;
+      v[j + 2] = q.z;
+      v[j + 3] = q.w;
+    } else {
+      const vf2 q = lds_read2(off + j);
+      v[j] = q.x;
+      v[j + 1] = q.y;
+    }
+  }
+}
+
+template <int R>
+__device__ __forceinline__ void lds_write_row(int off, const float (&v)[R]) {
+#pragma unroll
+  for (int j = 0; j < R; j += 4) {
+    if (j + 4 <= R)
+      lds_write4(off + j, vf4{v[j], v[j + 1], v[j + 2], v[j + 3]});
+    else
+      lds_write2(off + j, vf2{v[j], v[j + 1]});
+  }
+}
 
 // Map the launch order of workgroups to tiles so that consecutive tiles run
 // on the same XCD (workgroups are dispatched to the 8 XCDs round-robin):
@@ -72,28 +111,11 @@ __device__ __forceinline__ int center_out(int id, int n) {
 
 // Load the R taps of one window; `src` points at its first padded float.
 template <int R>
-__device__ __forceinline__ void load_win(int src, float (&v)[R]) {
-#pragma unroll
-  for (int j = 0; j < R; j += 4) {
-    const vf4 q = lds_read4(src + j);
-    v[j] = q.x;
-    v[j + 1] = q.y;
-    v[j + 2] = q.z;
-    v[j + 3] = q.w;
-  }
-}
+__device__ __forceinline__ void load_win(int src, float (&v)[R]) { lds_read_row<R>(src, v); }
 
+// The R input samples of group g.
 template <int R>
-__device__ __forceinline__ void load_x(int xs, int s0, float (&v)[R]) {
-#pragma unroll
-  for (int j = 0; j < R; j += 4) {
-    const vf4 q = lds_read4(xs + s0 + j);
-    v[j] = q.x;
-    v[j + 1] = q.y;
-    v[j + 2] = q.z;
-    v[j + 3] = q.w;
-  }
-}
+__device__ __forceinline__ void load_x(int xs, int g, float (&v)[R]) { lds_read_row<R>(xs + g * Geo<R>::XG, v); }
 
 // One group of R input samples: for each sample t (in order) and each of
 // the lane's R outputs r, p[r] += x[t] * h[(lane window) + r - t].
@@ -128,16 +150,16 @@ __device__ __forceinline__ void chunk_compute(int hs, int xs, int lane, int G, i
   load_win<R>(wl + (G - g0) * ROW, Y);
   int g = g0;
   for (; g + 2 <= g1; g += 2) {
-    load_x<R>(xs, g * R, xv);
+    load_x<R>(xs, g, xv);
     fma_group<R>(xv, X, Y, p);                                 // group g:   A = X, B = Y
     load_win<R>(wl + (G - 2 - g) * ROW, Y);
-    load_x<R>(xs, (g + 1) * R, xv);
+    load_x<R>(xs, g + 1, xv);
     fma_group<R>(xv, Y, X, p);                                 // group g+1: A = Y, B = X
     // window of group g+2 (a harmless in-bounds read when the loop ends)
     load_win<R>(hs + max(lane + G - 3 - g, 0) * ROW, X);
   }
   if (g < g1) {
-    load_x<R>(xs, g * R, xv);
+    load_x<R>(xs, g, xv);
     fma_group<R>(xv, X, Y, p);
   }
 }
@@ -152,25 +174,38 @@ struct ChunkGeo {
   uint32_t nz;     // bit j: block j of the unit (or the single chunk, bit 0) has a nonzero sample
 };
 
-template <int R>
-__device__ __forceinline__ ChunkGeo chunk_geo(const GatherCall& d, int ck, int n0) {
-  ChunkGeo g;
-  int m_hi;
+// Where chunk ck lies and which IR it uses: the part of a chunk's geometry
+// that comes from memory (the per-block IR table, or the chunk table).
+struct ChunkDesc {
+  int m_lo, len;
+  BlockIR ir;
+};
+
+__device__ __forceinline__ ChunkDesc chunk_desc(const GatherCall& d, int ck) {
+  ChunkDesc c;
   if (d.ctab) {
     // an IR takes over inside some block: chunks come from the table
     const GLB int32_t* cd = gr(d.ctab) + (d.n_blocks + 1) + 3 * ck;
-    g.m_lo = cd[0];
-    g.len = cd[1];
-    m_hi = g.m_lo + g.len;
-    g.ir = load_ir(d.irs, cd[2]);
+    c.m_lo = cd[0];
+    c.len = cd[1];
+    c.ir = load_ir(d.irs, cd[2]);
   } else {
     const int b = ck / d.cpb;
     const int i = ck - b * d.cpb;
-    g.m_lo = b * d.B + (i * d.B) / d.cpb;
-    m_hi = b * d.B + ((i + 1) * d.B) / d.cpb;
-    g.len = m_hi - g.m_lo;
-    g.ir = d.irs ? load_ir(d.irs, b) : d.ir0;
+    c.m_lo = b * d.B + (i * d.B) / d.cpb;
+    c.len = b * d.B + ((i + 1) * d.B) / d.cpb - c.m_lo;
+    c.ir = d.irs ? load_ir(d.irs, b) : d.ir0;
   }
+  return c;
+}
+
+template <int R>
+__device__ __forceinline__ ChunkGeo chunk_geo(const ChunkDesc& c, int ck, int n0) {
+  ChunkGeo g;
+  g.m_lo = c.m_lo;
+  g.len = c.len;
+  g.ir = c.ir;
+  const int m_hi = g.m_lo + g.len;
   g.len_pad = (g.len + R - 1) / R * R;
   // the chunk's taches cover outputs [m_lo, m_hi - 1 + L - 1]
   g.reaches = g.len > 0 && g.m_lo <= n0 + Geo<R>::T - 1 && m_hi + g.ir.L - 2 >= n0;
@@ -197,7 +232,7 @@ __device__ __forceinline__ ChunkGeo unit_geo(const GatherCall& d, int ck, int ck
     g.nz = 0u;
     return g;
   }
-  if (kmax == 1) return chunk_geo<R>(d, ck, n0);
+  if (kmax == 1) return chunk_geo<R>(chunk_desc(d, ck), ck, n0);
   g.ir = d.irs ? load_ir(d.irs, ck) : d.ir0;
   int e = min(ck + kmax, ck_end);
   if (d.irs) {
@@ -219,8 +254,9 @@ __device__ __forceinline__ ChunkGeo unit_geo(const GatherCall& d, int ck, int ck
   return g;
 }
 
-// 16-byte load from a 4-byte-aligned global address.
+// 16- and 8-byte loads from a 4-byte-aligned global address.
 __device__ __forceinline__ vf4u load4(const GLB float* p) { return *reinterpret_cast<const GLB vf4u*>(p); }
+__device__ __forceinline__ vf2u load2(const GLB float* p) { return *reinterpret_cast<const GLB vf2u*>(p); }
 
 // One chunk's staged data on its way from global memory to LDS: each lane
 // holds two R-tap rows of the IR window (rows lane and lane + 64) and up to
@@ -249,11 +285,17 @@ __device__ __forceinline__ void chunk_load(const ChunkGeo& g, const GLB float* _
     if (row < rows && j0 >= 0 && j0 + R <= L) {
 #pragma unroll
       for (int e = 0; e < R; e += 4) {
-        const vf4u q = load4(h + j0 + e);
-        pf.hrow[k][e] = q.x;
-        pf.hrow[k][e + 1] = q.y;
-        pf.hrow[k][e + 2] = q.z;
-        pf.hrow[k][e + 3] = q.w;
+        if (e + 4 <= R) {
+          const vf4u q = load4(h + j0 + e);
+          pf.hrow[k][e] = q.x;
+          pf.hrow[k][e + 1] = q.y;
+          pf.hrow[k][e + 2] = q.z;
+          pf.hrow[k][e + 3] = q.w;
+        } else {
+          const vf2u q = load2(h + j0 + e);
+          pf.hrow[k][e] = q.x;
+          pf.hrow[k][e + 1] = q.y;
+        }
       }
     } else {
 #pragma unroll
@@ -302,25 +344,21 @@ __device__ __forceinline__ void chunk_store(const ChunkGeo& g, int lane, const P
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
     const int row = lane + 64 * k;
-    if (row < rows) {
-      const int dst = hs + row * Geo<R>::ROW;
-#pragma unroll
-      for (int e = 0; e < R; e += 4)
-        lds_write4(dst + e, vf4{pf.hrow[k][e], pf.hrow[k][e + 1], pf.hrow[k][e + 2], pf.hrow[k][e + 3]});
-    }
+    if (row < rows) lds_write_row<R>(hs + row * Geo<R>::ROW, pf.hrow[k]);
   }
 #pragma unroll
   for (int k = 0; k < Prefetch<R>::XPL; ++k) {
     const int s = lane + 64 * k;
-    if (s < g.len_pad) g_lds[xs + s] = pf.xv[k];
+    if (s < g.len_pad) g_lds[xs + (s / R) * Geo<R>::XG + s % R] = pf.xv[k];
   }
 }
 
 // One output tile of one channel of one call.  W waves share the tile; wave
 // w handles chunks w, w+W, ... of each round and the partial sums are added
 // to the accumulators in chunk order after every round.  Each wave keeps the
-// accumulators of R/W of a lane's R outputs (outputs w*R/W .. (w+1)*R/W - 1)
-// and adds only those partial sums, then writes those outputs.
+// accumulators of its share of a lane's R outputs (outputs
+// floor(w*R/W) .. floor((w+1)*R/W) - 1) and adds only those partial sums,
+// then writes those outputs.
 template <int R, int W, typename TailT>
 __device__ __forceinline__ void gather_tile(const GatherCall& d, int c, int tile) {
   constexpr int T = Geo<R>::T;
@@ -328,20 +366,22 @@ __device__ __forceinline__ void gather_tile(const GatherCall& d, int c, int tile
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
   const int hs = w * Geo<R>::WF;           // LDS float offsets of this wave's region
   const int xs = hs + Geo<R>::HF;
-  const int pbuf = W * Geo<R>::WF;         // [W][64][R], used when W > 1
+  const int pbuf = W * Geo<R>::WF;         // [W][64][R4], used when W > 1
 
   const int n0 = tile * T;
-  constexpr int Q = R / W;                 // accumulators this wave owns per lane
-  static_assert(Q * W == R, "W must divide R");
-  const int nq = n0 + lane * R + w * Q;    // the first of them
+  constexpr int QM = (R + W - 1) / W;      // most accumulators a wave owns per lane
+  constexpr bool EVEN = R % W == 0;
+  const int q0 = (w * R) / W;              // the first of this wave's
+  const int qn = EVEN ? QM : ((w + 1) * R) / W - q0;   // and their number (wave-uniform)
+  const int nq = n0 + lane * R + q0;
   GLB TailT* ring = gw(reinterpret_cast<TailT*>(d.ring)) + (int64_t)c * d.ring_cstride;
 
-  TailT acc[Q];
+  TailT acc[QM];
 #pragma unroll
-  for (int q = 0; q < Q; ++q) {
+  for (int q = 0; q < QM; ++q) {
     const int n = nq + q;
     TailT v = 0;
-    if (n < d.live_in) {
+    if (q < qn && n < d.live_in) {
       int slot = d.head + n;
       if (slot >= d.Rcap) slot -= d.Rcap;
       v = ring[slot];
@@ -403,16 +443,20 @@ __device__ __forceinline__ void gather_tile(const GatherCall& d, int c, int tile
       }
     } else {
     // Wave w handles chunks w, w + W, w + 2W, ... and the partial sums of
-    // each round are added in chunk order.
+    // each round are added in chunk order.  The descriptor of the wave's
+    // chunk two rounds ahead is loaded a round before its IR window, so the
+    // window loads need not wait for it.
     ChunkGeo gc, gn;
     gc.reaches = gn.reaches = false;
-    if (w < nch) gc = chunk_geo<R>(d, c_first + w, n0);
+    if (w < nch) gc = chunk_geo<R>(chunk_desc(d, c_first + w), c_first + w, n0);
     if (gc.reaches) {
       chunk_load<R>(gc, xc, n0, lane, pf);
       gc.nz = nonzero_blocks<R>(gc, lane, pf, d.B);
       chunk_store<R>(gc, lane, pf, hs, xs);
     }
-    if (w + W < nch) gn = chunk_geo<R>(d, c_first + w + W, n0);
+    if (w + W < nch) gn = chunk_geo<R>(chunk_desc(d, c_first + w + W), c_first + w + W, n0);
+    ChunkDesc dn{};
+    if (w + 2 * W < nch) dn = chunk_desc(d, c_first + w + 2 * W);
     if (gn.reaches) chunk_load<R>(gn, xc, n0, lane, pf);
     for (int base = 0; base < nch; base += W) {
       float p[R];
@@ -425,19 +469,18 @@ __device__ __forceinline__ void gather_tile(const GatherCall& d, int c, int tile
       }
       gc = gn;
       gn.reaches = false;
-      if (base + 2 * W + w < nch) gn = chunk_geo<R>(d, c_first + base + 2 * W + w, n0);
+      if (base + 2 * W + w < nch) gn = chunk_geo<R>(dn, c_first + base + 2 * W + w, n0);
+      if (base + 3 * W + w < nch) dn = chunk_desc(d, c_first + base + 3 * W + w);
       if (gn.reaches) chunk_load<R>(gn, xc, n0, lane, pf);
       {
-        const int mine = pbuf + (w * 64 + lane) * R;
-#pragma unroll
-        for (int r = 0; r < R; r += 4) lds_write4(mine + r, vf4{p[r], p[r + 1], p[r + 2], p[r + 3]});
+        lds_write_row<R>(pbuf + (w * 64 + lane) * Geo<R>::R4, p);
         __syncthreads();
         const int nv = min(W, nch - base);
         for (int v = 0; v < nv; ++v) {
-          const int src = pbuf + (v * 64 + lane) * R + w * Q;
-          if constexpr (Q % 4 == 0) {
+          const int src = pbuf + (v * 64 + lane) * Geo<R>::R4 + q0;
+          if constexpr (EVEN && QM % 4 == 0) {
 #pragma unroll
-            for (int q = 0; q < Q; q += 4) {
+            for (int q = 0; q < QM; q += 4) {
               const vf4 t = lds_read4(src + q);
               acc[q] += (TailT)t.x;
               acc[q + 1] += (TailT)t.y;
@@ -446,7 +489,8 @@ __device__ __forceinline__ void gather_tile(const GatherCall& d, int c, int tile
             }
           } else {
 #pragma unroll
-            for (int q = 0; q < Q; ++q) acc[q] += (TailT)g_lds[src + q];
+            for (int q = 0; q < QM; ++q)
+              if (q < qn) acc[q] += (TailT)g_lds[src + q];
           }
         }
         __syncthreads();
@@ -458,9 +502,9 @@ __device__ __forceinline__ void gather_tile(const GatherCall& d, int c, int tile
   {
     GLB float* yc = gw(d.y) + (int64_t)c * d.y_cstride;
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
+    for (int q = 0; q < QM; ++q) {
       const int n = nq + q;
-      if (n < d.n_out) {
+      if (q < qn && n < d.n_out) {
         int slot = d.head + n;
         if (slot >= d.Rcap) slot -= d.Rcap;
         if (n < d.S) {
@@ -476,7 +520,7 @@ __device__ __forceinline__ void gather_tile(const GatherCall& d, int c, int tile
 
 template <int R, int W>
 constexpr int lds_bytes() {
-  return 4 * (W * Geo<R>::WF + (W > 1 ? W * 64 * R : 0));
+  return 4 * (W * Geo<R>::WF + (W > 1 ? W * 64 * Geo<R>::R4 : 0));
 }
 
 template <int R, int W, typename TailT>
@@ -560,6 +604,7 @@ hipError_t launch_gather(const GatherCall& call, bool tail_fp64, int r, int w, h
     case 4: return launch_r<4>(call, tail_fp64, w, st);
     case 8: return launch_r<8>(call, tail_fp64, w, st);
     case 12: return launch_r<12>(call, tail_fp64, w, st);
+    case 14: return launch_r<14>(call, tail_fp64, w, st);
     case 16: return launch_r<16>(call, tail_fp64, w, st);
     default: return hipErrorInvalidValue;
   }

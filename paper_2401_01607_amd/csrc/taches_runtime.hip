@@ -274,7 +274,7 @@ double plan_cost(int64_t S, int64_t n_out, int64_t lmax, int channels, int r, in
     cu[c] += work;
     cnt[c] += 1;
   }
-  static const double eff_r[17] = {0, 0, 0, 0, 0.85, 0, 0, 0, 0.92, 0, 0, 0, 0.95, 0, 0, 0, 0.97};
+  static const double eff_r[17] = {0, 0, 0, 0, 0.85, 0, 0, 0, 0.92, 0, 0, 0, 0.95, 0, 0.885, 0, 0.97};
   double worst = 0.0;
   for (int i = 0; i < ncu; ++i) {
     const double waves = (double)cnt[i] * w;
@@ -294,7 +294,7 @@ TilePlan pick_tile(const taches_stream* s, int64_t S, int64_t n_out, int64_t lma
     best.order = 2;
     return best;
   }
-  static const int rs[4] = {16, 12, 8, 4};
+  static const int rs[5] = {16, 14, 12, 8, 4};
   static const int ws[3] = {1, 2, 4};
   double best_cost = 1e300;
   for (int r : rs)
@@ -869,8 +869,8 @@ int taches_set_tile(taches_stream* s, int32_t r, int32_t w) {
     s->force_r = s->force_w = 0;
     return TACHES_OK;
   }
-  if ((r != 4 && r != 8 && r != 12 && r != 16) || (w != 1 && w != 2 && w != 4))
-    return fail(TACHES_EINVAL, "tile (%d, %d) not in {4,8,12,16} x {1,2,4}", r, w);
+  if ((r != 4 && r != 8 && r != 12 && r != 14 && r != 16) || (w != 1 && w != 2 && w != 4))
+    return fail(TACHES_EINVAL, "tile (%d, %d) not in {4,8,12,14,16} x {1,2,4}", r, w);
   s->force_r = r;
   s->force_w = w;
   return TACHES_OK;

@@ -71,7 +71,7 @@ def test_config1_parity_and_modes_agree():
     assert i1.tail_fp64 == 0
 
 
-@pytest.mark.parametrize("tile", [(r, w) for r in (4, 8, 12, 16) for w in (1, 2, 4)])
+@pytest.mark.parametrize("tile", [(r, w) for r in (4, 8, 12, 14, 16) for w in (1, 2, 4)])
 def test_every_tile_shape_gives_the_same_bits(tile):
     spec = W.config2(n=20_000, L=5000, block=256, period=4800)
     nb = -(-(spec.n_samples + 4999) // 256)
@@ -278,7 +278,7 @@ def _silence(x, B, seed):
 
 
 @pytest.mark.parametrize("B", (32, 64, 256, 300))
-@pytest.mark.parametrize("tile", [(16, 1), (16, 4), (4, 1), (12, 2)])
+@pytest.mark.parametrize("tile", [(16, 1), (16, 4), (4, 1), (12, 2), (14, 4)])
 def test_zero_blocks_are_bypassed_exactly(B, tile):
     """Chunks whose samples are all zero skip their multiply-adds and their
     addition to the tail (exact-zero bypass); outputs stay exact."""
@@ -326,7 +326,7 @@ SAMPLE_SWAP_CASES = [
 
 
 @pytest.mark.parametrize("case", SAMPLE_SWAP_CASES, ids=[f"B{c[0]}" for c in SAMPLE_SWAP_CASES])
-@pytest.mark.parametrize("tile", [None, (16, 1), (16, 4), (4, 2)])
+@pytest.mark.parametrize("tile", [None, (16, 1), (16, 4), (4, 2), (14, 4)])
 def test_sample_accurate_swap_bitwise(case, tile):
     """An IR taking over at sample o of a block: integer inputs match the
     oracle exactly, per-block calls (taches_set_ir_at) and multi-block calls
