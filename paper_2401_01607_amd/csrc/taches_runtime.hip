@@ -120,6 +120,7 @@ struct taches_stream {
   BlockIR *irtab_dev = nullptr, *irtab_pin = nullptr;
   hipEvent_t irtab_ev = nullptr;
   bool irtab_pending = false;
+  std::vector<unsigned char> irtab_new, irtab_dev_copy;   // table being built; what irtab_dev holds
   int force_r = 0, force_w = 0, last_r = 0, last_w = 0;
   int64_t device_bytes = 0;
   taches_pool* pool = nullptr;
@@ -444,14 +445,13 @@ int plan_call(taches_stream* s, const float* x_dev, int64_t x_cstride, float* y_
     g.irs = nullptr;
     g.ir0 = ir_of(first_slot);
   } else {
-    if (!s->irtab_pin) {
-      int rc = host_alloc(&s->irtab_pin, (size_t)irtab_bytes(c));
-      if (rc != TACHES_OK) return rc;
-    }
-    if (s->irtab_pending) {
-      HIPCHK(hipEventSynchronize(s->irtab_ev));
-      s->irtab_pending = false;
-    }
+    // The table is built on the host and uploaded only when it differs from
+    // what the device copy already holds (a call that repeats the previous
+    // call's schedule and slots reuses it): the upload is a host-to-device
+    // transfer the kernel has to wait for.
+    std::vector<unsigned char>& tb = s->irtab_new;
+    tb.resize((size_t)irtab_bytes(c));
+    BlockIR* tab = reinterpret_cast<BlockIR*>(tb.data());
     size_t bytes;
     if (!intra) {
       int k = s->active;
@@ -459,15 +459,15 @@ int plan_call(taches_stream* s, const float* x_dev, int64_t x_cstride, float* y_
         int e, off;
         entry(b, &e, &off);
         if (e >= 0) k = e;
-        s->irtab_pin[b] = ir_of(k);
+        tab[b] = ir_of(k);
       }
       bytes = (size_t)n_blocks * sizeof(BlockIR);
     } else {
       // slot table, then the chunk table: each IR segment of a block is cut
       // into ceil(len / CHUNK_MAX) near-equal chunks (a block without a swap
       // inside gets exactly the chunks of the regular geometry)
-      for (int k = 0; k < c.ir_slots; ++k) s->irtab_pin[k] = ir_of(k);
-      int32_t* bc0 = reinterpret_cast<int32_t*>(s->irtab_pin + c.ir_slots);
+      for (int k = 0; k < c.ir_slots; ++k) tab[k] = ir_of(k);
+      int32_t* bc0 = reinterpret_cast<int32_t*>(tab + c.ir_slots);
       int32_t* cd = bc0 + (n_blocks + 1);
       int nc = 0;
       auto cut = [&](int b, int a, int e, int k) {
@@ -499,9 +499,22 @@ int plan_call(taches_stream* s, const float* x_dev, int64_t x_cstride, float* y_
       bytes = (size_t)c.ir_slots * sizeof(BlockIR) + 4 * ((size_t)n_blocks + 1 + 3 * (size_t)nc);
       g.ctab = reinterpret_cast<const int32_t*>(s->irtab_dev + c.ir_slots);
     }
-    HIPCHK(hipMemcpyAsync(s->irtab_dev, s->irtab_pin, bytes, hipMemcpyHostToDevice, s->stream));
-    HIPCHK(hipEventRecord(s->irtab_ev, s->stream));
-    s->irtab_pending = true;
+    const bool same = s->irtab_dev_copy.size() == bytes && std::memcmp(s->irtab_dev_copy.data(), tb.data(), bytes) == 0;
+    if (!same) {
+      if (!s->irtab_pin) {
+        int rc = host_alloc(&s->irtab_pin, (size_t)irtab_bytes(c));
+        if (rc != TACHES_OK) return rc;
+      }
+      if (s->irtab_pending) {   // the pinned copy may still be in flight
+        HIPCHK(hipEventSynchronize(s->irtab_ev));
+        s->irtab_pending = false;
+      }
+      std::memcpy(s->irtab_pin, tb.data(), bytes);
+      HIPCHK(hipMemcpyAsync(s->irtab_dev, s->irtab_pin, bytes, hipMemcpyHostToDevice, s->stream));
+      HIPCHK(hipEventRecord(s->irtab_ev, s->stream));
+      s->irtab_pending = true;
+      s->irtab_dev_copy.assign(tb.begin(), tb.begin() + bytes);
+    }
     g.irs = s->irtab_dev;
   }
   out->next_active = cur;
