@@ -203,6 +203,18 @@ typedef struct taches_info {
 
 int taches_get_info(const taches_stream* s, taches_info* out);
 
+/* Device timing of calls (measurement).  While timing is on, every
+ * taches_process* call records a pair of HIP events on the stream right
+ * before and right after its kernel launches, so host-side work before the
+ * launch is not counted; the last 4096 recorded calls are kept.
+ * taches_call_times waits for the recorded calls, writes the device time in
+ * ms of the last min(n, recorded) of them, oldest first, to ms_out, clears
+ * the record and returns how many it wrote (negative: error code).  Calls on
+ * a stream attached to a pool are not recorded (taches_pool_info reports the
+ * batched launch). */
+int taches_set_timing(taches_stream* s, int32_t on);
+int taches_call_times(taches_stream* s, double* ms_out, int32_t n);
+
 /* Device bytes a stream with this config would own (for HBM admission). */
 int64_t taches_bytes_for(const taches_config* cfg);
 

@@ -121,6 +121,9 @@ struct taches_stream {
   hipEvent_t irtab_ev = nullptr;
   bool irtab_pending = false;
   std::vector<unsigned char> irtab_new, irtab_dev_copy;   // table being built; what irtab_dev holds
+  bool timing = false;                            // record events around each call's kernels
+  std::vector<hipEvent_t> tev;                    // [2 * kTimedCalls] start/end pairs (ring)
+  int64_t timed = 0;                              // calls recorded since the last read
   int force_r = 0, force_w = 0, last_r = 0, last_w = 0;
   int64_t device_bytes = 0;
   taches_pool* pool = nullptr;
@@ -154,6 +157,8 @@ void free_stream(taches_stream* s) {
   (void)hipFree(s->xs_hi);
   (void)hipFree(s->xs_lo);
   if (s->irtab_ev) (void)hipEventDestroy(s->irtab_ev);
+  for (hipEvent_t ev : s->tev)
+    if (ev) (void)hipEventDestroy(ev);
   if (s->own) (void)hipStreamDestroy(s->own);
   delete s;
 }
@@ -533,12 +538,30 @@ void commit_call(taches_stream* s, const CallPlan& p) {
   s->blocks_done += p.n_blocks;
 }
 
+constexpr int kTimedCalls = 4096;
+
+// Event pair of the next timed call (nullptrs when timing is off).
+void timed_events(taches_stream* s, hipEvent_t* e0, hipEvent_t* e1) {
+  *e0 = *e1 = nullptr;
+  if (!s->timing || s->tev.empty()) return;
+  const int k = (int)(s->timed % kTimedCalls);
+  *e0 = s->tev[2 * k];
+  *e1 = s->tev[2 * k + 1];
+}
+
 // Launch one planned call on the stream's own kernels.
 int launch_call(taches_stream* s, CallPlan& p) {
   GatherCall& g = p.g;
+  hipEvent_t e0, e1;
+  timed_events(s, &e0, &e1);
   if (s->cfg.precision == TACHES_PREC_SPLIT_BF16) {
+    if (e0) HIPCHK(hipEventRecord(e0, s->stream));
     hipError_t e = taches::launch_toeplitz(g, s->tail_fp64, s->stream);
     if (e != hipSuccess) return fail(TACHES_EDEVICE, "toeplitz launch: %s", hipGetErrorString(e));
+    if (e1) {
+      HIPCHK(hipEventRecord(e1, s->stream));
+      ++s->timed;
+    }
     s->last_r = 0;
     s->last_w = 0;
     return TACHES_OK;
@@ -560,8 +583,13 @@ int launch_call(taches_stream* s, CallPlan& p) {
     s->plan_val[2] = plan.order;
   }
   g.tile_order = plan.order;
+  if (e0) HIPCHK(hipEventRecord(e0, s->stream));
   hipError_t e = taches::launch_gather(g, s->tail_fp64, plan.r, plan.w, s->stream);
   if (e != hipSuccess) return fail(TACHES_EDEVICE, "gather launch: %s", hipGetErrorString(e));
+  if (e1) {
+    HIPCHK(hipEventRecord(e1, s->stream));
+    ++s->timed;
+  }
   s->last_r = plan.r;
   s->last_w = plan.w;
   return TACHES_OK;
@@ -792,6 +820,36 @@ int taches_process_blocks_at(taches_stream* s, const float* x_dev, float* y_dev,
   if (!s) return fail(TACHES_EINVAL, "stream is NULL");
   if (offset_of_block && !ir_slot_of_block) return fail(TACHES_EINVAL, "offsets given without a schedule");
   return process_common(s, x_dev, y_dev, n_blocks, ir_slot_of_block, offset_of_block);
+}
+
+int taches_set_timing(taches_stream* s, int32_t on) {
+  if (!s) return fail(TACHES_EINVAL, "stream is NULL");
+  if (on && s->tev.empty()) {
+    HIPCHK(hipSetDevice(s->cfg.device));
+    s->tev.assign(2 * kTimedCalls, nullptr);
+    for (hipEvent_t& ev : s->tev) {
+      hipError_t e = hipEventCreate(&ev);
+      if (e != hipSuccess) return fail(TACHES_EDEVICE, "hipEventCreate: %s", hipGetErrorString(e));
+    }
+  }
+  s->timing = on != 0;
+  return TACHES_OK;
+}
+
+int taches_call_times(taches_stream* s, double* ms_out, int32_t n) {
+  if (!s || (!ms_out && n > 0)) return fail(TACHES_EINVAL, "NULL argument");
+  if (n < 0) return fail(TACHES_EINVAL, "n = %d", n);
+  const int64_t have = std::min<int64_t>(s->timed, kTimedCalls);
+  const int64_t m = std::min<int64_t>(have, n);
+  for (int64_t i = 0; i < m; ++i) {
+    const int k = (int)((s->timed - m + i) % kTimedCalls);
+    HIPCHK(hipEventSynchronize(s->tev[2 * k + 1]));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, s->tev[2 * k], s->tev[2 * k + 1]));
+    ms_out[i] = ms;
+  }
+  s->timed = 0;
+  return (int)m;
 }
 
 int taches_get_info(const taches_stream* s, taches_info* out) {

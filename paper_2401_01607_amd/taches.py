@@ -79,6 +79,8 @@ _SIGS = {
     "taches_bytes_for": (_i64, [_P(taches_config)]),
     "taches_read_tail": (ctypes.c_int, [_vp, _i32, _vp, _i32]),
     "taches_set_tile": (ctypes.c_int, [_vp, _i32, _i32]),
+    "taches_set_timing": (ctypes.c_int, [_vp, _i32]),
+    "taches_call_times": (ctypes.c_int, [_vp, _vp, _i32]),
     "taches_reset": (ctypes.c_int, [_vp]),
     "taches_pool_create": (_vp, [_i32, _i64, _i32]),
     "taches_pool_destroy": (ctypes.c_int, [_vp]),
@@ -225,6 +227,18 @@ def taches_read_tail(s, channel: int, n: int) -> np.ndarray:
 
 def taches_set_tile(s, r: int, w: int) -> int:
     return lib.taches_set_tile(s, r, w)
+
+
+def taches_set_timing(s, on: bool) -> int:
+    return lib.taches_set_timing(s, 1 if on else 0)
+
+
+def taches_call_times(s, n: int) -> np.ndarray:
+    out = np.zeros(max(n, 0), dtype=np.float64)
+    m = lib.taches_call_times(s, _host_ptr(out) if n > 0 else None, n)
+    if m < 0:
+        _check(m, "taches_call_times")
+    return out[:m]
 
 
 def taches_reset(s) -> int:
@@ -407,6 +421,14 @@ class Stream:
 
     def set_tile(self, r: int, w: int) -> None:
         _check(taches_set_tile(self.h, r, w), "taches_set_tile")
+
+    def set_timing(self, on: bool) -> None:
+        """Record HIP events around each call's kernel launches (see call_times)."""
+        _check(taches_set_timing(self.h, on), "taches_set_timing")
+
+    def call_times(self, n: int) -> np.ndarray:
+        """Device times (ms) of the last n timed calls, oldest first; clears the record."""
+        return taches_call_times(self.h, n)
 
     def synchronize(self) -> None:
         _check(taches_synchronize(self.h), "taches_synchronize")

@@ -84,3 +84,32 @@ def test_fp32_fma_ceiling_is_positive_and_below_the_packed_peak():
     from paper_2401_01607_amd import taches as T
     v = T.taches_fp32_fma_ceiling(0)
     assert 1.0 < v < 2 * 157.3
+
+
+def test_call_times_record_only_timed_calls():
+    """taches_set_timing / taches_call_times: only calls made while timing is
+    on are recorded, oldest first; reading clears the record; the device time
+    of a long call exceeds that of a one-block call."""
+    import torch
+    from paper_2401_01607_amd import taches as T
+    B, L = 256, 4096
+    s = T.Stream(B, L, max_blocks_per_call=64)
+    s.set_ir(torch.ones(L, device="cuda"))
+    x = torch.ones((1, 64 * B), device="cuda")
+    y = torch.empty_like(x)
+    s.process_blocks(x, y, 64)                   # not timed
+    assert len(s.call_times(8)) == 0
+    s.set_timing(True)
+    s.process_blocks(x[:, :B], y[:, :B], 1)
+    s.process_blocks(x, y, 64)
+    s.set_timing(False)
+    s.process_blocks(x, y, 64)                   # not timed
+    t = s.call_times(8)
+    assert len(t) == 2 and t[0] > 0 and t[1] > t[0]
+    assert len(s.call_times(8)) == 0
+    s.set_timing(True)
+    for _ in range(3):
+        s.process_blocks(x, y, 64)
+    t = s.call_times(2)                          # the last two of three
+    assert len(t) == 2 and all(v > 0 for v in t)
+    s.close()
