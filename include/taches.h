@@ -254,7 +254,9 @@ int taches_pool_destroy(taches_pool* p);
  * in a pool, TACHES_ENOMEM if its device bytes exceed the remaining budget. */
 int taches_pool_attach(taches_pool* p, taches_stream* s);
 
-/* Release the stream's slot and bytes; waits for the pool's work first. */
+/* Release the stream's slot and bytes.  Does not wait: later work on the
+ * stream's own HIP stream is ordered after the pool's queued steps, which
+ * may still use the stream's tail and IR slots. */
 int taches_pool_detach(taches_pool* p, taches_stream* s);
 
 /* Advance n attached streams (each listed once): stream i processes
@@ -302,6 +304,8 @@ typedef struct taches_pool_info {
   double last_imbalance;    /* busiest workgroup's work / mean work */
   double last_device_ms;    /* device time of the last step's batched launch
                                (table copy + kernel); -1 until it has run */
+  double device_ms_total;   /* device time of all batched launches found
+                               complete so far (steps run without waiting) */
 } taches_pool_info;
 
 int taches_pool_get_info(const taches_pool* p, taches_pool_info* out);

@@ -961,12 +961,16 @@ struct taches_pool {
   int device = 0;
   std::vector<taches_stream*> attached;
   hipStream_t own = nullptr, stream = nullptr, capture = nullptr;
-  // one packed table: [calls][fp64 flags][wg_begin][items], pinned and device
-  unsigned char* tab_pin = nullptr;
+  // one packed table: [calls][fp64 flags][wg_begin][items], pinned and device.
+  // Two pinned buffers are used in turn, so the host can build a step's
+  // table while the previous step (and its copy) is still queued.
+  unsigned char* tab_pin[2] = {nullptr, nullptr};
   unsigned char* tab_dev = nullptr;
   size_t tab_cap = 0;
-  hipEvent_t tab_free = nullptr;
-  bool tab_pending = false;
+  hipEvent_t tab_free[2] = {nullptr, nullptr};
+  bool tab_pending[2] = {false, false};
+  int tab_cur = 0;
+  hipEvent_t detach_ev = nullptr;
   int force_r = 0;
   bool use_graph = false;
   hipGraph_t graph = nullptr;
@@ -980,8 +984,13 @@ struct taches_pool {
   double last_plan_ms = 0.0;
   double last_imbalance = 0.0;
   uint64_t steps = 0;                             // step counter (duplicate detection)
-  hipEvent_t ev_beg = nullptr, ev_end = nullptr;  // device time of the last batched launch
-  bool timed = false;
+  // device time of the batched launches: a ring of event pairs; completed
+  // launches are added to dev_ms_total when they are found complete
+  static constexpr int kRing = 8;
+  hipEvent_t ev_beg[kRing] = {}, ev_end[kRing] = {};
+  mutable bool ev_pending[kRing] = {};
+  mutable double dev_ms_total = 0.0;
+  int ev_next = 0, ev_last = -1;
 };
 
 namespace {
@@ -1023,23 +1032,43 @@ void sort_by_work_desc(const std::vector<ItemT>& items, std::vector<uint32_t>& o
   }
 }
 
+// Add the device time of every completed launch of the ring to the total
+// (wait: block until each pending launch has completed).
+int pool_account(const taches_pool* p, bool wait) {
+  for (int k = 0; k < taches_pool::kRing; ++k) {
+    if (!p->ev_pending[k]) continue;
+    if (wait) HIPCHK(hipEventSynchronize(p->ev_end[k]));
+    else if (hipEventQuery(p->ev_end[k]) != hipSuccess) continue;
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, p->ev_beg[k], p->ev_end[k]));
+    p->dev_ms_total += ms;
+    p->ev_pending[k] = false;
+  }
+  return TACHES_OK;
+}
+
 int pool_reserve(taches_pool* p, size_t bytes) {
   if (bytes <= p->tab_cap) return TACHES_OK;
-  if (p->tab_pending) {
-    HIPCHK(hipEventSynchronize(p->tab_free));
-    p->tab_pending = false;
-  }
+  for (int k = 0; k < 2; ++k)
+    if (p->tab_pending[k]) {
+      HIPCHK(hipEventSynchronize(p->tab_free[k]));
+      p->tab_pending[k] = false;
+    }
   HIPCHK(hipStreamSynchronize(p->stream));
   pool_drop_graph(p);
-  (void)hipHostFree(p->tab_pin);
+  for (int k = 0; k < 2; ++k) {
+    (void)hipHostFree(p->tab_pin[k]);
+    p->tab_pin[k] = nullptr;
+  }
   (void)hipFree(p->tab_dev);
-  p->tab_pin = nullptr;
   p->tab_dev = nullptr;
   p->tab_cap = 0;
   const size_t cap = align256(bytes + bytes / 2);
-  hipError_t e = hipHostMalloc((void**)&p->tab_pin, cap, hipHostMallocDefault);
-  if (e != hipSuccess) return fail(TACHES_ENOMEM, "pool table (host): %s", hipGetErrorString(e));
-  e = hipMalloc((void**)&p->tab_dev, cap);
+  for (int k = 0; k < 2; ++k) {
+    hipError_t e = hipHostMalloc((void**)&p->tab_pin[k], cap, hipHostMallocDefault);
+    if (e != hipSuccess) return fail(TACHES_ENOMEM, "pool table (host): %s", hipGetErrorString(e));
+  }
+  hipError_t e = hipMalloc((void**)&p->tab_dev, cap);
   if (e != hipSuccess) return fail(TACHES_ENOMEM, "pool table (device): %s", hipGetErrorString(e));
   p->tab_cap = cap;
   return TACHES_OK;
@@ -1078,16 +1107,23 @@ taches_pool* taches_pool_create(int32_t max_streams, int64_t hbm_budget_bytes, i
   p->max_streams = max_streams;
   p->budget = hbm_budget_bytes;
   p->device = device;
-  if (hipSetDevice(device) != hipSuccess || hipStreamCreateWithFlags(&p->own, hipStreamNonBlocking) != hipSuccess ||
-      hipStreamCreateWithFlags(&p->capture, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&p->tab_free, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreate(&p->ev_beg) != hipSuccess || hipEventCreate(&p->ev_end) != hipSuccess) {
+  bool ok = hipSetDevice(device) == hipSuccess && hipStreamCreateWithFlags(&p->own, hipStreamNonBlocking) == hipSuccess &&
+            hipStreamCreateWithFlags(&p->capture, hipStreamNonBlocking) == hipSuccess &&
+            hipEventCreateWithFlags(&p->tab_free[0], hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&p->tab_free[1], hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&p->detach_ev, hipEventDisableTiming) == hipSuccess;
+  for (int k = 0; ok && k < taches_pool::kRing; ++k)
+    ok = hipEventCreate(&p->ev_beg[k]) == hipSuccess && hipEventCreate(&p->ev_end[k]) == hipSuccess;
+  if (!ok) {
     fail(TACHES_EDEVICE, "pool stream/event creation failed");
     if (p->own) (void)hipStreamDestroy(p->own);
     if (p->capture) (void)hipStreamDestroy(p->capture);
-    if (p->tab_free) (void)hipEventDestroy(p->tab_free);
-    if (p->ev_beg) (void)hipEventDestroy(p->ev_beg);
-    if (p->ev_end) (void)hipEventDestroy(p->ev_end);
+    for (hipEvent_t ev : {p->tab_free[0], p->tab_free[1], p->detach_ev})
+      if (ev) (void)hipEventDestroy(ev);
+    for (int k = 0; k < taches_pool::kRing; ++k) {
+      if (p->ev_beg[k]) (void)hipEventDestroy(p->ev_beg[k]);
+      if (p->ev_end[k]) (void)hipEventDestroy(p->ev_end[k]);
+    }
     delete p;
     return nullptr;
   }
@@ -1100,11 +1136,14 @@ int taches_pool_destroy(taches_pool* p) {
   if (!p->attached.empty()) return fail(TACHES_EBUSY, "pool still has %zu attached streams", p->attached.size());
   (void)hipStreamSynchronize(p->stream);
   pool_drop_graph(p);
-  (void)hipHostFree(p->tab_pin);
+  for (int k = 0; k < 2; ++k) (void)hipHostFree(p->tab_pin[k]);
   (void)hipFree(p->tab_dev);
-  if (p->tab_free) (void)hipEventDestroy(p->tab_free);
-  if (p->ev_beg) (void)hipEventDestroy(p->ev_beg);
-  if (p->ev_end) (void)hipEventDestroy(p->ev_end);
+  for (hipEvent_t ev : {p->tab_free[0], p->tab_free[1], p->detach_ev})
+    if (ev) (void)hipEventDestroy(ev);
+  for (int k = 0; k < taches_pool::kRing; ++k) {
+    (void)hipEventDestroy(p->ev_beg[k]);
+    (void)hipEventDestroy(p->ev_end[k]);
+  }
   (void)hipStreamDestroy(p->own);
   (void)hipStreamDestroy(p->capture);
   delete p;
@@ -1142,7 +1181,10 @@ int taches_pool_attach(taches_pool* p, taches_stream* s) {
 int taches_pool_detach(taches_pool* p, taches_stream* s) {
   if (!p || !s) return fail(TACHES_EINVAL, "NULL argument");
   if (s->pool != p) return fail(TACHES_EINVAL, "stream is not attached to this pool");
-  HIPCHK(hipStreamSynchronize(p->stream));
+  // later work on the stream's own HIP stream waits for the pool's queued
+  // steps (which may still use the stream's tail and IR slots)
+  HIPCHK(hipEventRecord(p->detach_ev, p->stream));
+  HIPCHK(hipStreamWaitEvent(s->stream_before_pool, p->detach_ev, 0));
   p->attached.erase(std::find(p->attached.begin(), p->attached.end(), s));
   p->used -= s->device_bytes;
   s->pool = nullptr;
@@ -1184,8 +1226,12 @@ int taches_pool_get_info(const taches_pool* p, taches_pool_info* out) {
   out->last_imbalance = p->last_imbalance;
   out->last_device_ms = -1.0;
   float ms = 0.f;
-  if (p->timed && hipEventQuery(p->ev_end) == hipSuccess && hipEventElapsedTime(&ms, p->ev_beg, p->ev_end) == hipSuccess)
+  if (p->ev_last >= 0 && hipEventQuery(p->ev_end[p->ev_last]) == hipSuccess &&
+      hipEventElapsedTime(&ms, p->ev_beg[p->ev_last], p->ev_end[p->ev_last]) == hipSuccess)
     out->last_device_ms = ms;
+  int rc = pool_account(p, false);
+  if (rc != TACHES_OK) return rc;
+  out->device_ms_total = p->dev_ms_total;
   return TACHES_OK;
 }
 
@@ -1209,7 +1255,7 @@ int taches_pool_step_strided(taches_pool* p, int32_t n, taches_stream* const* st
   if (n == 0) return TACHES_OK;
   const auto t0 = std::chrono::steady_clock::now();
   const uint64_t mark = ++p->steps;
-  p->timed = false;
+  p->ev_last = -1;
   for (int i = 0; i < n; ++i) {
     if (!streams[i] || streams[i]->pool != p) return fail(TACHES_EINVAL, "stream %d is not attached to this pool", i);
     if (streams[i]->step_mark == mark) return fail(TACHES_EINVAL, "stream listed twice in one step");
@@ -1371,19 +1417,21 @@ int taches_pool_step_strided(taches_pool* p, int32_t n, taches_stream* const* st
     const size_t bytes = align256(off_items + sizeof(WorkItem) * items.size());
     int rc = pool_reserve(p, bytes);
     if (rc != TACHES_OK) return rc;
-    if (p->tab_pending) {
-      HIPCHK(hipEventSynchronize(p->tab_free));
-      p->tab_pending = false;
+    const int cur = p->tab_cur;
+    unsigned char* pin = p->tab_pin[cur];
+    if (p->tab_pending[cur]) {   // the step before the previous one read this buffer
+      HIPCHK(hipEventSynchronize(p->tab_free[cur]));
+      p->tab_pending[cur] = false;
     }
-    taches::BatchHeader* hd = (taches::BatchHeader*)p->tab_pin;
+    taches::BatchHeader* hd = (taches::BatchHeader*)pin;
     hd->off_calls = (int32_t)off_calls;
     hd->off_fp64 = (int32_t)off_fp64;
     hd->off_wgb = (int32_t)off_wgb;
     hd->off_items = (int32_t)off_items;
-    GatherCall* calls = (GatherCall*)(p->tab_pin + off_calls);
-    int32_t* fp64 = (int32_t*)(p->tab_pin + off_fp64);
-    int32_t* wgb = (int32_t*)(p->tab_pin + off_wgb);
-    WorkItem* wit = (WorkItem*)(p->tab_pin + off_items);
+    GatherCall* calls = (GatherCall*)(pin + off_calls);
+    int32_t* fp64 = (int32_t*)(pin + off_fp64);
+    int32_t* wgb = (int32_t*)(pin + off_wgb);
+    WorkItem* wit = (WorkItem*)(pin + off_items);
     for (int k = 0; k < ng; ++k) {
       calls[k] = plans[gather_ids[k]].g;
       calls[k].tile_order = 2;
@@ -1396,7 +1444,13 @@ int taches_pool_step_strided(taches_pool* p, int32_t n, taches_stream* const* st
     const auto t1 = std::chrono::steady_clock::now();
     p->last_plan_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
     bool launched = false;
-    HIPCHK(hipEventRecord(p->ev_beg, p->stream));
+    const int ev = p->ev_next;
+    if (p->ev_pending[ev]) {
+      HIPCHK(hipEventSynchronize(p->ev_end[ev]));
+      int rc2 = pool_account(p, false);
+      if (rc2 != TACHES_OK) return rc2;
+    }
+    HIPCHK(hipEventRecord(p->ev_beg[ev], p->stream));
     if (p->use_graph) {
       // capture [table copy -> batched kernel] once per (tile, workgroups,
       // table capacity); later steps only resize the copy and replay
@@ -1404,7 +1458,7 @@ int taches_pool_step_strided(taches_pool* p, int32_t n, taches_stream* const* st
           p->graph_mixed != mixed) {
         pool_drop_graph(p);
         HIPCHK(hipStreamBeginCapture(p->capture, hipStreamCaptureModeThreadLocal));
-        hipError_t e1 = hipMemcpyAsync(p->tab_dev, p->tab_pin, p->tab_cap, hipMemcpyHostToDevice, p->capture);
+        hipError_t e1 = hipMemcpyAsync(p->tab_dev, pin, p->tab_cap, hipMemcpyHostToDevice, p->capture);
         hipError_t e2 = taches::launch_gather_batched(p->tab_dev, nwg, r, mixed, p->capture);
         hipError_t e3 = hipStreamEndCapture(p->capture, &p->graph);
         if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess)
@@ -1425,7 +1479,7 @@ int taches_pool_step_strided(taches_pool* p, int32_t n, taches_stream* const* st
         p->graph_cap = p->tab_cap;
       }
       if (p->copy_node &&
-          hipGraphExecMemcpyNodeSetParams1D(p->exec, p->copy_node, p->tab_dev, p->tab_pin, bytes, hipMemcpyHostToDevice) ==
+          hipGraphExecMemcpyNodeSetParams1D(p->exec, p->copy_node, p->tab_dev, pin, bytes, hipMemcpyHostToDevice) ==
               hipSuccess) {
         HIPCHK(hipGraphLaunch(p->exec, p->stream));
         p->replays += 1;
@@ -1433,14 +1487,17 @@ int taches_pool_step_strided(taches_pool* p, int32_t n, taches_stream* const* st
       }
     }
     if (!launched) {
-      HIPCHK(hipMemcpyAsync(p->tab_dev, p->tab_pin, bytes, hipMemcpyHostToDevice, p->stream));
+      HIPCHK(hipMemcpyAsync(p->tab_dev, pin, bytes, hipMemcpyHostToDevice, p->stream));
       hipError_t e = taches::launch_gather_batched(p->tab_dev, nwg, r, mixed, p->stream);
       if (e != hipSuccess) return fail(TACHES_EDEVICE, "batched launch: %s", hipGetErrorString(e));
     }
-    HIPCHK(hipEventRecord(p->ev_end, p->stream));
-    p->timed = true;
-    HIPCHK(hipEventRecord(p->tab_free, p->stream));
-    p->tab_pending = true;
+    HIPCHK(hipEventRecord(p->ev_end[ev], p->stream));
+    p->ev_pending[ev] = true;
+    p->ev_last = ev;
+    p->ev_next = (ev + 1) % taches_pool::kRing;
+    HIPCHK(hipEventRecord(p->tab_free[cur], p->stream));
+    p->tab_pending[cur] = true;
+    p->tab_cur = cur ^ 1;
     p->last_items = (int)items.size();
     p->last_wg = nwg;
     p->last_r = r;

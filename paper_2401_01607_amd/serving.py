@@ -173,6 +173,7 @@ class Scheduler:
         # fewer, larger steps)
         self.min_tick_s = min_tick_s
         self._last_step_s = -1e30
+        self._clock = None   # the real-time clock relative to its start (None: simulated)
 
     @property
     def active(self) -> dict:
@@ -255,7 +256,10 @@ class Scheduler:
         self.ex.step(t.handle[idx], k0, n)                  # outputs ready on return
         elapsed = time.perf_counter() - t0
         self.stats.busy_s += elapsed
-        done_s = now + (elapsed if self.step_cost_s is None else self.step_cost_s)
+        if self._clock is not None:
+            done_s = self._clock()    # real time: includes this tick's host work before the step
+        else:
+            done_s = now + (elapsed if self.step_cost_s is None else self.step_cost_s)
         self.stats.steps += 1
         self._record(done_s, start[idx], k0, n, Bi, is_in, t.L[idx], t.C[idx])
         t.nxt[idx] = end
@@ -288,6 +292,7 @@ class Scheduler:
     # -- drivers -----------------------------------------------------------
     def run_realtime(self, duration_s: float, clock=time.perf_counter, sleep=time.sleep) -> dict:
         t0 = clock()
+        self._clock = lambda: clock() - t0
         while True:
             now = clock() - t0
             if now >= duration_s:
@@ -296,6 +301,7 @@ class Scheduler:
                 nxt = self._next_event_s(now)
                 if nxt is not None and nxt > now:
                     sleep(min(nxt - now, 0.0005))
+        self._clock = None
         return self.stats.summary(clock() - t0)
 
     def run_simulated(self, duration_s: float) -> dict:
@@ -375,7 +381,6 @@ class GpuExecutor:
         self.budget = hbm_budget_bytes
         self.idle_bytes = 0          # recycled streams not attached (counted against the budget)
         self.scratch = torch.empty(1 << 20, device="cuda")
-        self.device_s = 0.0          # device time of the batched launches so far
         # per-handle arrays read by step(); handles are reused after retire
         cap = max_streams
         self.h_stream = np.zeros(cap, np.uint64)
@@ -472,9 +477,11 @@ class GpuExecutor:
         self.pool.step_strided(self.h_stream[handles], xp, np.full(handles.size, self.bank_len, np.int64), yp,
                                np.where(kept, self.h_ycs[handles], 0), n.astype(np.int32))
         self.pool.synchronize()
-        dev = self.pool.info().last_device_ms
-        if dev > 0:
-            self.device_s += dev / 1e3
+
+    @property
+    def device_s(self) -> float:
+        """Device time of the batched launches so far (table copy + kernel)."""
+        return self.pool.info().device_ms_total / 1e3
 
     def retire(self, handle, req):
         s, y, key, _ = self.live.pop(handle)

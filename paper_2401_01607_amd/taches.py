@@ -54,7 +54,7 @@ class taches_pool_info(ctypes.Structure):
                 ("last_items", ctypes.c_int32), ("last_workgroups", ctypes.c_int32),
                 ("last_r", ctypes.c_int32), ("pad_", ctypes.c_int32), ("graph_replays", ctypes.c_int64),
                 ("last_plan_ms", ctypes.c_double), ("last_imbalance", ctypes.c_double),
-                ("last_device_ms", ctypes.c_double)]
+                ("last_device_ms", ctypes.c_double), ("device_ms_total", ctypes.c_double)]
 
 
 _vp, _i32, _i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64

@@ -381,3 +381,39 @@ def test_sample_accurate_swap_on_attached_stream():
     pool.detach(s)
     s.close()
     pool.close()
+
+
+def test_detach_does_not_wait_and_keeps_order():
+    """A stream detached right after a step was queued (no synchronisation)
+    continues on its own HIP stream after that step: a call made right
+    after the detach gives the same bits as the two calls made alone.  The
+    pool's running device time covers its completed launches."""
+    import torch
+    T = binding()
+    B, L = 128, 3000
+    nb1, nb2 = 12, 40
+    h = W.impulse_response(L, 171)
+    x = W.signal_gauss((nb1 + nb2) * B, 172)
+    xd = torch.from_numpy(x).cuda()
+    ref = T.Stream(B, L, max_blocks_per_call=nb2)
+    ref.set_ir(h)
+    y_ref = torch.empty(((nb1 + nb2) * B,), device="cuda")
+    ref.process_blocks(xd[None, :nb1 * B], y_ref[None, :nb1 * B], nb1)
+    ref.process_blocks(xd[None, nb1 * B:], y_ref[None, nb1 * B:], nb2)
+    ref.synchronize()
+    s = T.Stream(B, L, max_blocks_per_call=nb2, torch_stream=False)   # its own HIP stream
+    s.set_ir(h)
+    pool = T.Pool(4, 8 * GB, use_graph=True)
+    assert pool.attach(s) == T.TACHES_OK
+    y = torch.empty_like(y_ref)
+    pool.step([s], [xd[None, :nb1 * B]], [y[None, :nb1 * B]], [nb1])
+    pool.detach(s)                                   # the step may still be queued
+    s.process_blocks(xd[None, nb1 * B:], y[None, nb1 * B:], nb2)
+    s.synchronize()
+    pool.synchronize()
+    assert torch.equal(y, y_ref)
+    info = pool.info()
+    assert info.device_ms_total > 0 and info.device_ms_total >= info.last_device_ms > 0
+    pool.close()
+    s.close()
+    ref.close()

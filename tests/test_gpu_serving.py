@@ -12,13 +12,13 @@ from tests.gpu_harness import binding, oracle_run, rel_err
 pytestmark = pytest.mark.gpu
 
 
-def _replay_alone(ex, req, hist, x_in):
+def _replay_alone(ex, req, hist, x_in, precision=0):
     """The same request on its own stream: same input blocks, same IR
     versions applied at the same blocks."""
     import torch
     T = binding()
     B, C = req.block, req.channels
-    s = T.Stream(B, ex.ir_class(req.ir_len), channels=C, max_blocks_per_call=1)
+    s = T.Stream(B, ex.ir_class(req.ir_len), channels=C, max_blocks_per_call=1, precision=precision)
     s.set_ir(ex.ir(req, 0))
     swaps = dict((b, v + 1) for v, b in enumerate(hist.swap_blocks))
     outs = []
@@ -89,4 +89,37 @@ def test_small_budget_queues_requests():
     assert st["max_active_streams"] <= budget // per_min
     assert st["completed"] == len(reqs)
     assert sch.stats.refused_attempts > 0
+    ex.close()
+
+
+def test_split_bf16_mix_equals_alone_and_within_bound():
+    """Serving with split-BF16 streams (each runs its Toeplitz MFMA kernel on
+    the pool's stream inside the batched step): each kept stream equals the
+    same stream processed alone bit for bit, and the FP64 oracle within the
+    split-BF16 bound (max |err| <= 1e-4 * RMS)."""
+    from paper_2401_01607_amd.serving import GpuExecutor, Scheduler
+    T = binding()
+    reqs = W.config5_requests(horizon_s=0.8, rate_hz=30.0, seed=79, dur=(0.2, 0.4), lrange=(256, 4096),
+                              swap_rate_hz=5.0)
+    keep = [r.rid for r in reqs[::3]]
+    ex = GpuExecutor(max_streams=16, hbm_budget_bytes=1 << 34, keep_outputs=keep, ir_bank=8,
+                     max_ir_len=4096, precision=T.TACHES_PREC_SPLIT_BF16)
+    sch = Scheduler(reqs, ex, min_tick_s=0.005)
+    st = sch.run_realtime(0.8 + 0.4 + 4096 / 48000 + 1.5)
+    assert st["completed"] == st["admitted"] == len(reqs)
+    assert any(len(sch.history[rid].swap_blocks) > 0 for rid in keep)
+    for i, rid in enumerate(keep):
+        req = next(r for r in reqs if r.rid == rid)
+        hist = sch.history[rid]
+        x_in, y_mix = ex.kept[rid]
+        y_alone = _replay_alone(ex, req, hist, x_in, precision=T.TACHES_PREC_SPLIT_BF16)
+        assert np.array_equal(y_mix, y_alone)
+        if i < 2:
+            irs = [ex.ir(req, v).cpu().numpy() for v in range(len(hist.swap_blocks) + 1)]
+            sched = [(0, 0)] + [(b, v + 1) for v, b in enumerate(hist.swap_blocks)]
+            x_planar = x_in.transpose(1, 0, 2).reshape(req.channels, -1)
+            ref = oracle_run(x_planar, irs, sched, req.block, req.ir_len, hist.n_total)
+            y_planar = y_mix.transpose(1, 0, 2).reshape(req.channels, -1)
+            err = np.abs(y_planar.astype(np.float64) - ref)
+            assert err.max() <= 1e-4 * np.sqrt(np.mean(ref ** 2))
     ex.close()
