@@ -1,10 +1,13 @@
 // Host runtime and C-ABI of libtaches: stream handles, IR slots, the
 // circular tail, call planning and kernel launches.
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -252,12 +255,15 @@ struct TilePlan {
   int r = 4, w = 1, order = 0;
 };
 
-double plan_cost(int64_t S, int64_t n_out, int64_t lmax, int channels, int r, int w, int order) {
+// CU loads of one tile shape and launch order (the same for every W): the
+// FMA work of the tiles each CU receives, and their number.
+void plan_loads(int64_t S, int64_t n_out, int64_t lmax, int channels, int r, int order, std::vector<double>& cu,
+                std::vector<int>& cnt) {
   const int64_t T = 64 * r;
   const int64_t nt = (n_out + T - 1) / T;
   const int ncu = 256;
-  std::vector<double> cu(ncu, 0.0);
-  std::vector<int> cnt(ncu, 0);
+  cu.assign(ncu, 0.0);
+  cnt.assign(ncu, 0);
   const int64_t total = nt * channels;
   const int64_t mid = (nt - 1) / 2;
   const int64_t q = nt >> 3, rem = nt & 7;
@@ -280,9 +286,13 @@ double plan_cost(int64_t S, int64_t n_out, int64_t lmax, int channels, int r, in
     cu[c] += work;
     cnt[c] += 1;
   }
+}
+
+// Estimated time of the launch with w waves per tile: its busiest CU.
+double plan_cost(const std::vector<double>& cu, const std::vector<int>& cnt, int r, int w) {
   static const double eff_r[17] = {0, 0, 0, 0, 0.85, 0, 0, 0, 0.92, 0, 0, 0, 0.95, 0, 0.885, 0, 0.97};
   double worst = 0.0;
-  for (int i = 0; i < ncu; ++i) {
+  for (size_t i = 0; i < cu.size(); ++i) {
     const double waves = (double)cnt[i] * w;
     const double simds = std::min(4.0, waves);
     double t = simds > 0 ? cu[i] / simds : 0.0;
@@ -292,6 +302,11 @@ double plan_cost(int64_t S, int64_t n_out, int64_t lmax, int channels, int r, in
   return worst / eff_r[r];
 }
 
+// Plans by call shape, shared by all streams of the process (a stream also
+// keeps its last plan): a call shape seen before is not simulated again.
+std::mutex g_plan_mu;
+std::map<std::array<int64_t, 5>, TilePlan> g_plans;
+
 TilePlan pick_tile(const taches_stream* s, int64_t S, int64_t n_out, int64_t lmax, int chunks_per_tile) {
   TilePlan best;
   if (s->force_r) {
@@ -300,14 +315,23 @@ TilePlan pick_tile(const taches_stream* s, int64_t S, int64_t n_out, int64_t lma
     best.order = 2;
     return best;
   }
+  const std::array<int64_t, 5> key = {S, n_out, lmax, s->cfg.channels, chunks_per_tile};
+  {
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    auto it = g_plans.find(key);
+    if (it != g_plans.end()) return it->second;
+  }
   static const int rs[5] = {16, 14, 12, 8, 4};
   static const int ws[3] = {1, 2, 4};
   double best_cost = 1e300;
-  for (int r : rs)
+  std::vector<double> cu[3];
+  std::vector<int> cnt[3];
+  for (int r : rs) {
+    for (int order = 0; order < 3; ++order) plan_loads(S, n_out, lmax, s->cfg.channels, r, order, cu[order], cnt[order]);
     for (int w : ws) {
       if (w > 1 && chunks_per_tile < 2 * w) continue;
       for (int order = 0; order < 3; ++order) {
-        const double c = plan_cost(S, n_out, lmax, s->cfg.channels, r, w, order);
+        const double c = plan_cost(cu[order], cnt[order], r, w);
         if (c < best_cost * 0.999) {
           best_cost = c;
           best.r = r;
@@ -316,6 +340,10 @@ TilePlan pick_tile(const taches_stream* s, int64_t S, int64_t n_out, int64_t lma
         }
       }
     }
+  }
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  if (g_plans.size() >= 4096) g_plans.clear();
+  g_plans[key] = best;
   return best;
 }
 
