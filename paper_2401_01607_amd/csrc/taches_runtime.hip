@@ -289,8 +289,13 @@ void plan_loads(int64_t S, int64_t n_out, int64_t lmax, int channels, int r, int
 }
 
 // Estimated time of the launch with w waves per tile: its busiest CU.
+// Measured efficiencies with every CU full: longer per-lane tiles need
+// fewer LDS reads per FMA (eff_r); waves that share a tile work on adjacent
+// chunks whose IR windows overlap, one-wave tiles each stream their own
+// window (eff_w).
 double plan_cost(const std::vector<double>& cu, const std::vector<int>& cnt, int r, int w) {
   static const double eff_r[17] = {0, 0, 0, 0, 0.85, 0, 0, 0, 0.92, 0, 0, 0, 0.95, 0, 0.885, 0, 0.97};
+  const double eff_w = w == 4 ? 1.0 : w == 2 ? 0.92 : 0.845;
   double worst = 0.0;
   for (size_t i = 0; i < cu.size(); ++i) {
     const double waves = (double)cnt[i] * w;
@@ -299,7 +304,7 @@ double plan_cost(const std::vector<double>& cu, const std::vector<int>& cnt, int
     if (waves < 8.0) t /= 0.9;  // fewer than two waves per SIMD
     worst = std::max(worst, t);
   }
-  return worst / eff_r[r];
+  return worst / (eff_r[r] * eff_w);
 }
 
 // Plans by call shape, shared by all streams of the process (a stream also
