@@ -558,7 +558,8 @@ __global__ __launch_bounds__(64 * W) void k_gather(GatherCall d, int n_tiles) {
 // MIXED: some calls keep an FP64 tail (both tail types compiled in);
 // otherwise the FP32-tail code alone, which needs fewer registers.
 template <int R, bool MIXED>
-__global__ __launch_bounds__(64) void k_gather_batched(const unsigned char* __restrict__ table) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_gather_batched(
+    const unsigned char* __restrict__ table) {
   const BatchHeader hd = *reinterpret_cast<const BatchHeader*>(table);
   const GatherCall* __restrict__ calls = reinterpret_cast<const GatherCall*>(table + hd.off_calls);
   const int32_t* __restrict__ call_fp64 = reinterpret_cast<const int32_t*>(table + hd.off_fp64);
