@@ -373,6 +373,58 @@ __device__ __forceinline__ void chunk_store(const ChunkGeo& g, int lane, const P
   }
 }
 
+// One-wave tiles: a lane's run of tail slots moves as 16-byte vectors when it
+// neither wraps around the ring nor crosses the live, emitted or written
+// boundary (every lane but a few at those boundaries); the others move value
+// by value.  In short calls (a few blocks per stream, as in serving steps)
+// the tail traffic dominates the tile.  Multi-wave tiles own a few outputs
+// per lane and keep the value-by-value form, which schedules better there.
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<float> {
+  typedef float type __attribute__((ext_vector_type(4))) __attribute__((aligned(4)));
+  static constexpr int N = 4;
+};
+template <>
+struct Vec16<double> {
+  typedef double type __attribute__((ext_vector_type(2))) __attribute__((aligned(8)));
+  static constexpr int N = 2;
+};
+
+template <typename T, int Q>
+__device__ __forceinline__ void load_run(const GLB T* p, T (&v)[Q]) {
+  constexpr int N = Vec16<T>::N;
+  if constexpr (Q % N == 0) {
+#pragma unroll
+    for (int k = 0; k < Q / N; ++k) {
+      const typename Vec16<T>::type u = *reinterpret_cast<const GLB typename Vec16<T>::type*>(p + k * N);
+#pragma unroll
+      for (int j = 0; j < N; ++j) v[k * N + j] = u[j];
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) v[q] = p[q];
+  }
+}
+
+template <typename T, int Q>
+__device__ __forceinline__ void store_run(GLB T* p, const T (&v)[Q]) {
+  constexpr int N = Vec16<T>::N;
+  if constexpr (Q % N == 0) {
+#pragma unroll
+    for (int k = 0; k < Q / N; ++k) {
+      typename Vec16<T>::type u;
+#pragma unroll
+      for (int j = 0; j < N; ++j) u[j] = v[k * N + j];
+      *reinterpret_cast<GLB typename Vec16<T>::type*>(p + k * N) = u;
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) p[q] = v[q];
+  }
+}
+
 // One output tile of one channel of one call.  W waves share the tile; wave
 // w handles chunks w, w+W, ... of each round and the partial sums are added
 // to the accumulators in chunk order after every round.  Each wave keeps the
@@ -396,17 +448,24 @@ __device__ __forceinline__ void gather_tile(const GatherCall& d, int c, int tile
   const int nq = n0 + lane * R + q0;
   GLB TailT* ring = gw(reinterpret_cast<TailT*>(d.ring)) + (int64_t)c * d.ring_cstride;
 
+  // slot of the lane's first output (its run is contiguous unless it wraps)
+  int s0 = d.head + nq;
+  if (s0 >= d.Rcap) s0 -= d.Rcap;
   TailT acc[QM];
+  if (W == 1 && qn == QM && nq + QM <= d.live_in && s0 + QM <= d.Rcap) {
+    load_run<TailT, QM>(ring + s0, acc);
+  } else {
 #pragma unroll
-  for (int q = 0; q < QM; ++q) {
-    const int n = nq + q;
-    TailT v = 0;
-    if (q < qn && n < d.live_in) {
-      int slot = d.head + n;
-      if (slot >= d.Rcap) slot -= d.Rcap;
-      v = ring[slot];
+    for (int q = 0; q < QM; ++q) {
+      const int n = nq + q;
+      TailT v = 0;
+      if (q < qn && n < d.live_in) {
+        int slot = d.head + n;
+        if (slot >= d.Rcap) slot -= d.Rcap;
+        v = ring[slot];
+      }
+      acc[q] = v;
     }
-    acc[q] = v;
   }
 
   if (d.x != nullptr) {
@@ -521,17 +580,32 @@ __device__ __forceinline__ void gather_tile(const GatherCall& d, int c, int tile
 
   {
     GLB float* yc = gw(d.y) + (int64_t)c * d.y_cstride;
+    const bool whole = W == 1 && qn == QM && nq + QM <= d.n_out && s0 + QM <= d.Rcap;
+    if (whole && nq + QM <= d.S) {          // all emitted: outputs out, slots cleared
+      float yv[QM];
+      TailT z[QM];
 #pragma unroll
-    for (int q = 0; q < QM; ++q) {
-      const int n = nq + q;
-      if (q < qn && n < d.n_out) {
-        int slot = d.head + n;
-        if (slot >= d.Rcap) slot -= d.Rcap;
-        if (n < d.S) {
-          yc[n] = (float)acc[q];
-          ring[slot] = (TailT)0;
-        } else {
-          ring[slot] = acc[q];
+      for (int q = 0; q < QM; ++q) {
+        yv[q] = (float)acc[q];
+        z[q] = (TailT)0;
+      }
+      store_run<float, QM>(yc + nq, yv);
+      store_run<TailT, QM>(ring + s0, z);
+    } else if (whole && nq >= d.S) {        // all kept in the tail
+      store_run<TailT, QM>(ring + s0, acc);
+    } else {
+#pragma unroll
+      for (int q = 0; q < QM; ++q) {
+        const int n = nq + q;
+        if (q < qn && n < d.n_out) {
+          int slot = d.head + n;
+          if (slot >= d.Rcap) slot -= d.Rcap;
+          if (n < d.S) {
+            yc[n] = (float)acc[q];
+            ring[slot] = (TailT)0;
+          } else {
+            ring[slot] = acc[q];
+          }
         }
       }
     }
