@@ -1335,6 +1335,19 @@ int taches_pool_step_strided(taches_pool* p, int32_t n, taches_stream* const* st
       }
       return work;
     };
+    // Tiles [flat_lo, flat_hi) of a call are reached by all its S input
+    // samples (or, without input, all tiles): their work is the same.  The
+    // work of the others rises or falls by T per tile at the two ends.
+    auto flat_range = [T](const GatherCall& g, int64_t nt, int64_t* lo, int64_t* hi) {
+      if (!g.x) {
+        *lo = 0;
+        *hi = nt;
+        return;
+      }
+      *lo = std::max<int64_t>(0, (g.S + T - 1) / T - 1);                 // (t + 1) T >= S
+      *hi = std::min<int64_t>(nt, (int64_t)(g.Lmax_call - 1) / T + 1);   // t T <= Lmax - 1
+      if (*hi < *lo) *hi = *lo;
+    };
     const int per_cu = taches::gather_batched_waves_per_cu(r, mixed);
     const int64_t wg_max = 256LL * per_cu;
     int64_t n_tiles = 0, tiles_work = 0, tile_max = 1;
@@ -1342,26 +1355,40 @@ int taches_pool_step_strided(taches_pool* p, int32_t n, taches_stream* const* st
       const GatherCall& g = plans[gather_ids[k]].g;
       const int64_t nt = (g.n_out + T - 1) / T;
       n_tiles += nt * g.channels;
-      for (int64_t t = 0; t < nt; ++t) {
-        const int64_t w = tile_work(g, t);
-        tiles_work += w * g.channels;
-        tile_max = std::max(tile_max, w);
-      }
+      int64_t lo, hi;
+      flat_range(g, nt, &lo, &hi);
+      int64_t sum = 0;
+      for (int64_t t = 0; t < lo; ++t) sum += tile_work(g, t);
+      for (int64_t t = hi; t < nt; ++t) sum += tile_work(g, t);
+      if (hi > lo) sum += (hi - lo) * tile_work(g, lo);
+      tiles_work += sum * g.channels;
+      for (int64_t t : {(int64_t)0, lo, hi - 1, hi, nt - 1})
+        if (t >= 0 && t < nt) tile_max = std::max(tile_max, tile_work(g, t));
     }
-    // With very many small tiles (a step of one or a few blocks per stream
-    // touches every tail slot of every stream), consecutive tiles are merged
-    // into items of about 1/16 of a workgroup's share, so the table and its
-    // planning shrink; otherwise one item per tile.
-    const int64_t span_work = n_tiles > 64 * wg_max ? std::max(tile_max, tiles_work / (16 * wg_max)) : 0;
+    // With many small tiles (more than 32 per resident workgroup, as in a
+    // step of one or a few blocks per stream, which touches every tail slot
+    // of every stream), consecutive tiles are merged into items of about
+    // 1/16 of a workgroup's share, so the table and its planning shrink;
+    // otherwise one item per tile.
+    const int64_t span_work = n_tiles > 32 * wg_max ? std::max(tile_max, tiles_work / (16 * wg_max)) : 0;
     std::vector<Item> items;
     items.reserve(span_work ? (size_t)(tiles_work / span_work + ng * 2 + 16) : (size_t)n_tiles);
     for (int k = 0; k < ng; ++k) {
       const GatherCall& g = plans[gather_ids[k]].g;
       const int64_t nt = (g.n_out + T - 1) / T;
+      int64_t flo, fhi;
+      flat_range(g, nt, &flo, &fhi);
       for (int c = 0; c < g.channels; ++c) {
         int64_t t = 0;
         while (t < nt) {
           int64_t t1 = t + 1, w = tile_work(g, t);
+          if (span_work && t >= flo && t < fhi) {
+            // equal tiles: as many as fit in span_work, within the flat range
+            const int64_t m = std::max<int64_t>(1, std::min<int64_t>({span_work / w, fhi - t, 65535}));
+            items.push_back({WorkItem{k, c, (int32_t)t, (int32_t)m}, w * m});
+            t += m;
+            continue;
+          }
           if (span_work) {
             while (t1 < nt && t1 - t < 65535) {
               const int64_t w1 = tile_work(g, t1);
