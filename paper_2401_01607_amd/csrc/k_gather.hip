@@ -181,16 +181,6 @@ struct ChunkDesc {
   BlockIR ir;
 };
 
-// Wave-uniform values loaded with vector loads: keep them in scalar registers.
-__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
-template <typename T>
-__device__ __forceinline__ const T* uni(const T* p) {
-  const uint64_t a = reinterpret_cast<uint64_t>(p);
-  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
-  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
-  return reinterpret_cast<const T*>(((uint64_t)hi << 32) | lo);
-}
-
 __device__ __forceinline__ ChunkDesc chunk_desc(const GatherCall& d, int ck) {
   ChunkDesc c;
   if (d.ctab) {
@@ -206,11 +196,6 @@ __device__ __forceinline__ ChunkDesc chunk_desc(const GatherCall& d, int ck) {
     c.len = b * d.B + ((i + 1) * d.B) / d.cpb - c.m_lo;
     c.ir = d.irs ? load_ir(d.irs, b) : d.ir0;
   }
-  // a chunk's descriptor is the same for the whole wave (ck is)
-  c.m_lo = uni(c.m_lo);
-  c.len = uni(c.len);
-  c.ir.h = uni(c.ir.h);
-  c.ir.L = uni(c.ir.L);
   return c;
 }
 
