@@ -229,7 +229,9 @@ int taches_read_tail(taches_stream* s, int32_t channel, double* out, int32_t n);
 int taches_reset(taches_stream* s);
 
 /* Force the gather tile shape (R outputs per lane in {4, 8, 12, 14, 16}, W waves
- * per output tile in {1, 2, 4}); 0, 0 = automatic choice per call. */
+ * per output tile in {1, 2, 4}); 0, 0 = automatic choice per call.  A forced
+ * shape keeps the automatic choice of launch order (the order in which
+ * output tiles are handed to workgroups).  Results do not depend on either. */
 int taches_set_tile(taches_stream* s, int32_t r, int32_t w);
 
 /* ---- a6/a7: pools — many streams advanced by one batched launch ----------

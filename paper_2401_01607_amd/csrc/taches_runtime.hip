@@ -310,31 +310,33 @@ double plan_cost(const std::vector<double>& cu, const std::vector<int>& cnt, int
 // Plans by call shape, shared by all streams of the process (a stream also
 // keeps its last plan): a call shape seen before is not simulated again.
 std::mutex g_plan_mu;
-std::map<std::array<int64_t, 5>, TilePlan> g_plans;
+std::map<std::array<int64_t, 6>, TilePlan> g_plans;
 
 TilePlan pick_tile(const taches_stream* s, int64_t S, int64_t n_out, int64_t lmax, int chunks_per_tile) {
   TilePlan best;
-  if (s->force_r) {
-    best.r = s->force_r;
-    best.w = s->force_w ? s->force_w : 1;
-    best.order = 2;
-    return best;
-  }
-  const std::array<int64_t, 5> key = {S, n_out, lmax, s->cfg.channels, chunks_per_tile};
+  // a forced shape still gets the launch order the estimate prefers for it
+  const int force = s->force_r ? s->force_r * 8 + (s->force_w ? s->force_w : 1) : 0;
+  const std::array<int64_t, 6> key = {S, n_out, lmax, s->cfg.channels, chunks_per_tile, force};
   {
     std::lock_guard<std::mutex> lk(g_plan_mu);
     auto it = g_plans.find(key);
     if (it != g_plans.end()) return it->second;
   }
-  static const int rs[5] = {16, 14, 12, 8, 4};
-  static const int ws[3] = {1, 2, 4};
+  static const int rs_auto[5] = {16, 14, 12, 8, 4};
+  static const int ws_auto[3] = {1, 2, 4};
+  const int rs_forced[1] = {force >> 3}, ws_forced[1] = {force & 7};
+  const int* rs = force ? rs_forced : rs_auto;
+  const int* ws = force ? ws_forced : ws_auto;
+  const int nr = force ? 1 : 5, nw = force ? 1 : 3;
   double best_cost = 1e300;
   std::vector<double> cu[3];
   std::vector<int> cnt[3];
-  for (int r : rs) {
+  for (int ir = 0; ir < nr; ++ir) {
+    const int r = rs[ir];
     for (int order = 0; order < 3; ++order) plan_loads(S, n_out, lmax, s->cfg.channels, r, order, cu[order], cnt[order]);
-    for (int w : ws) {
-      if (w > 1 && chunks_per_tile < 2 * w) continue;
+    for (int iw = 0; iw < nw; ++iw) {
+      const int w = ws[iw];
+      if (!force && w > 1 && chunks_per_tile < 2 * w) continue;
       for (int order = 0; order < 3; ++order) {
         const double c = plan_cost(cu[order], cnt[order], r, w);
         if (c < best_cost * 0.999) {
