@@ -1370,9 +1370,9 @@ int taches_pool_step_strided(taches_pool* p, int32_t n, taches_stream* const* st
     // With many small tiles (more than 32 per resident workgroup, as in a
     // step of one or a few blocks per stream, which touches every tail slot
     // of every stream), consecutive tiles are merged into items of about
-    // 1/16 of a workgroup's share, so the table and its planning shrink;
-    // otherwise one item per tile.
-    const int64_t span_work = n_tiles > 32 * wg_max ? std::max(tile_max, tiles_work / (16 * wg_max)) : 0;
+    // 1/8 of a workgroup's share, so the table, its planning and the
+    // kernel's per-item work shrink; otherwise one item per tile.
+    const int64_t span_work = n_tiles > 32 * wg_max ? std::max(tile_max, tiles_work / (8 * wg_max)) : 0;
     std::vector<Item> items;
     items.reserve(span_work ? (size_t)(tiles_work / span_work + ng * 2 + 16) : (size_t)n_tiles);
     for (int k = 0; k < ng; ++k) {
@@ -1380,17 +1380,19 @@ int taches_pool_step_strided(taches_pool* p, int32_t n, taches_stream* const* st
       const int64_t nt = (g.n_out + T - 1) / T;
       int64_t flo, fhi;
       flat_range(g, nt, &flo, &fhi);
+      // equal tiles of the flat range: as many per item as fit in span_work
+      const int64_t w_flat = fhi > flo ? tile_work(g, flo) : 1;
+      const int64_t m_flat = span_work ? std::max<int64_t>(1, std::min<int64_t>(span_work / w_flat, 65535)) : 1;
       for (int c = 0; c < g.channels; ++c) {
         int64_t t = 0;
         while (t < nt) {
-          int64_t t1 = t + 1, w = tile_work(g, t);
           if (span_work && t >= flo && t < fhi) {
-            // equal tiles: as many as fit in span_work, within the flat range
-            const int64_t m = std::max<int64_t>(1, std::min<int64_t>({span_work / w, fhi - t, 65535}));
-            items.push_back({WorkItem{k, c, (int32_t)t, (int32_t)m}, w * m});
+            const int64_t m = std::min<int64_t>(m_flat, fhi - t);
+            items.push_back({WorkItem{k, c, (int32_t)t, (int32_t)m}, w_flat * m});
             t += m;
             continue;
           }
+          int64_t t1 = t + 1, w = tile_work(g, t);
           if (span_work) {
             while (t1 < nt && t1 - t < 65535) {
               const int64_t w1 = tile_work(g, t1);
@@ -1418,15 +1420,22 @@ int taches_pool_step_strided(taches_pool* p, int32_t n, taches_stream* const* st
     std::vector<int> count(nwg, 0);
     std::vector<int64_t> load(nwg, 0);
     const size_t n_items = items.size();
-    if (total_work >= 8 * max_work * (int64_t)nwg && n_items >= 16 * (size_t)nwg) {
-      // many small items: cut the list, in stream and tile order, into nwg
-      // runs of near-equal work (item i goes to the workgroup holding the
-      // middle of its work).  O(n), no sort; no workgroup exceeds the mean
-      // by more than one item, which is at most 1/8 of the mean here.
-      int64_t before = 0;
+    if ((span_work > 0 && n_items >= 8 * (size_t)nwg) ||
+        (total_work >= 8 * max_work * (int64_t)nwg && n_items >= 16 * (size_t)nwg)) {
+      // merged runs (at most one merge span each) or many small items: cut
+      // the list, in stream and tile order, into nwg runs of near-equal work
+      // (item i goes to the workgroup holding the middle of its work).  O(n),
+      // no sort; no workgroup exceeds the mean by more than one item.  The
+      // owner never decreases along the list, so a moving boundary replaces
+      // a division per item.
+      int64_t before = 0, bound = 2 * total_work;   // (b + 1) * 2 * total_work
+      int b = 0;
       for (size_t i = 0; i < n_items; ++i) {
         const int64_t mid2 = 2 * before + items[i].work;   // twice the item's midpoint
-        const int b = (int)std::min<int64_t>(nwg - 1, mid2 * nwg / (2 * total_work));
+        while (b < nwg - 1 && mid2 * nwg >= bound) {
+          ++b;
+          bound += 2 * total_work;
+        }
         owner[i] = b;
         load[b] += items[i].work;
         before += items[i].work;

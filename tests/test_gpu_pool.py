@@ -353,6 +353,48 @@ def test_many_tiles_are_merged_into_range_items_exactly():
     pool.close()
 
 
+def test_heavy_and_light_streams_in_one_step_exactly():
+    """256 light streams (one block of 64 per step) and 2 heavy ones (40
+    blocks of 512 per step), L = 16 384, R = 16: every tile is one item
+    (too few tiles to merge), many per workgroup, with tiles of very
+    different work (dealt out largest first); the heavy streams and sampled
+    light ones equal their solo runs bit for bit."""
+    import torch
+    T = binding()
+    n_light, L, steps = 256, 16384, 2
+    specs = [(64, 1, 700 + i) for i in range(n_light)] + [(512, 40, 900), (512, 40, 901)]
+    h = torch.from_numpy(W.impulse_response(L, 95)).cuda()
+    pool = T.Pool(len(specs), 64 * GB, use_graph=True, tile_r=16)
+    ss, xs, ys = [], [], []
+    for B, nb, seed in specs:
+        s = T.Stream(B, L, max_blocks_per_call=nb)
+        s.set_ir(h)
+        assert pool.attach(s) == T.TACHES_OK
+        ss.append(s)
+        xs.append(torch.from_numpy(W.signal_gauss(steps * nb * B, seed)).cuda())
+        ys.append(torch.empty(steps * nb * B, device="cuda"))
+    sp = np.array([s.h for s in ss], np.uint64)
+    nbs = np.array([nb for _, nb, _ in specs], np.int32)
+    for k in range(steps):
+        xp = np.array([x.data_ptr() + 4 * k * nb * B for x, (B, nb, _) in zip(xs, specs)], np.uint64)
+        yp = np.array([y.data_ptr() + 4 * k * nb * B for y, (B, nb, _) in zip(ys, specs)], np.uint64)
+        pool.step_strided(sp, xp, None, yp, None, nbs)
+    pool.synchronize()
+    info = pool.info()
+    assert info.last_r == 16
+    assert info.last_items == n_light * -(-(64 + L - 1) // 1024) + 2 * -(-(40 * 512 + L - 1) // 1024)
+    assert info.last_items >= 8 * info.last_workgroups
+    hn = h.cpu().numpy()
+    for i in list(range(0, n_light, 37)) + [n_light, n_light + 1]:
+        B, nb, _ = specs[i]
+        y = _alone(xs[i].cpu().numpy(), hn, B, L, steps * nb)
+        assert np.array_equal(ys[i].cpu().numpy(), y), f"stream {i}"
+    for s in ss:
+        pool.detach(s)
+        s.close()
+    pool.close()
+
+
 def test_sample_accurate_swap_on_attached_stream():
     """taches_set_ir_at on a stream attached to a pool applies at its next
     step, from the given sample: equals the oracle exactly (integers)."""
