@@ -29,7 +29,10 @@ streams that are admitted, swap IRs or retire in it.
 Executor interface: admit(req) -> int handle (raises AdmissionRefused),
 set_ir(handle, req, version), step(handles, k0, n) with int64 arrays (stream
 handles[i] processes blocks k0[i] .. k0[i]+n[i]-1; outputs ready on
-return), retire(handle, req), and an attribute max_blocks_per_step.
+return), retire(handle, req), and an attribute max_blocks_per_step.  An
+executor may also offer launch(handles, k0, n) and wait() (the step split
+at its device work): the scheduler then prepares its block records while
+the device runs; a block still counts as done when wait() returns.
 """
 from __future__ import annotations
 
@@ -253,7 +256,14 @@ class Scheduler:
         n = end - k0
         self._last_step_s = now
         t0 = time.perf_counter()
-        self.ex.step(t.handle[idx], k0, n)                  # outputs ready on return
+        if hasattr(self.ex, "launch"):
+            # the block records are prepared while the device runs the step
+            self.ex.launch(t.handle[idx], k0, n)
+            rec = self._record_begin(start[idx], k0, n, Bi, is_in, t.L[idx], t.C[idx])
+            self.ex.wait()                                  # outputs ready
+        else:
+            self.ex.step(t.handle[idx], k0, n)              # outputs ready on return
+            rec = self._record_begin(start[idx], k0, n, Bi, is_in, t.L[idx], t.C[idx])
         elapsed = time.perf_counter() - t0
         self.stats.busy_s += elapsed
         if self._clock is not None:
@@ -261,7 +271,7 @@ class Scheduler:
         else:
             done_s = now + (elapsed if self.step_cost_s is None else self.step_cost_s)
         self.stats.steps += 1
-        self._record(done_s, start[idx], k0, n, Bi, is_in, t.L[idx], t.C[idx])
+        self._record_end(done_s, rec)
         t.nxt[idx] = end
         for i in sorted(np.nonzero(t.nxt[:t.n] >= t.n_total[:t.n])[0], reverse=True):
             a = t.remove(int(i))
@@ -271,8 +281,10 @@ class Scheduler:
             self.stats.completed += 1
         return True
 
-    def _record(self, done_s, start, k0, n, B, is_in, L, C) -> None:
-        """Latency of every block of the step's ranges (vectorized)."""
+    def _record_begin(self, start, k0, n, B, is_in, L, C):
+        """Counters of the step, and the arrival time and deadline of every
+        block of its ranges after the warm-up (vectorized; independent of
+        when the step completes)."""
         st = self.stats
         tot = int(n.sum())
         st.blocks += tot
@@ -285,9 +297,13 @@ class Scheduler:
         # block k is complete at start + (k+1) B / fs
         ready_s = start[rng] + (k + 1) * per
         keep = ready_s >= self.warmup_s
-        if keep.any():
-            st._lat.append(done_s - ready_s[keep])
-            st._dl.append(per[keep])
+        return (ready_s[keep], per[keep]) if keep.any() else None
+
+    def _record_end(self, done_s, rec) -> None:
+        """Latency of every recorded block: step completion minus arrival."""
+        if rec is not None:
+            self.stats._lat.append(done_s - rec[0])
+            self.stats._dl.append(rec[1])
 
     # -- drivers -----------------------------------------------------------
     def run_realtime(self, duration_s: float, clock=time.perf_counter, sleep=time.sleep) -> dict:
@@ -462,7 +478,9 @@ class GpuExecutor:
     def set_ir(self, handle, req, version: int):
         self.live[handle][0].set_ir(self.ir(req, version))
 
-    def step(self, handles, k0, n) -> None:
+    def launch(self, handles, k0, n) -> None:
+        """Enqueue one pool step (stream handles[i] processes blocks k0[i] ..
+        k0[i]+n[i]-1); returns once it is queued on the device."""
         B, C = self.h_B[handles], self.h_C[handles]
         adv = (4 * k0 * B).astype(np.uint64)                # byte offset of block k0
         xp = np.where(k0 < self.h_nin[handles], self.h_x[handles] + adv, np.uint64(0)).astype(np.uint64)
@@ -476,7 +494,14 @@ class GpuExecutor:
         yp = np.where(kept, yk + adv, np.uint64(self.scratch.data_ptr()) + off).astype(np.uint64)
         self.pool.step_strided(self.h_stream[handles], xp, np.full(handles.size, self.bank_len, np.int64), yp,
                                np.where(kept, self.h_ycs[handles], 0), n.astype(np.int32))
+
+    def wait(self) -> None:
+        """Block until the launched step's outputs are ready."""
         self.pool.synchronize()
+
+    def step(self, handles, k0, n) -> None:
+        self.launch(handles, k0, n)
+        self.wait()
 
     @property
     def device_s(self) -> float:

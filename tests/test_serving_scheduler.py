@@ -148,3 +148,44 @@ def test_continuous_batching_joins_streams_in_one_step():
     sch2 = Scheduler(reqs, ex2, step_cost_s=0.0, min_tick_s=5e-3)
     sch2.run_simulated(10.0)
     assert max(ex2.steps) >= 4 and len(ex2.steps) < len(ex.steps) * 3
+
+
+class SplitOracleExecutor(OracleExecutor):
+    """The same executor offering the step split into launch and wait."""
+
+    def __init__(self, *a, **k):
+        super().__init__(*a, **k)
+        self.calls, self._queued = [], None
+
+    def launch(self, handles, k0s, ns):
+        assert self._queued is None, "one step at a time"
+        self.calls.append("launch")
+        self._queued = (handles.copy(), k0s.copy(), ns.copy())
+
+    def wait(self):
+        assert self._queued is not None
+        self.calls.append("wait")
+        self.step(*self._queued)
+        self._queued = None
+
+
+def test_split_launch_and_wait_give_the_same_records():
+    """An executor with launch/wait: the scheduler prepares the block records
+    between the two calls, and the run (outputs, latencies, deadlines,
+    counters) equals the run through step() on the same simulated clock."""
+    reqs = _reqs(30, 200.0)
+    runs = []
+    for cls in (OracleExecutor, SplitOracleExecutor):
+        ex = cls(max_streams=8, budget=1 << 30, max_blocks_per_step=16)
+        sch = Scheduler(reqs, ex, step_cost_s=4e-3, warmup_s=0.02)
+        st = sch.run_simulated(10.0)
+        runs.append((ex, sch, st))
+    (ex_a, sch_a, st_a), (ex_b, sch_b, st_b) = runs
+    assert ex_b.calls and ex_b.calls == ["launch", "wait"] * (len(ex_b.calls) // 2)
+    busy = "step_busy_fraction"          # measured host time, not simulated
+    assert {k: v for k, v in st_a.items() if k != busy} == {k: v for k, v in st_b.items() if k != busy}
+    assert np.array_equal(sch_a.stats.latencies_s, sch_b.stats.latencies_s)
+    assert np.array_equal(sch_a.stats.deadlines_s, sch_b.stats.deadlines_s)
+    assert sch_a.stats.latencies_s.size > 0
+    for r in reqs:
+        assert np.array_equal(ex_a.out[r.rid][1], ex_b.out[r.rid][1])
