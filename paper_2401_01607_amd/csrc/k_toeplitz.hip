@@ -34,10 +34,6 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-struct BFrag {
-  bf16x8 h0, l0, h1, l1;  // hi/lo B fragments of the two 32-channel tiles
-};
-
 constexpr int MT = 128;                    // output slots per workgroup (MT / 32 waves x 32 rows)
 constexpr int NT = 2 * MT;                 // threads per workgroup
 constexpr int KC = CHUNK_MAX;              // longest chunk (samples)
