@@ -353,6 +353,49 @@ def test_many_tiles_are_merged_into_range_items_exactly():
     pool.close()
 
 
+def test_config4_full_size_sampled_parity():
+    """Full batched-workload size in the benchmark's launch configuration:
+    512 streams of 96 000 samples (L log-uniform in [256, 131 072], B in
+    {32..512}), every stream's whole input in one pool step replayed from
+    the pool's graph; sampled outputs of 15 streams (the longest IR among
+    them) against Eq. (4) in FP64."""
+    import torch
+    from oracle import oracle as O
+    T = binding()
+    Ls, Bs = W.config4_draws()
+    n = 96_000
+    nbs = [-(-n // int(B)) for B in Bs]
+    pool = T.Pool(len(Ls), 64 * GB, use_graph=True)
+    ss, xs, ys, irs = [], [], [], []
+    for i, (L, B) in enumerate(zip(Ls, Bs)):
+        L, B = int(L), int(B)
+        xp = np.zeros(nbs[i] * B, np.float32)
+        xp[:n] = W.signal_gauss(n, 410_000 + i)
+        irs.append(W.impulse_response(L, 420_000 + i))
+        s = T.Stream(B, L, max_blocks_per_call=nbs[i])
+        s.set_ir(irs[-1])
+        assert pool.attach(s) == T.TACHES_OK
+        ss.append(s)
+        xs.append(torch.from_numpy(xp).cuda()[None])
+        ys.append(torch.empty_like(xs[-1]))
+    pool.step(ss, xs, ys, nbs)
+    pool.synchronize()
+    picks = sorted(set(list(range(0, len(Ls), 37)) + [int(np.argmax(Ls))]))
+    rng = np.random.default_rng(404)
+    for i in picks:
+        B, S = int(Bs[i]), nbs[i] * int(Bs[i])
+        y = ys[i].cpu().numpy()[0].astype(np.float64)
+        idx = set(rng.integers(0, S, 40).tolist()) | {0, 1, n - 1, n, S - 1}
+        idx = np.array(sorted(j for j in idx if 0 <= j < S))
+        ref = O.sampled_outputs(xs[i].cpu().numpy()[0], [irs[i]], [(0, 0)], B, idx)
+        rms = float(np.sqrt(np.mean(y ** 2)))
+        assert np.max(np.abs(y[idx] - ref)) <= 1e-5 * rms, f"stream {i} (L={int(Ls[i])}, B={B})"
+    for s in ss:
+        pool.detach(s)
+        s.close()
+    pool.close()
+
+
 def test_heavy_and_light_streams_in_one_step_exactly():
     """256 light streams (one block of 64 per step) and 2 heavy ones (40
     blocks of 512 per step), L = 16 384, R = 16: every tile is one item
