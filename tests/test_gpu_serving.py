@@ -123,3 +123,44 @@ def test_split_bf16_mix_equals_alone_and_within_bound():
             err = np.abs(y_planar.astype(np.float64) - ref)
             assert err.max() <= 1e-4 * np.sqrt(np.mean(ref ** 2))
     ex.close()
+
+
+def test_config5_full_load_sampled_parity():
+    """The serving workload at full size (Poisson 200 streams/s of 10-60 s,
+    L log-uniform in [512, 262 144], mono/stereo, B in {32..512}, IR swaps
+    at 0.5/s, 4096 slots, 64 GiB) driven on a simulated clock (2 ms per
+    step) through the real executor until about 3 700 streams are active;
+    short early requests are kept and, after retiring, checked on sampled
+    outputs (both sides of every applied swap) against Eq. (4) in FP64."""
+    from oracle import oracle as O
+    from paper_2401_01607_amd.serving import GpuExecutor, Scheduler
+    horizon = 20.0
+    reqs = W.config5_requests(horizon_s=horizon)
+    done_by = [r for r in reqs if r.arrival_s < 3.0 and r.arrival_s + r.duration_s + r.ir_len / W.FS < horizon - 2.0]
+    keep = [r.rid for r in sorted(done_by, key=lambda r: -r.ir_len)[:2]] + [r.rid for r in done_by[:2]]
+    ex = GpuExecutor(max_streams=4096, hbm_budget_bytes=64 << 30, use_graph=True, keep_outputs=keep)
+    sch = Scheduler(reqs, ex, step_cost_s=0.002)
+    st = sch.run_simulated(horizon)
+    assert st["max_active_streams"] >= 3000
+    rng = np.random.default_rng(505)
+    checked = 0
+    for rid in dict.fromkeys(keep):
+        req = next(r for r in reqs if r.rid == rid)
+        hist = sch.history[rid]
+        x_in, y_mix = ex.kept[rid]
+        irs = [ex.ir(req, v).cpu().numpy() for v in range(len(hist.swap_blocks) + 1)]
+        sched = [(0, 0)] + [(b, v + 1) for v, b in enumerate(hist.swap_blocks)]
+        x = x_in.transpose(1, 0, 2).reshape(req.channels, -1)
+        y = y_mix.transpose(1, 0, 2).reshape(req.channels, -1).astype(np.float64)
+        S = y.shape[1]
+        idx = set(rng.integers(0, S, 40).tolist()) | {0, x.shape[1] - 1, x.shape[1], S - 1}
+        for b in hist.swap_blocks:
+            idx.update([b * req.block - 1, b * req.block])
+        idx = np.array(sorted(j for j in idx if 0 <= j < S))
+        for c in range(req.channels):
+            ref = O.sampled_outputs(x[c], irs, sched, req.block, idx)
+            rms = float(np.sqrt(np.mean(y[c] ** 2)))
+            assert np.max(np.abs(y[c][idx] - ref)) <= 1e-5 * rms, f"request {rid} channel {c}"
+        checked += 1
+    assert checked >= 3
+    ex.close()
