@@ -240,8 +240,10 @@ int taches_set_tile(taches_stream* s, int32_t r, int32_t w);
  * sum of the attached streams' device_bytes).  taches_pool_step advances a
  * set of attached streams by n_blocks[i] blocks each in one persistent
  * launch: the host cuts every stream's call into output tiles and spreads
- * them over the resident workgroups, largest first.  Each stream's result
- * is bit-identical to processing it alone.  While attached, a stream's
+ * them over the resident workgroups: when tiles are many, runs of
+ * consecutive tiles are cut in stream order into shares of equal work;
+ * otherwise the largest are dealt first.  Each stream's result is
+ * bit-identical to processing it alone, whatever the assignment.  While attached, a stream's
  * device work runs on the pool's HIP stream; taches_set_ir and
  * taches_load_ir_slot stay usable (a pending IR applies at the stream's next
  * step); taches_process* and taches_close return TACHES_EBUSY. */
