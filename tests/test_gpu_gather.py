@@ -199,6 +199,41 @@ def test_long_ir_auto_picks_fp64_tail():
     s.close()
 
 
+def test_longest_ir_4m_taps_streaming_sampled_parity():
+    """A stream with a 4 194 304-tap IR (FP64 tail chosen automatically):
+    40 blocks of 256 in one call, then the whole temporal overflow (16 384
+    zero blocks) in one NULL-input call; sampled outputs against Eq. (4) in
+    FP64, and the tail empty afterwards."""
+    import torch
+    from oracle import oracle as O
+    from tests.gpu_harness import binding
+    T = binding()
+    B, L, nb = 256, 1 << 22, 40
+    nbd = -(-(L - 1) // B)
+    s = T.Stream(B, L, max_blocks_per_call=nbd)
+    assert s.info().tail_fp64 == 1
+    x = W.signal_gauss(nb * B, 141)
+    h = W.impulse_response(L, 142)
+    s.set_ir(h)
+    xd = torch.from_numpy(x).cuda()[None]
+    yd = torch.empty_like(xd)
+    yt = torch.empty((1, nbd * B), device="cuda")
+    s.process_blocks(xd, yd, nb)
+    s.process_blocks(None, yt, nbd)
+    s.synchronize()
+    assert s.info().live == 0
+    y = torch.cat([yd, yt], 1).cpu().numpy()[0].astype(np.float64)
+    n_out = nb * B + L - 1
+    rng = np.random.default_rng(143)
+    idx = set(rng.integers(0, n_out, 300).tolist()) | {0, nb * B - 1, nb * B, L - 1, L, n_out - 1}
+    idx = np.array(sorted(idx))
+    ref = O.sampled_outputs(x, [h], [(0, 0)], B, idx)
+    rms = float(np.sqrt(np.mean(y[:n_out] ** 2)))
+    assert np.max(np.abs(y[idx] - ref)) <= 1e-5 * rms
+    assert not np.any(y[n_out:])
+    s.close()
+
+
 def test_config2_full_size_sampled_parity():
     """Full config-2 size in the benchmark's launch configuration (one
     1875-block call with the IR schedule, then a NULL-input drain), checked

@@ -67,3 +67,22 @@ def test_errors():
     assert T.lib.taches_convolve(None, 10, 1, T._dev_ptr(h), 4, T._dev_ptr(y), 0, 0, 0, None) == T.TACHES_EINVAL
     assert T.lib.taches_convolve(T._dev_ptr(x), 0, 1, T._dev_ptr(h), 4, T._dev_ptr(y), 0, 0, 0, None) == T.TACHES_EINVAL
     assert T.lib.taches_convolve(T._dev_ptr(x), 10, 1, T._dev_ptr(h), 4, T._dev_ptr(y), 7, 0, 0, None) == T.TACHES_EINVAL
+
+
+@pytest.mark.parametrize("swap", [False, True])
+def test_longest_ir_4m_taps_sampled_parity(swap):
+    """The off-line capacity shape: 0.1 s of input (4 800 samples) through a
+    4 194 304-tap IR, in both roles; sampled outputs (the ramp, the flat part
+    and the end) against Eq. (1) in FP64."""
+    from oracle import oracle as O
+    x = W.signal_gauss(4800, 131)
+    h = W.impulse_response(1 << 22, 132)
+    y = _conv(x, h, role_swap=swap).astype(np.float64)
+    n_out = x.size + h.size - 1
+    assert y.shape == (n_out,) and np.all(np.isfinite(y))
+    rng = np.random.default_rng(133)
+    idx = set(rng.integers(0, n_out, 300).tolist()) | {0, 1, 4799, 4800, h.size - 1, h.size, n_out - 1}
+    idx = np.array(sorted(idx))
+    ref = O.sampled_outputs(x, [h], [(0, 0)], 4800, idx)
+    rms = float(np.sqrt(np.mean(y ** 2)))
+    assert np.max(np.abs(y[idx] - ref)) <= 1e-5 * rms
