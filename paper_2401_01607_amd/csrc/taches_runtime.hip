@@ -1428,13 +1428,15 @@ int taches_pool_step_strided(taches_pool* p, int32_t n, taches_stream* const* st
       // no sort; no workgroup exceeds the mean by more than one item.  The
       // owner never decreases along the list, so a moving boundary replaces
       // a division per item.
-      int64_t before = 0, bound = 2 * total_work;   // (b + 1) * 2 * total_work
+      // (128-bit products: work sums of very long calls times nwg exceed 2^63)
+      int64_t before = 0;
+      __int128 bound = 2 * (__int128)total_work;   // (b + 1) * 2 * total_work
       int b = 0;
       for (size_t i = 0; i < n_items; ++i) {
         const int64_t mid2 = 2 * before + items[i].work;   // twice the item's midpoint
-        while (b < nwg - 1 && mid2 * nwg >= bound) {
+        while (b < nwg - 1 && (__int128)mid2 * nwg >= bound) {
           ++b;
-          bound += 2 * total_work;
+          bound += 2 * (__int128)total_work;
         }
         owner[i] = b;
         load[b] += items[i].work;
