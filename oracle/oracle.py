@@ -7,12 +7,12 @@ which holds none of the method's arithmetic.
 
 Four forms of the same computation:
 
-* ``OracleStream`` (O1 FP64, O2 FP32): the paper's buffer algorithm
-  (Section 4.2, TachesAlgorithm), index-corrected, in C (``taches_oracle.c``).
-* ``vector_form`` (O3): the paper's vector algorithm (Section 4.1,
-  TachesAlgorithmVect): a residue array that receives e(n) * h, emits its
-  first element and shifts left with a zero fill, then flushes the temporal
-  overflow.  numpy, FP64.  Small inputs only.
+* ``OracleStream`` (O1 FP64, O2 FP32 with fused or separate roundings): the
+  buffer form of Section 4.2 (a circular residue that receives every
+  sample's tache, emits and clears one slot per sample), in C
+  (``taches_oracle.c``).
+* ``tache_sum`` (O3): Eq. (4) written as a sum of taches into a whole output
+  array (Section 3.2), no residue.  numpy, FP64.  Small inputs only.
 * ``brute_force`` (O4): Eq. (4) evaluated one output at a time, with exact
   Python integers / fractions.  Tiny inputs only.
 * ``sampled_outputs``: Eq. (4) for chosen output indices in FP64 with numpy
@@ -179,31 +179,28 @@ def run_channels(xs, irs, schedule, block: int, max_ir_len: int, n_blocks=None,
 
 
 # ---------------------------------------------------------------------------
-# O3: vector form (Section 4.1), FP64, small inputs.
+# O3: the sum of taches written into the output array, FP64, small inputs.
 # ---------------------------------------------------------------------------
 
-def vector_form(e: np.ndarray, h_of_sample) -> np.ndarray:
-    """TachesAlgorithmVect with a per-sample IR.
+def tache_sum(e: np.ndarray, h_of_sample) -> np.ndarray:
+    """Eq. (4) as a sum of taches (Section 3.2): input sample n adds its
+    tache e(n) * h to the output samples n .. n + len(h) - 1.
 
-    ``h_of_sample(n)`` returns the IR for input sample n (the block's IR).
-    The residue has ``Nh`` = longest IR slots.  For each sample: add
-    e(n) * h to the residue, append its first element to the output, shift
-    it left with a zero fill.  After the loop append the first Nh-1 residue
-    elements (the temporal overflow).  Output length Ne + Nh - 1.
+    ``h_of_sample(n)`` returns the IR for input sample n (the IR active when
+    n is consumed).  The output has Ne + Nh - 1 samples (Nh = longest IR),
+    the input length plus the temporal overflow (Section 4.1).  Each output
+    receives its products in input order, as in the residue of the buffer
+    form, so in FP64 the two agree bit for bit.
     """
     e = np.asarray(e, dtype=np.float32)
     Ne = e.size
-    hs = [np.asarray(h_of_sample(n), dtype=np.float32) for n in range(Ne)]
+    hs = [np.asarray(h_of_sample(n), dtype=np.float32).astype(np.float64) for n in range(Ne)]
     Nh = max(h.size for h in hs)
-    r = np.zeros(Nh, dtype=np.float64)
-    s = []
+    s = np.zeros(Ne + Nh - 1, dtype=np.float64)
     for n in range(Ne):
-        h = hs[n].astype(np.float64)
-        r[: h.size] = r[: h.size] + np.float64(e[n]) * h
-        s.append(r[0])
-        r = np.concatenate([r[1:], [0.0]])
-    s.extend(r[: Nh - 1].tolist())
-    return np.array(s, dtype=np.float64)
+        h = hs[n]
+        s[n:n + h.size] += np.float64(e[n]) * h
+    return s
 
 
 # ---------------------------------------------------------------------------

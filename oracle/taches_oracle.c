@@ -13,20 +13,19 @@
  * given sample of the next block (the "even sample-by-sample" update of
  * Section 6): the taches of that block's earlier samples use the old IR.
  *
- * How (Section 4.2, algorithm TachesAlgorithm, buffer form): a circular
- * residue r of Lmax slots and an index p.  For each input sample, in input
- * order:
- *   1. scatter e0 * h[k] into slot (p + k) mod Lmax for k = 0 .. L-1, written
- *      as the paper's two loops, one up to the end of the buffer and one
- *      after the wrap;
- *   2. the current output is r[p];
- *   3. r[p] is set to 0;
- *   4. p advances by one, wrapping to the first slot.
- * The printed listing puts h(1) one slot after the emitted one and wraps to
- * index 0 of a 1-based array; here h[0] lands on the emitted slot (so an
- * impulse returns h unchanged) and the wrap goes to the first slot.  The
- * residue and index are stream state kept across calls; the listing's
- * per-call reset would drop every tail.
+ * How (Section 4.2, buffer form): the not-yet-emitted part of the sum is
+ * kept in a circular residue r of Lmax slots; slot (p + k) mod Lmax holds the
+ * pending sum of the output k samples after the current one.  For each input
+ * sample, in input order:
+ *   1. its tache is added: r[(p + k) mod Lmax] += e0 * h[k] for k = 0 .. L-1
+ *      (Eq. 4: input sample n0 contributes e0 * h[n - n0] to output n, and
+ *      output n = n0 + k sits k slots after the current one);
+ *   2. the current output is r[p] (it now holds every tache that reaches it,
+ *      its own sample's h[0] term included: zero latency);
+ *   3. r[p] is set to 0, ready for the output Lmax samples later;
+ *   4. p advances by one slot, modulo Lmax.
+ * The residue and index are stream state kept across calls (the residue
+ * carries the remaining parts of past taches from one block to the next).
  *
  * Precision.  OR_FP64: residue in double; a product of two floats is exact
  * in double, so only the additions round.  OR_FP32_FMA: residue in float,
@@ -92,28 +91,32 @@ int or_set_ir_at(or_stream *s, const float *h, int L, int offset) {
 /* Queue an IR for the whole next block. */
 int or_set_ir(or_stream *s, const float *h, int L) { return or_set_ir_at(s, h, L, 0); }
 
-/* Scatter one tache into one channel's residue, emit, clear, (caller advances). */
+/* Add the tache of one input sample (value e0, IR h of L taps) to one
+ * channel's residue, then emit and clear the current slot p (the caller
+ * advances p).  Each slot receives its products in input-sample order. */
 static double tache_step64(double *r, int Lmax, int p, double e0, const float *h, int L) {
-  /* first loop: slots p .. min(p+L, Lmax)-1 hold h[0 .. ] */
-  int n1 = Lmax - p;
-  if (n1 > L) n1 = L;
-  for (int k = 0; k < n1; ++k) r[p + k] += e0 * (double)h[k];
-  /* second loop: after the wrap, slots 0 .. L-n1-1 hold h[n1 .. L-1] */
-  for (int k = n1; k < L; ++k) r[p + k - Lmax] += e0 * (double)h[k];
+  for (int k = 0; k < L; ++k) {
+    int j = p + k;                       /* (p + k) mod Lmax: p < Lmax and k < L <= Lmax */
+    if (j >= Lmax) j -= Lmax;
+    r[j] += e0 * (double)h[k];
+  }
   double out = r[p];
   r[p] = 0.0;
   return out;
 }
 
+/* Same in float: fused = one rounding per multiply-accumulate (fmaf);
+ * otherwise the product is rounded to float, then the sum. */
 static float tache_step32(float *r, int Lmax, int p, float e0, const float *h, int L, int fused) {
-  int n1 = Lmax - p;
-  if (n1 > L) n1 = L;
-  if (fused) {
-    for (int k = 0; k < n1; ++k) r[p + k] = fmaf(e0, h[k], r[p + k]);
-    for (int k = n1; k < L; ++k) r[p + k - Lmax] = fmaf(e0, h[k], r[p + k - Lmax]);
-  } else {
-    for (int k = 0; k < n1; ++k) { float t = e0 * h[k]; r[p + k] = r[p + k] + t; }
-    for (int k = n1; k < L; ++k) { float t = e0 * h[k]; r[p + k - Lmax] = r[p + k - Lmax] + t; }
+  for (int k = 0; k < L; ++k) {
+    int j = p + k;
+    if (j >= Lmax) j -= Lmax;
+    if (fused) {
+      r[j] = fmaf(e0, h[k], r[j]);
+    } else {
+      const float t = e0 * h[k];
+      r[j] = r[j] + t;
+    }
   }
   float out = r[p];
   r[p] = 0.0f;

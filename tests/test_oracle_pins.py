@@ -2,9 +2,11 @@
 
 Every pin is written as a function of an implementation
 ``impl(x, irs, schedule, B, Lmax, n_out) -> float64[n_out]`` so that the same
-pins run on the buffer-form oracle (O1/O2, C), on the vector-form oracle (O3)
-and on deliberately broken variants of the vector form, which must each fail
-at least one pin.
+pins run on the buffer-form oracle in its three precisions (O1 FP64, O2 FP32
+with one rounding per multiply-accumulate, O2m FP32 with the product and the
+sum rounded separately; C), on the tache-sum oracle (O3) and on deliberately
+broken variants of a shift-register formulation (Section 4.1), which must
+each fail at least one pin.
 """
 import os
 
@@ -30,6 +32,10 @@ def impl_o2(x, irs, schedule, B, Lmax, n_out):
     return impl_o1(x, irs, schedule, B, Lmax, n_out, prec=O.OR_FP32_FMA)
 
 
+def impl_o2m(x, irs, schedule, B, Lmax, n_out):
+    return impl_o1(x, irs, schedule, B, Lmax, n_out, prec=O.OR_FP32_MULADD)
+
+
 def _active_of_sample(schedule, B, n, ignore_offsets=False):
     """IR index of each input sample 0 .. n-1 (None before the first IR): a
     schedule entry (block, ir[, offset]) applies from sample block*B + offset
@@ -51,10 +57,12 @@ def impl_o3(x, irs, schedule, B, Lmax, n_out):
     def h_of(n):
         k = act[n]
         return zero if k is None else irs[k]
-    return O.vector_form(xx, h_of)[:n_out]
+    return O.tache_sum(xx, h_of)[:n_out]
 
 
-# Broken variants of the vector form: each is a plausible coding mistake.
+# Broken variants of a shift-register formulation (a residue that receives
+# e(n) * h, emits its first element and shifts left, Section 4.1): each is a
+# plausible coding mistake.
 def _vector_mutant(kind):
     def impl(x, irs, schedule, B, Lmax, n_out):
         xx = np.zeros(n_out, dtype=np.float32)
@@ -291,7 +299,8 @@ PINS = [pin_golden_fig5, pin_golden_swap, pin_brute_force, pin_impulse, pin_over
 
 
 @pytest.mark.parametrize("pin", PINS, ids=lambda p: p.__name__)
-@pytest.mark.parametrize("impl", [impl_o1, impl_o2, impl_o3], ids=["O1_fp64", "O2_fp32", "O3_vector"])
+@pytest.mark.parametrize("impl", [impl_o1, impl_o2, impl_o2m, impl_o3],
+                         ids=["O1_fp64", "O2_fp32_fma", "O2m_fp32_muladd", "O3_tache_sum"])
 def test_pin_holds(impl, pin):
     assert pin(impl)
 
@@ -323,9 +332,10 @@ def test_o1_matches_numpy_convolve():
     assert np.all(np.abs(y - ref) <= 2 * 257 * 2.0**-53 * mag + 1e-300)
 
 
-def test_vector_form_bitwise_equals_buffer_form():
-    """Both pseudo-code forms add each output's taches in input order, so in
-    FP64 they agree bit for bit (Sections 4.1 and 4.2)."""
+def test_tache_sum_bitwise_equals_buffer_form():
+    """The residue of the buffer form (Section 4.2) and the whole-array sum
+    of taches (Section 3.2) add each output's products in input order, so in
+    FP64 they agree bit for bit."""
     x = W.signal_gauss(500, 8)
     ha, hb = W.impulse_response(40, 9), W.impulse_response(25, 10)
     sched = [(0, 0), (7, 1), (20, 0)]
@@ -432,6 +442,48 @@ def test_fp32_oracle_within_rounding_bound():
     gam = 2048 * u / (1 - 2048 * u)
     assert np.all(np.abs(y32 - y64) <= gam * mag * (1 + 1e-9) + 1e-30)
     assert np.any(y32 != y64)  # it really is a different precision
+
+
+def test_fp32_separate_roundings_within_bound():
+    """O2m rounds every product to FP32 and then every sum (two roundings per
+    multiply-accumulate, the form of Section 5.3's requantization count with
+    the product requantized before the accumulation).  An output that sums k
+    products is within gamma_k * sum|x h| of the exact sum (the product of
+    the first term and the k - 1 additions that follow it are k roundings;
+    gamma_k = k u / (1 - k u), u = 2^-24).  It differs from the fused form."""
+    x = W.signal_gauss(4000, 73)
+    h = W.impulse_response(2048, 74)
+    n_out = 4000 + 2047
+    y64 = impl_o1(x, [h], [(0, 0)], 128, 2048, n_out)
+    y32m = impl_o2m(x, [h], [(0, 0)], 128, 2048, n_out)
+    y32f = impl_o2(x, [h], [(0, 0)], 128, 2048, n_out)
+    mag = O.abs_bound_weights(x, [h], [(0, 0)], 128, 2048)[:n_out]
+    u = 2.0**-24
+    gam = 2048 * u / (1 - 2048 * u)
+    assert np.all(np.abs(y32m - y64) <= gam * mag * (1 + 1e-9) + 1e-30)
+    assert np.any(y32m != y64)
+    assert np.any(y32m != y32f)
+
+
+def test_precision_modes_on_a_hand_derived_rounding_case():
+    """Two samples, two taps: output 1 = x0*h1 + x1*h0 with x0*h1 =
+    -(1 + 2^-11) (exact) and x1*h0 = (1 + 2^-12)^2 = 1 + 2^-11 + 2^-24.  The
+    exact sum is 2^-24.  FP64 holds every step exactly; one fused rounding
+    of -(1 + 2^-11) + (1 + 2^-11 + 2^-24) is exact too; but the product
+    rounded to FP32 first is a tie between 1 + 2^-11 and 1 + 2^-11 + 2^-23,
+    which rounds to the even 1 + 2^-11, and the sum is then 0.  Output 0 =
+    x0*h0 = -(1 + 2^-11)(1 + 2^-12) = -(1 + 2^-12 + 2^-11 + 2^-23) fits in 24
+    bits: exact in every mode."""
+    a = 1.0 + 2.0**-12
+    x = np.array([-(1.0 + 2.0**-11), a], np.float32)
+    h = np.array([a, 1.0], np.float32)
+    y0 = -(1.0 + 2.0**-12 + 2.0**-11 + 2.0**-23)
+    want = {O.OR_FP64: [y0, 2.0**-24, 1.0 + 2.0**-12],
+            O.OR_FP32_FMA: [y0, 2.0**-24, 1.0 + 2.0**-12],
+            O.OR_FP32_MULADD: [y0, 0.0, 1.0 + 2.0**-12]}
+    for prec, w in want.items():
+        y = impl_o1(x, [h], [(0, 0)], 1, 2, 3, prec=prec)
+        assert y.tolist() == w, (prec, y.tolist())
 
 
 def test_sampled_outputs_match_full_oracle():
