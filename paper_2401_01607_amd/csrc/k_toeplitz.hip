@@ -26,6 +26,8 @@
 //    one aligned 16-byte read from the copy that matches its alignment.  The
 //    window is loaded into registers one chunk ahead, stored once, and the
 //    shifted copies are built from it inside LDS.
+#include <algorithm>
+
 #include "taches_internal.h"
 
 namespace taches {
@@ -68,12 +70,12 @@ __device__ __forceinline__ void chunk_span(const GatherCall& d, int ck, int& m_l
   len = b * d.B + ((i + 1) * d.B) / d.cpb - m_lo;
 }
 
-// One thread per (chunk, k-group of 8 samples, padded channel): split 8
-// samples into hi/lo BF16 and store them as one 16-byte fragment each.
-__global__ __launch_bounds__(256) void k_split_input(GatherCall d, int n_chunks) {
+// Fragment t of a call's input, t = (chunk * 32 + k-group of 8 samples) *
+// cpad + padded channel: split the 8 samples into hi/lo BF16 and store them
+// as one 16-byte fragment each.
+__device__ __forceinline__ void split_fragment(const GatherCall& d, int64_t t) {
   const int cpad = d.cpad;
-  const int64_t total = (int64_t)n_chunks * 32 * cpad;
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+  {
     const int c = (int)(t % cpad);
     const int kg = (int)((t / cpad) % 32);
     const int ck = (int)(t / ((int64_t)cpad * 32));
@@ -95,6 +97,36 @@ __global__ __launch_bounds__(256) void k_split_input(GatherCall d, int n_chunks)
     pl.z = lv[4] | ((uint32_t)lv[5] << 16); pl.w = lv[6] | ((uint32_t)lv[7] << 16);
     *reinterpret_cast<uint4*>(d.xs_hi + t * 8) = ph;
     *reinterpret_cast<uint4*>(d.xs_lo + t * 8) = pl;
+  }
+}
+
+// One thread per fragment of one call.
+__global__ __launch_bounds__(256) void k_split_input(GatherCall d, int n_chunks) {
+  const int64_t total = (int64_t)n_chunks * 32 * d.cpad;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x)
+    split_fragment(d, t);
+}
+
+// Index k with start[k] <= v < start[k + 1] (start ascending, start[0] = 0).
+template <typename T>
+__device__ __forceinline__ int find_call(const T* start, int n, int64_t v) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if ((int64_t)gr(start)[mid] <= v) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Every input fragment of the calls of one pool-step class.
+__global__ __launch_bounds__(256) void k_split_input_batched(const GatherCall* calls, const int64_t* frag_start,
+                                                              int n_calls) {
+  const int64_t total = gr(frag_start)[n_calls];
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int k = find_call(frag_start, n_calls, t);
+    const GatherCall d = calls[k];
+    split_fragment(d, t - gr(frag_start)[k]);
   }
 }
 
@@ -125,7 +157,7 @@ __device__ __forceinline__ void rev_load(const BlockIR& ir, int top, int tid, Re
 // (LDS) and NN pairs of B fragments (global, hi and lo) and issues 3*NM*NN
 // MFMAs, so taller wave tiles (NM = 2) halve the global B traffic per MFMA.
 template <typename TailT, int NM, int NN>
-__global__ __launch_bounds__(NT) void k_toeplitz(GatherCall d, int n_tiles) {
+__device__ __forceinline__ void toeplitz_tile(const GatherCall& d, const int tile) {
   __shared__ __attribute__((aligned(16))) uint16_t cp_hi[8 * CP_LEN];
   __shared__ __attribute__((aligned(16))) uint16_t cp_lo[8 * CP_LEN];
   __shared__ __attribute__((aligned(16))) uint16_t rev_hi[REV_LEN];
@@ -135,7 +167,6 @@ __global__ __launch_bounds__(NT) void k_toeplitz(GatherCall d, int n_tiles) {
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int i = l & 31;   // row within the wave's 32-row MFMA tile (A) / column (B, D)
   const int kg = l >> 5;  // k-group of 8 within a 16-deep K-step
-  const int tile = xcd_remap(blockIdx.x, n_tiles);
   const int n0 = tile * MT;
   const int cpad = d.cpad;
   TailT* ring = reinterpret_cast<TailT*>(d.ring);
@@ -359,7 +390,49 @@ __global__ __launch_bounds__(NT) void k_toeplitz(GatherCall d, int n_tiles) {
       }
 }
 
+template <typename TailT, int NM, int NN>
+__global__ __launch_bounds__(NT) void k_toeplitz(GatherCall d, int n_tiles) {
+  toeplitz_tile<TailT, NM, NN>(d, xcd_remap(blockIdx.x, n_tiles));
+}
+
+// The calls of one pool-step class: workgroup i takes tile i - tile_start[k]
+// of call k (tile_start: prefix sums of the calls' tile counts).
+template <typename TailT, int NM, int NN>
+__global__ __launch_bounds__(NT) void k_toeplitz_batched(const GatherCall* calls, const int32_t* tile_start,
+                                                         int n_calls) {
+  const int id = xcd_remap(blockIdx.x, gridDim.x);
+  const int k = find_call(tile_start, n_calls, id);
+  const GatherCall d = calls[k];
+  toeplitz_tile<TailT, NM, NN>(d, id - gr(tile_start)[k]);
+}
+
+template <typename TailT, int NM, int NN>
+hipError_t launch_batched_class(const unsigned char* tab, const ToeplitzBatch& b, hipStream_t st) {
+  const GatherCall* calls = reinterpret_cast<const GatherCall*>(tab + b.off_calls);
+  if (b.n_frags > 0) {
+    const int blocks = (int)std::min<int64_t>((b.n_frags + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_split_input_batched, dim3(blocks), dim3(256), 0, st, calls,
+                       reinterpret_cast<const int64_t*>(tab + b.off_frags), b.n_calls);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (b.n_tiles > 0)
+    hipLaunchKernelGGL((k_toeplitz_batched<TailT, NM, NN>), dim3((unsigned)b.n_tiles), dim3(NT), 0, st, calls,
+                       reinterpret_cast<const int32_t*>(tab + b.off_tiles), b.n_calls);
+  return hipGetLastError();
+}
+
 }  // namespace
+
+int toeplitz_rows_per_tile() { return MT; }
+
+hipError_t launch_toeplitz_batched(const unsigned char* table_dev, const ToeplitzBatch& b, bool tail_fp64, bool wide,
+                                   hipStream_t st) {
+  if (b.n_calls <= 0) return hipSuccess;
+  if (tail_fp64)
+    return wide ? launch_batched_class<double, 2, 1>(table_dev, b, st) : launch_batched_class<double, 1, 1>(table_dev, b, st);
+  return wide ? launch_batched_class<float, 2, 1>(table_dev, b, st) : launch_batched_class<float, 1, 1>(table_dev, b, st);
+}
 
 hipError_t launch_split_bf16(const float* h, uint16_t* hi, uint16_t* lo, int L, hipStream_t st) {
   if (L <= 0) return hipSuccess;

@@ -116,6 +116,23 @@ hipError_t launch_toeplitz(const GatherCall& call, bool tail_fp64, hipStream_t s
 bool split_supported(const taches_config& cfg);
 int split_cpad(int channels);
 
+// Split-BF16 streams of one pool step that share a kernel class (tail type,
+// padded channel count): their calls and prefix sums in the pool table.
+struct ToeplitzBatch {
+  int64_t off_calls;   // GatherCall[n_calls]
+  int64_t off_tiles;   // int32 tile_start[n_calls + 1]: first output tile of each call
+  int64_t off_frags;   // int64 frag_start[n_calls + 1]: first input fragment of each call
+  int64_t n_tiles;     // tile_start[n_calls]
+  int64_t n_frags;     // frag_start[n_calls]
+  int32_t n_calls;
+  int32_t pad_;
+};
+// Output rows of one Toeplitz workgroup tile.
+int toeplitz_rows_per_tile();
+// The split-input launch (if any input) and the Toeplitz launch of one class.
+hipError_t launch_toeplitz_batched(const unsigned char* table_dev, const ToeplitzBatch& b, bool tail_fp64, bool wide,
+                                   hipStream_t st);
+
 // FP32 FMA issue ceiling of the device (k_diag.hip): TFLOP/s reached by
 // independent v_fmac_f32 chains.
 hipError_t measure_fmac_ceiling(int device, double* tflops);

@@ -19,17 +19,25 @@ using taches::GatherCall;
 
 namespace {
 
-thread_local std::string g_err;
+// Message of the last failure on this thread: a fixed buffer, so that
+// reporting an error allocates nothing.
+constexpr size_t kErrLen = 512;
+thread_local char g_err[kErrLen] = "";
 
 int fail(int code, const char* fmt, ...) {
-  char buf[512];
   va_list ap;
   va_start(ap, fmt);
-  vsnprintf(buf, sizeof buf, fmt, ap);
+  vsnprintf(g_err, kErrLen, fmt, ap);
   va_end(ap);
-  g_err = buf;
   return code;
 }
+
+// Keeps the current error message across cleanup calls that may fail.
+struct ErrKeep {
+  char msg[kErrLen];
+  ErrKeep() { std::memcpy(msg, g_err, kErrLen); }
+  ~ErrKeep() { std::memcpy(g_err, msg, kErrLen); }
+};
 
 #define HIPCHK(expr)                                                                        \
   do {                                                                                      \
@@ -257,13 +265,15 @@ struct TilePlan {
 
 // CU loads of one tile shape and launch order (the same for every W): the
 // FMA work of the tiles each CU receives, and their number.
-void plan_loads(int64_t S, int64_t n_out, int64_t lmax, int channels, int r, int order, std::vector<double>& cu,
-                std::vector<int>& cnt) {
+constexpr int kCUs = 256;
+typedef std::array<double, kCUs> CuLoad;
+typedef std::array<int, kCUs> CuCount;
+
+void plan_loads(int64_t S, int64_t n_out, int64_t lmax, int channels, int r, int order, CuLoad& cu, CuCount& cnt) {
   const int64_t T = 64 * r;
   const int64_t nt = (n_out + T - 1) / T;
-  const int ncu = 256;
-  cu.assign(ncu, 0.0);
-  cnt.assign(ncu, 0);
+  cu.fill(0.0);
+  cnt.fill(0);
   const int64_t total = nt * channels;
   const int64_t mid = (nt - 1) / 2;
   const int64_t q = nt >> 3, rem = nt & 7;
@@ -293,7 +303,7 @@ void plan_loads(int64_t S, int64_t n_out, int64_t lmax, int channels, int r, int
 // fewer LDS reads per FMA (eff_r); waves that share a tile work on adjacent
 // chunks whose IR windows overlap, one-wave tiles each stream their own
 // window (eff_w).
-double plan_cost(const std::vector<double>& cu, const std::vector<int>& cnt, int r, int w) {
+double plan_cost(const CuLoad& cu, const CuCount& cnt, int r, int w) {
   static const double eff_r[17] = {0, 0, 0, 0, 0.85, 0, 0, 0, 0.92, 0, 0, 0, 0.95, 0, 0.885, 0, 0.97};
   const double eff_w = w == 4 ? 1.0 : w == 2 ? 0.92 : 0.845;
   double worst = 0.0;
@@ -312,16 +322,11 @@ double plan_cost(const std::vector<double>& cu, const std::vector<int>& cnt, int
 std::mutex g_plan_mu;
 std::map<std::array<int64_t, 6>, TilePlan> g_plans;
 
-TilePlan pick_tile(const taches_stream* s, int64_t S, int64_t n_out, int64_t lmax, int chunks_per_tile) {
+// The estimate for one call shape (no caching, no allocation).  force =
+// R * 8 + W for a forced shape (which still gets the launch order the
+// estimate prefers for it), 0 for the automatic choice.
+TilePlan plan_tile(int force, int channels, int64_t S, int64_t n_out, int64_t lmax, int chunks_per_tile) {
   TilePlan best;
-  // a forced shape still gets the launch order the estimate prefers for it
-  const int force = s->force_r ? s->force_r * 8 + (s->force_w ? s->force_w : 1) : 0;
-  const std::array<int64_t, 6> key = {S, n_out, lmax, s->cfg.channels, chunks_per_tile, force};
-  {
-    std::lock_guard<std::mutex> lk(g_plan_mu);
-    auto it = g_plans.find(key);
-    if (it != g_plans.end()) return it->second;
-  }
   static const int rs_auto[5] = {16, 14, 12, 8, 4};
   static const int ws_auto[3] = {1, 2, 4};
   const int rs_forced[1] = {force >> 3}, ws_forced[1] = {force & 7};
@@ -329,11 +334,11 @@ TilePlan pick_tile(const taches_stream* s, int64_t S, int64_t n_out, int64_t lma
   const int* ws = force ? ws_forced : ws_auto;
   const int nr = force ? 1 : 5, nw = force ? 1 : 3;
   double best_cost = 1e300;
-  std::vector<double> cu[3];
-  std::vector<int> cnt[3];
+  CuLoad cu[3];
+  CuCount cnt[3];
   for (int ir = 0; ir < nr; ++ir) {
     const int r = rs[ir];
-    for (int order = 0; order < 3; ++order) plan_loads(S, n_out, lmax, s->cfg.channels, r, order, cu[order], cnt[order]);
+    for (int order = 0; order < 3; ++order) plan_loads(S, n_out, lmax, channels, r, order, cu[order], cnt[order]);
     for (int iw = 0; iw < nw; ++iw) {
       const int w = ws[iw];
       if (!force && w > 1 && chunks_per_tile < 2 * w) continue;
@@ -348,6 +353,18 @@ TilePlan pick_tile(const taches_stream* s, int64_t S, int64_t n_out, int64_t lma
       }
     }
   }
+  return best;
+}
+
+TilePlan pick_tile(const taches_stream* s, int64_t S, int64_t n_out, int64_t lmax, int chunks_per_tile) {
+  const int force = s->force_r ? s->force_r * 8 + (s->force_w ? s->force_w : 1) : 0;
+  const std::array<int64_t, 6> key = {S, n_out, lmax, s->cfg.channels, chunks_per_tile, force};
+  {
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    auto it = g_plans.find(key);
+    if (it != g_plans.end()) return it->second;
+  }
+  const TilePlan best = plan_tile(force, s->cfg.channels, S, n_out, lmax, chunks_per_tile);
   std::lock_guard<std::mutex> lk(g_plan_mu);
   if (g_plans.size() >= 4096) g_plans.clear();
   g_plans[key] = best;
@@ -659,7 +676,7 @@ void taches_config_default(taches_config* cfg, int32_t block_size, int32_t max_i
   cfg->device = 0;
 }
 
-const char* taches_last_error(void) { return g_err.c_str(); }
+const char* taches_last_error(void) { return g_err; }
 
 taches_stream* taches_open_ex(const taches_config* cfg) {
   if (validate(cfg) != TACHES_OK) return nullptr;
@@ -670,9 +687,8 @@ taches_stream* taches_open_ex(const taches_config* cfg) {
   }
   s->cfg = *cfg;
   if (stream_init(s) != TACHES_OK) {
-    std::string keep = g_err;
+    ErrKeep keep;
     free_stream(s);
-    g_err = keep;
     return nullptr;
   }
   return s;
@@ -844,9 +860,10 @@ int taches_convolve(const float* x_dev, int64_t nx, int32_t channels, const floa
   (void)hipStreamSynchronize(s->stream);
   (void)hipFree(xp);
   (void)hipFree(yp);
-  std::string keep = g_err;
-  (void)taches_close(s);
-  g_err = keep;
+  {
+    ErrKeep keep;
+    (void)taches_close(s);
+  }
   return rc;
 }
 
@@ -1303,30 +1320,48 @@ int taches_pool_step_strided(taches_pool* p, int32_t n, taches_stream* const* st
                        y_cstride ? y_cstride[i] : 0, n_blocks[i], nullptr, nullptr, &plans[i]);
     if (rc != TACHES_OK) return rc;
   }
-  // split-precision streams run their own MFMA kernel on the pool's stream
+  // Every fallible host step (planning, table packing, table buffers, graph
+  // capture) comes before the first launch.  Once work is enqueued, every
+  // stream whose kernels are on the device is committed, also when a later
+  // launch fails, so the host state (head, live tail) always matches the
+  // device's.  FP32 streams share one persistent gather launch; split-BF16
+  // streams share one split-input launch and one Toeplitz MFMA launch per
+  // class (tail type, padded channel count), after the gather launch.
   std::vector<int> gather_ids;
   std::vector<const GatherCall*> gcalls;
+  std::vector<int> split_ids[4];   // class = 2 * tail_fp64 + (cpad > 32)
   for (int i = 0; i < n; ++i) {
-    if (streams[i]->cfg.precision == TACHES_PREC_SPLIT_BF16) {
-      int rc = launch_call(streams[i], plans[i]);
-      if (rc != TACHES_OK) return rc;
+    taches_stream* s = streams[i];
+    if (s->cfg.precision == TACHES_PREC_SPLIT_BF16) {
+      split_ids[2 * (s->tail_fp64 ? 1 : 0) + (s->cpad > 32 ? 1 : 0)].push_back(i);
     } else {
       gather_ids.push_back(i);
       gcalls.push_back(&plans[i].g);
     }
   }
-  if (!gather_ids.empty()) {
-    bool mixed = false;   // some stream keeps an FP64 tail
+  std::vector<char> enqueued(n, 0);
+  auto finish = [&](int rc) {
+    for (int i = 0; i < n; ++i)
+      if (enqueued[i]) commit_call(streams[i], plans[i]);
+    return rc;
+  };
+  const bool has_gather = !gather_ids.empty();
+  // ---- gather planning: work items over the resident workgroups ----
+  struct Item {
+    WorkItem w;
+    int64_t work;
+  };
+  std::vector<Item> items;
+  std::vector<int> owner, count;
+  int nwg = 0, r = 0;
+  bool mixed = false;   // some gather stream keeps an FP64 tail
+  const int ng = (int)gather_ids.size();
+  if (has_gather) {
     for (int i : gather_ids) mixed |= streams[i]->tail_fp64;
-    const int r = pool_pick_r(p, gcalls, mixed);
+    r = pool_pick_r(p, gcalls, mixed);
     const int64_t T = 64 * r;
     // work items: runs of consecutive output tiles of one channel of one
     // call, with their FMA count (plus the tail read/write)
-    struct Item {
-      WorkItem w;
-      int64_t work;
-    };
-    const int ng = (int)gather_ids.size();
     auto tile_work = [T](const GatherCall& g, int64_t t) {
       const int64_t n0 = t * T;
       int64_t work = 4 * T;
@@ -1373,7 +1408,6 @@ int taches_pool_step_strided(taches_pool* p, int32_t n, taches_stream* const* st
     // 1/8 of a workgroup's share, so the table, its planning and the
     // kernel's per-item work shrink; otherwise one item per tile.
     const int64_t span_work = n_tiles > 32 * wg_max ? std::max(tile_max, tiles_work / (8 * wg_max)) : 0;
-    std::vector<Item> items;
     items.reserve(span_work ? (size_t)(tiles_work / span_work + ng * 2 + 16) : (size_t)n_tiles);
     for (int k = 0; k < ng; ++k) {
       const GatherCall& g = plans[gather_ids[k]].g;
@@ -1414,10 +1448,10 @@ int taches_pool_step_strided(taches_pool* p, int32_t n, taches_stream* const* st
       max_work = std::max(max_work, it.work);
     }
     const int64_t by_work = std::max<int64_t>(1, total_work / max_work);
-    const int nwg = (int)std::max<int64_t>(std::min<int64_t>(256, (int64_t)items.size()),
+    nwg = (int)std::max<int64_t>(std::min<int64_t>(256, (int64_t)items.size()),
                                            std::min<int64_t>(256LL * per_cu, by_work));
-    std::vector<int> owner(items.size());
-    std::vector<int> count(nwg, 0);
+    owner.assign(items.size(), 0);
+    count.assign(nwg, 0);
     std::vector<int64_t> load(nwg, 0);
     const size_t n_items = items.size();
     if ((span_work > 0 && n_items >= 8 * (size_t)nwg) ||
@@ -1482,20 +1516,48 @@ int taches_pool_step_strided(taches_pool* p, int32_t n, taches_stream* const* st
       sum += load[b];
     }
     p->last_imbalance = sum > 0 ? (double)mx * nwg / (double)sum : 1.0;
-    // pack the table: header, calls, fp64 flags, wg_begin, items grouped by workgroup
-    const size_t off_calls = align256(sizeof(taches::BatchHeader));
-    const size_t off_fp64 = align256(off_calls + sizeof(GatherCall) * ng);
-    const size_t off_wgb = align256(off_fp64 + sizeof(int32_t) * ng);
-    const size_t off_items = align256(off_wgb + sizeof(int32_t) * (nwg + 1));
-    const size_t bytes = align256(off_items + sizeof(WorkItem) * items.size());
-    int rc = pool_reserve(p, bytes);
-    if (rc != TACHES_OK) return rc;
-    const int cur = p->tab_cur;
-    unsigned char* pin = p->tab_pin[cur];
-    if (p->tab_pending[cur]) {   // the step before the previous one read this buffer
-      HIPCHK(hipEventSynchronize(p->tab_free[cur]));
-      p->tab_pending[cur] = false;
+  }
+  // ---- split classes: calls, tile and fragment prefix sums ----
+  const int mt = taches::toeplitz_rows_per_tile();
+  taches::ToeplitzBatch sb[4];
+  int64_t split_tiles = 0;
+  for (int k = 0; k < 4; ++k) {
+    sb[k] = taches::ToeplitzBatch{};
+    sb[k].n_calls = (int32_t)split_ids[k].size();
+    for (int i : split_ids[k]) {
+      const GatherCall& g = plans[i].g;
+      sb[k].n_tiles += (g.n_out + mt - 1) / mt;
+      if (g.x) sb[k].n_frags += (int64_t)g.n_blocks * g.cpb * 32 * g.cpad;
     }
+    split_tiles += sb[k].n_tiles;
+  }
+  if (split_tiles > INT32_MAX) return fail(TACHES_EINVAL, "step too large: %lld Toeplitz tiles", (long long)split_tiles);
+  // ---- table layout: [gather: header, calls, fp64 flags, wg_begin, items]
+  // [per split class: calls, tile starts (int32), fragment starts (int64)] ----
+  size_t off_calls = 0, off_fp64 = 0, off_wgb = 0, off_items = 0, bytes = 0;
+  if (has_gather) {
+    off_calls = align256(sizeof(taches::BatchHeader));
+    off_fp64 = align256(off_calls + sizeof(GatherCall) * ng);
+    off_wgb = align256(off_fp64 + sizeof(int32_t) * ng);
+    off_items = align256(off_wgb + sizeof(int32_t) * (nwg + 1));
+    bytes = align256(off_items + sizeof(WorkItem) * items.size());
+  }
+  for (int k = 0; k < 4; ++k) {
+    if (!sb[k].n_calls) continue;
+    sb[k].off_calls = (int64_t)bytes;
+    sb[k].off_tiles = (int64_t)align256(bytes + sizeof(GatherCall) * sb[k].n_calls);
+    sb[k].off_frags = (int64_t)align256(sb[k].off_tiles + sizeof(int32_t) * (sb[k].n_calls + 1));
+    bytes = align256(sb[k].off_frags + sizeof(int64_t) * (sb[k].n_calls + 1));
+  }
+  int rc = pool_reserve(p, bytes);
+  if (rc != TACHES_OK) return rc;
+  const int cur = p->tab_cur;
+  unsigned char* pin = p->tab_pin[cur];
+  if (p->tab_pending[cur]) {   // the step before the previous one read this buffer
+    HIPCHK(hipEventSynchronize(p->tab_free[cur]));
+    p->tab_pending[cur] = false;
+  }
+  if (has_gather) {
     taches::BatchHeader* hd = (taches::BatchHeader*)pin;
     hd->off_calls = (int32_t)off_calls;
     hd->off_fp64 = (int32_t)off_fp64;
@@ -1514,73 +1576,100 @@ int taches_pool_step_strided(taches_pool* p, int32_t n, taches_stream* const* st
     for (int b = 0; b < nwg; ++b) wgb[b + 1] = wgb[b] + count[b];
     std::vector<int32_t> fill(wgb, wgb + nwg);
     for (size_t i = 0; i < items.size(); ++i) wit[fill[owner[i]]++] = items[i].w;
-    const auto t1 = std::chrono::steady_clock::now();
-    p->last_plan_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
-    bool launched = false;
-    const int ev = p->ev_next;
-    if (p->ev_pending[ev]) {
-      HIPCHK(hipEventSynchronize(p->ev_end[ev]));
-      int rc2 = pool_account(p, false);
-      if (rc2 != TACHES_OK) return rc2;
-    }
-    HIPCHK(hipEventRecord(p->ev_beg[ev], p->stream));
-    if (p->use_graph) {
-      // capture [table copy -> batched kernel] once per (tile, workgroups,
-      // table capacity); later steps only resize the copy and replay
-      if (!p->exec || p->graph_r != r || p->graph_nwg != nwg || p->graph_cap != p->tab_cap ||
-          p->graph_mixed != mixed) {
-        pool_drop_graph(p);
-        HIPCHK(hipStreamBeginCapture(p->capture, hipStreamCaptureModeThreadLocal));
-        hipError_t e1 = hipMemcpyAsync(p->tab_dev, pin, p->tab_cap, hipMemcpyHostToDevice, p->capture);
-        hipError_t e2 = taches::launch_gather_batched(p->tab_dev, nwg, r, mixed, p->capture);
-        hipError_t e3 = hipStreamEndCapture(p->capture, &p->graph);
-        if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess)
-          return fail(TACHES_EDEVICE, "graph capture failed: %s", hipGetErrorString(e1 != hipSuccess ? e1 : e2 != hipSuccess ? e2 : e3));
-        HIPCHK(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
-        size_t nn = 0;
-        HIPCHK(hipGraphGetNodes(p->graph, nullptr, &nn));
-        std::vector<hipGraphNode_t> nodes(nn);
-        HIPCHK(hipGraphGetNodes(p->graph, nodes.data(), &nn));
-        for (auto nd : nodes) {
-          hipGraphNodeType ty;
-          HIPCHK(hipGraphNodeGetType(nd, &ty));
-          if (ty == hipGraphNodeTypeMemcpy) p->copy_node = nd;
-        }
-        p->graph_r = r;
-        p->graph_mixed = mixed;
-        p->graph_nwg = nwg;
-        p->graph_cap = p->tab_cap;
-      }
-      if (p->copy_node &&
-          hipGraphExecMemcpyNodeSetParams1D(p->exec, p->copy_node, p->tab_dev, pin, bytes, hipMemcpyHostToDevice) ==
-              hipSuccess) {
-        HIPCHK(hipGraphLaunch(p->exec, p->stream));
-        p->replays += 1;
-        launched = true;
-      }
-    }
-    if (!launched) {
-      HIPCHK(hipMemcpyAsync(p->tab_dev, pin, bytes, hipMemcpyHostToDevice, p->stream));
-      hipError_t e = taches::launch_gather_batched(p->tab_dev, nwg, r, mixed, p->stream);
-      if (e != hipSuccess) return fail(TACHES_EDEVICE, "batched launch: %s", hipGetErrorString(e));
-    }
-    HIPCHK(hipEventRecord(p->ev_end[ev], p->stream));
-    p->ev_pending[ev] = true;
-    p->ev_last = ev;
-    p->ev_next = (ev + 1) % taches_pool::kRing;
-    HIPCHK(hipEventRecord(p->tab_free[cur], p->stream));
-    p->tab_pending[cur] = true;
-    p->tab_cur = cur ^ 1;
-    p->last_items = (int)items.size();
-    p->last_wg = nwg;
-    p->last_r = r;
-    for (int k = 0; k < ng; ++k) {
-      streams[gather_ids[k]]->last_r = r;
-      streams[gather_ids[k]]->last_w = 1;
+  }
+  for (int k = 0; k < 4; ++k) {
+    if (!sb[k].n_calls) continue;
+    GatherCall* calls = (GatherCall*)(pin + sb[k].off_calls);
+    int32_t* ts = (int32_t*)(pin + sb[k].off_tiles);
+    int64_t* fs = (int64_t*)(pin + sb[k].off_frags);
+    ts[0] = 0;
+    fs[0] = 0;
+    for (int j = 0; j < sb[k].n_calls; ++j) {
+      const GatherCall& g = plans[split_ids[k][j]].g;
+      calls[j] = g;
+      ts[j + 1] = ts[j] + (g.n_out + mt - 1) / mt;
+      fs[j + 1] = fs[j] + (g.x ? (int64_t)g.n_blocks * g.cpb * 32 * g.cpad : 0);
     }
   }
-  for (int i = 0; i < n; ++i) commit_call(streams[i], plans[i]);
-  return TACHES_OK;
+  const auto t1 = std::chrono::steady_clock::now();
+  p->last_plan_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  const int ev = p->ev_next;
+  if (p->ev_pending[ev]) {
+    HIPCHK(hipEventSynchronize(p->ev_end[ev]));
+    int rc2 = pool_account(p, false);
+    if (rc2 != TACHES_OK) return rc2;
+  }
+  if (has_gather && p->use_graph) {
+    // capture [table copy -> batched kernel] once per (tile, workgroups,
+    // table capacity); later steps only resize the copy and replay
+    if (!p->exec || p->graph_r != r || p->graph_nwg != nwg || p->graph_cap != p->tab_cap ||
+        p->graph_mixed != mixed) {
+      pool_drop_graph(p);
+      HIPCHK(hipStreamBeginCapture(p->capture, hipStreamCaptureModeThreadLocal));
+      hipError_t e1 = hipMemcpyAsync(p->tab_dev, pin, p->tab_cap, hipMemcpyHostToDevice, p->capture);
+      hipError_t e2 = taches::launch_gather_batched(p->tab_dev, nwg, r, mixed, p->capture);
+      hipError_t e3 = hipStreamEndCapture(p->capture, &p->graph);
+      if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess)
+        return fail(TACHES_EDEVICE, "graph capture failed: %s", hipGetErrorString(e1 != hipSuccess ? e1 : e2 != hipSuccess ? e2 : e3));
+      HIPCHK(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
+      size_t nn = 0;
+      HIPCHK(hipGraphGetNodes(p->graph, nullptr, &nn));
+      std::vector<hipGraphNode_t> nodes(nn);
+      HIPCHK(hipGraphGetNodes(p->graph, nodes.data(), &nn));
+      for (auto nd : nodes) {
+        hipGraphNodeType ty;
+        HIPCHK(hipGraphNodeGetType(nd, &ty));
+        if (ty == hipGraphNodeTypeMemcpy) p->copy_node = nd;
+      }
+      p->graph_r = r;
+      p->graph_mixed = mixed;
+      p->graph_nwg = nwg;
+      p->graph_cap = p->tab_cap;
+    }
+  }
+  const bool replay = has_gather && p->use_graph && p->copy_node &&
+                      hipGraphExecMemcpyNodeSetParams1D(p->exec, p->copy_node, p->tab_dev, pin, bytes,
+                                                        hipMemcpyHostToDevice) == hipSuccess;
+  // ---- enqueue: from here on, failures commit what was enqueued ----
+  hipError_t e = hipEventRecord(p->ev_beg[ev], p->stream);
+  if (e == hipSuccess) {
+    if (replay) {
+      e = hipGraphLaunch(p->exec, p->stream);
+      if (e == hipSuccess) p->replays += 1;
+    } else {
+      e = hipMemcpyAsync(p->tab_dev, pin, bytes, hipMemcpyHostToDevice, p->stream);
+      if (e == hipSuccess && has_gather) e = taches::launch_gather_batched(p->tab_dev, nwg, r, mixed, p->stream);
+    }
+  }
+  if (e != hipSuccess) return finish(fail(TACHES_EDEVICE, "batched launch: %s", hipGetErrorString(e)));
+  for (int i : gather_ids) enqueued[i] = 1;
+  for (int k = 0; k < 4; ++k) {
+    if (!sb[k].n_calls) continue;
+    e = taches::launch_toeplitz_batched(p->tab_dev, sb[k], (k & 2) != 0, (k & 1) != 0, p->stream);
+    if (e != hipSuccess) return finish(fail(TACHES_EDEVICE, "batched Toeplitz launch: %s", hipGetErrorString(e)));
+    for (int i : split_ids[k]) {
+      enqueued[i] = 1;
+      streams[i]->last_r = 0;
+      streams[i]->last_w = 0;
+    }
+  }
+  p->ev_pending[ev] = hipEventRecord(p->ev_end[ev], p->stream) == hipSuccess;
+  p->ev_last = p->ev_pending[ev] ? ev : -1;
+  p->ev_next = (ev + 1) % taches_pool::kRing;
+  p->tab_pending[cur] = hipEventRecord(p->tab_free[cur], p->stream) == hipSuccess;
+  if (!p->tab_pending[cur]) {
+    // without the event the pinned table cannot be reused safely: wait here
+    (void)hipStreamSynchronize(p->stream);
+  }
+  p->tab_cur = cur ^ 1;
+  p->last_items = (int)items.size();
+  p->last_wg = nwg;
+  p->last_r = r;
+  for (int k = 0; k < ng; ++k) {
+    streams[gather_ids[k]]->last_r = r;
+    streams[gather_ids[k]]->last_w = 1;
+  }
+  return finish(TACHES_OK);
 }
 
 }  // extern "C"

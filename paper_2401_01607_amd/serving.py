@@ -81,6 +81,7 @@ class Stats:
     queue_waits_s: list = field(default_factory=list)
     _lat: list = field(default_factory=list)            # per-tick arrays of block latencies (after warm-up)
     _dl: list = field(default_factory=list)             # matching deadlines
+    _bs: list = field(default_factory=list)             # matching block sizes
 
     @property
     def latencies_s(self) -> np.ndarray:
@@ -89,6 +90,10 @@ class Stats:
     @property
     def deadlines_s(self) -> np.ndarray:
         return np.concatenate(self._dl) if self._dl else np.zeros(0)
+
+    @property
+    def block_sizes(self) -> np.ndarray:
+        return np.concatenate(self._bs) if self._bs else np.zeros(0, np.int64)
 
     def summary(self, wall_s: float) -> dict:
         lat = self.latencies_s * 1e3
@@ -106,6 +111,16 @@ class Stats:
                         "latency_ms_max": round(float(lat.max()), 3),
                         "deadline_misses": int(np.sum(lat > dl)),
                         "deadline_miss_fraction": round(float(np.mean(lat > dl)), 5)})
+            bs = self.block_sizes
+            by = {}
+            for b in np.unique(bs):
+                m = bs == b
+                lb = lat[m]
+                by[str(int(b))] = {"blocks": int(m.sum()), "deadline_ms": round(float(dl[m][0]), 3),
+                                   "latency_ms_p50": round(float(np.percentile(lb, 50)), 3),
+                                   "latency_ms_p99": round(float(np.percentile(lb, 99)), 3),
+                                   "deadline_miss_fraction": round(float(np.mean(lb > dl[m])), 5)}
+            out["by_block_size"] = by
         if self.queue_waits_s:
             q = np.array(self.queue_waits_s)
             out.update({"queue_wait_s_p50": round(float(np.percentile(q, 50)), 3),
@@ -297,13 +312,14 @@ class Scheduler:
         # block k is complete at start + (k+1) B / fs
         ready_s = start[rng] + (k + 1) * per
         keep = ready_s >= self.warmup_s
-        return (ready_s[keep], per[keep]) if keep.any() else None
+        return (ready_s[keep], per[keep], B[rng][keep]) if keep.any() else None
 
     def _record_end(self, done_s, rec) -> None:
         """Latency of every recorded block: step completion minus arrival."""
         if rec is not None:
             self.stats._lat.append(done_s - rec[0])
             self.stats._dl.append(rec[1])
+            self.stats._bs.append(rec[2])
 
     # -- drivers -----------------------------------------------------------
     def run_realtime(self, duration_s: float, clock=time.perf_counter, sleep=time.sleep) -> dict:
@@ -522,6 +538,31 @@ class GpuExecutor:
         self.idle_bytes += s.info().device_bytes
         self.h_stream[handle] = 0
         self.free_handles.append(handle)
+
+    def kept_outputs(self, sch, rid):
+        """(input [C][n_in*B], outputs so far [C][blocks done*B], blocks of the
+        applied IR swaps) of a request listed in keep_outputs, retired or still
+        running under scheduler `sch`; None if it was never admitted."""
+        req = None
+        if rid in self.kept:
+            xin, ymix = self.kept[rid]
+            hist = sch.history[rid]
+            C = xin.shape[1]
+            x = xin.transpose(1, 0, 2).reshape(C, -1)
+            y = ymix.transpose(1, 0, 2).reshape(C, -1)
+            return x, y, list(hist.swap_blocks)
+        t = sch.tab
+        for i in range(t.n):
+            a = t.objs[i]
+            if a.req.rid == rid:
+                req = a.req
+                done = int(t.nxt[i])
+                s, y, _, _ = self.live[a.handle]
+                self.wait()
+                x = self.input_signal(req).cpu().numpy()
+                yo = y[:, :done * req.block].cpu().numpy() if y is not None else None
+                return (x, yo, list(a.swap_blocks)) if yo is not None else None
+        return None
 
     def close(self):
         for s, *_ in self.live.values():

@@ -108,3 +108,13 @@ def rel_err(y, y64):
     y = np.asarray(y, np.float64)
     rms = float(np.sqrt(np.mean(np.square(y64))))
     return float(np.max(np.abs(y - y64))) / rms if rms > 0 else float(np.max(np.abs(y - y64)))
+
+
+def rms_y64(x, irs, schedule, B, n_out):
+    """RMS over every output (all channels, n_out samples each) of the FP64
+    result of Eq. (4): the normaliser of the stated tolerances.  Computed
+    with the oracle's FFT helper (FP64; its error is far below the
+    tolerances)."""
+    from oracle import oracle as O
+    y = O.fft_outputs(np.atleast_2d(np.asarray(x, dtype=np.float32)), irs, schedule, B, n_out)
+    return float(np.sqrt(np.mean(np.square(y))))

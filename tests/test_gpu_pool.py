@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from paper_2401_01607_amd import workloads as W
-from tests.gpu_harness import binding, oracle_run, rel_err
+from tests.gpu_harness import binding, oracle_run, rel_err, rms_y64
 
 pytestmark = pytest.mark.gpu
 
@@ -206,6 +206,107 @@ def test_mixed_split_and_fp32_streams_in_one_step():
     sp.close()
 
 
+def test_split_streams_batched_equal_alone_bitwise():
+    """Split-BF16 streams of every kernel class in one pool step (one
+    split-input and one Toeplitz launch per class: FP32 or FP64 tail, 32 or
+    64 padded channels), with FP32 streams beside them, over uneven steps:
+    each equals the same stream run alone bit for bit, and stays within the
+    split-BF16 bound of the FP64 oracle."""
+    import torch
+    from tests.test_gpu_split import check_bound
+    T = binding()
+    SPLIT = T.TACHES_PREC_SPLIT_BF16
+    shapes = [(1, 64, 700, 1), (2, 128, 1500, 2), (40, 256, 900, 1), (3, 32, 400, 2), (33, 512, 1200, 2),
+              (1, 256, 2000, 0)]   # (channels, B, L, tail: 0 auto, 1 FP32, 2 FP64); the last is FP32 precision
+    steps = [3, 1, 4, 2]
+    nbs = sum(steps)
+
+    def make(i, C, B, L, tail):
+        prec = SPLIT if i < len(shapes) - 1 else T.TACHES_PREC_FP32
+        s = T.Stream(B, L, channels=C, max_blocks_per_call=max(steps), precision=prec, tail=tail)
+        s.set_ir(W.impulse_response(L, 610 + i))
+        return s
+    xs = [np.stack([W.signal_gauss(nbs * B, 620 + 10 * i + c) for c in range(C)]) for i, (C, B, L, _) in enumerate(shapes)]
+    # alone
+    alone = []
+    for i, (C, B, L, tail) in enumerate(shapes):
+        s = make(i, C, B, L, tail)
+        outs, k0 = [], 0
+        for n in steps:
+            xd = torch.from_numpy(np.ascontiguousarray(xs[i][:, k0 * B:(k0 + n) * B])).cuda()
+            yd = torch.empty_like(xd)
+            s.process_blocks(xd, yd, n)
+            outs.append(yd)
+            k0 += n
+        s.synchronize()
+        alone.append(torch.cat(outs, 1).cpu().numpy())
+        s.close()
+    # batched
+    ss = [make(i, *sh) for i, sh in enumerate(shapes)]
+    pool = T.Pool(len(ss), 64 * GB, use_graph=True)
+    for s in ss:
+        assert pool.attach(s) == T.TACHES_OK
+    outs = [[] for _ in ss]
+    k0 = 0
+    for n in steps:
+        xd = [torch.from_numpy(np.ascontiguousarray(xs[i][:, k0 * sh[1]:(k0 + n) * sh[1]])).cuda()
+              for i, sh in enumerate(shapes)]
+        yd = [torch.empty_like(x) for x in xd]
+        pool.step(ss, xd, yd, [n] * len(ss))
+        for i in range(len(ss)):
+            outs[i].append(yd[i])
+        k0 += n
+    pool.synchronize()
+    for i in range(len(ss)):
+        y = torch.cat(outs[i], 1).cpu().numpy()
+        assert np.array_equal(y, alone[i]), f"stream {i} {shapes[i]}"
+    for i in (0, 2, 4):
+        C, B, L, _ = shapes[i]
+        check_bound(alone[i], xs[i], [W.impulse_response(L, 610 + i)], [(0, 0)], B, L, nbs)
+    pool.close()
+    for s in ss:
+        s.close()
+
+
+def test_failed_step_with_a_split_stream_advances_nothing():
+    """A step that lists a split-BF16 stream before a stream whose call is
+    invalid fails as a whole: no stream advances (blocks done unchanged) and
+    later steps give the same outputs as if the failed step never happened."""
+    import torch
+    T = binding()
+    B, L, n = 128, 900, 2048
+    nb = n // B
+    xs = np.stack([W.signal_gauss(n, 80 + c) for c in range(2)])
+    h = W.impulse_response(L, 82)
+
+    def run(with_failure):
+        sp = T.Stream(B, L, channels=2, max_blocks_per_call=nb, precision=T.TACHES_PREC_SPLIT_BF16)
+        sf = T.Stream(B, L, max_blocks_per_call=4)
+        sp.set_ir(h)
+        sf.set_ir(h)
+        pool = T.Pool(4, 8 * GB)
+        pool.attach(sp)
+        pool.attach(sf)
+        xsp = torch.from_numpy(np.ascontiguousarray(xs)).cuda()
+        xf = torch.from_numpy(np.ascontiguousarray(xs[:1, :4 * B])).cuda()
+        ysp, yf = torch.empty_like(xsp), torch.empty_like(xf)
+        if with_failure:
+            rc = T.taches_pool_step(pool.h, [sp.h, sf.h], [xsp, xf], [ysp, yf], [nb, 5])  # 5 > 4 blocks
+            assert rc == T.TACHES_EINVAL
+            pool.synchronize()
+            assert sp.info().blocks_done == 0 and sf.info().blocks_done == 0
+        pool.step([sp, sf], [xsp, xf], [ysp, yf], [nb, 4])
+        pool.synchronize()
+        out = (ysp.cpu().numpy(), yf.cpu().numpy(), sp.info().blocks_done, sf.info().blocks_done)
+        pool.close()
+        sp.close()
+        sf.close()
+        return out
+    a, b = run(False), run(True)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    assert a[2:] == b[2:] == (nb, 4)
+
+
 def test_config4_reduced_parity():
     """Batched-workload shape (log-uniform L, B in {32..512}) on 48 streams
     of 12 000 samples with L up to 16 384, one launch, vs the oracle."""
@@ -387,8 +488,9 @@ def test_config4_full_size_sampled_parity():
         y = ys[i].cpu().numpy()[0].astype(np.float64)
         idx = set(rng.integers(0, S, 40).tolist()) | {0, 1, n - 1, n, S - 1}
         idx = np.array(sorted(j for j in idx if 0 <= j < S))
-        ref = O.sampled_outputs(xs[i].cpu().numpy()[0], [irs[i]], [(0, 0)], B, idx)
-        rms = float(np.sqrt(np.mean(y ** 2)))
+        xi = xs[i].cpu().numpy()[0]
+        ref = O.sampled_outputs(xi, [irs[i]], [(0, 0)], B, idx)
+        rms = rms_y64(xi, [irs[i]], [(0, 0)], B, S)
         assert np.max(np.abs(y[idx] - ref)) <= 1e-5 * rms, f"stream {i} (L={int(Ls[i])}, B={B})"
     for s in ss:
         pool.detach(s)

@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 from paper_2401_01607_amd import workloads as W
-from tests.gpu_harness import binding, oracle_run, rel_err
+from tests.gpu_harness import binding, oracle_run, rel_err, rms_y64
 
 pytestmark = pytest.mark.gpu
 
@@ -159,7 +159,7 @@ def test_config5_full_load_sampled_parity():
         idx = np.array(sorted(j for j in idx if 0 <= j < S))
         for c in range(req.channels):
             ref = O.sampled_outputs(x[c], irs, sched, req.block, idx)
-            rms = float(np.sqrt(np.mean(y[c] ** 2)))
+            rms = rms_y64(x[c], irs, sched, req.block, S)
             assert np.max(np.abs(y[c][idx] - ref)) <= 1e-5 * rms, f"request {rid} channel {c}"
         checked += 1
     assert checked >= 3

@@ -128,40 +128,3 @@ def test_tail_state_split_layout():
         s.process(xb)
     for c in range(C):
         assert np.array_equal(s.read_tail(c, L), o.residue(c))
-
-
-def test_config3_full_size_sampled():
-    """Full multichannel size (64 channels x 240 000 samples, L = 2^18,
-    B = 512, FP64 tail) in one multi-block call plus drain, sampled outputs
-    against Eq. (4) in FP64 (numpy dot products)."""
-    import torch
-    from oracle import oracle as O
-    from tests.gpu_harness import binding
-    T = binding()
-    spec = W.config3()
-    B, L, C = spec.block, spec.max_ir_len, spec.channels
-    nb = spec.n_blocks()
-    nbd = -(-(L - 1) // B)
-    s = T.Stream(B, L, channels=C, max_blocks_per_call=max(nb, nbd), precision=SPLIT)
-    assert s.info().tail_fp64 == 1
-    s.set_ir(spec.irs[0])
-    xp = np.zeros((C, nb * B), np.float32)
-    xp[:, :spec.n_samples] = spec.x
-    xd = torch.from_numpy(xp).cuda()
-    yd = torch.empty_like(xd)
-    yt = torch.empty((C, nbd * B), device="cuda")
-    s.process_blocks(xd, yd, nb)
-    s.process_blocks(None, yt, nbd)
-    y = torch.cat([yd, yt], 1).cpu().numpy().astype(np.float64)
-    s.close()
-    rng = np.random.default_rng(3)
-    n_tot = spec.n_samples + L - 1
-    errs, refs = [], []
-    for c in range(0, C, 7):
-        idx = np.unique(np.concatenate([rng.integers(0, n_tot, 40), [0, 511, 512, spec.n_samples - 1, n_tot - 1]]))
-        ref = O.sampled_outputs(spec.x[c], spec.irs, spec.schedule, B, idx)
-        errs.append(np.abs(y[c, idx] - ref))
-        refs.append(ref)
-        assert not np.any(y[c, n_tot:])
-    rms = np.sqrt(np.mean(np.concatenate(refs) ** 2))
-    assert np.concatenate(errs).max() <= 1e-4 * rms

@@ -495,6 +495,41 @@ def test_sampled_outputs_match_full_oracle():
     assert np.all(np.abs(s - y[idx]) <= 1e-12 * mag[idx] + 1e-300)
 
 
+def test_sampled_and_fft_outputs_on_integer_swap_cases():
+    """The two whole-signal helpers used for full-size checks against Eq. (4)
+    summed in Python integers: sampled_outputs (FP64 dot products per IR
+    run) is exact on integers; fft_outputs (FP64 FFT per IR run) rounds to
+    the exact integers, with a swap inside a block too."""
+    cases = [(11, 37, 5, 9, 4, [(3, 0), (5, 0)]), (17, 40, 6, 3, 4, [(2, 1), (5, 3), (7, 0)]),
+             (15, 16, 16, 4, 5, [])]
+    for seed, n, L1, L2, B, swaps in cases:
+        x = W.signal_int(n, seed)
+        irs = [W.signal_int(L1, seed + 1), W.signal_int(L2, seed + 2)]
+        sched = [(0, 0)] + [(b, (i + 1) % 2, o) for i, (b, o) in enumerate(swaps)]
+        n_out = n + max(L1, L2) + B
+        ref = np.array([float(v) for v in O.brute_force(x, irs, sched, B, n_out)])
+        idx = np.arange(n_out)
+        assert np.array_equal(O.sampled_outputs(x, irs, sched, B, idx), ref)
+        f = O.fft_outputs(x, irs, sched, B, n_out)
+        assert np.array_equal(np.rint(f), ref)
+        assert np.max(np.abs(f - ref)) < 1e-9
+
+
+def test_fft_outputs_match_buffer_oracle_on_floats():
+    """fft_outputs agrees with O1 to FP64 rounding (1e-12 of the output RMS)
+    on a stream with swaps, and with numpy.convolve without swaps."""
+    spec = W.config2(n=6000, L=3000, block=256, period=1000)
+    n_out = 6000 + 2999
+    y = impl_o1(spec.x[0], spec.irs, spec.schedule, 256, 3000, n_out)
+    f = O.fft_outputs(spec.x[0], spec.irs, spec.schedule, 256, n_out)
+    rms = np.sqrt(np.mean(y ** 2))
+    assert np.max(np.abs(f - y)) <= 1e-12 * rms
+    x = W.signal_gauss(5000, 91)
+    h = W.impulse_response(777, 92)
+    c = np.convolve(x.astype(np.float64), h.astype(np.float64))
+    assert np.max(np.abs(O.fft_outputs(x, [h], [(0, 0)], 64, c.size) - c)) <= 1e-12 * np.sqrt(np.mean(c ** 2))
+
+
 def test_sample_swap_per_block_calls_equal_schedule_run():
     """set_ir(h, offset) between two blocks equals the scheduled whole-signal
     run bit for bit; a swap at offset 0 equals the block swap."""
