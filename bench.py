@@ -81,7 +81,7 @@ def parse():
     p.add_argument("--no-extras", action="store_true", help="main step, its errors and the CPU baseline only")
     p.add_argument("--no-errors", action="store_true", help="skip the error figures (profiling runs)")
     p.add_argument("--only", type=str, default="",
-                   help="run one extra section only (c1, c2, c3split, c4, c5, f2, f3, f4)")
+                   help="run one extra section only (c1, c2, c3split, c4, c5, f2, f4, tail, f3)")
     p.add_argument("--device-warmup-s", type=float, default=1.0,
                    help="seconds of untimed steps before the warm-up steps (device clock ramp)")
     return p.parse_args()
@@ -272,6 +272,7 @@ def main():
         run.step(timed=True)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
+    print(f"bench: {args.steps} timed steps, {dt * 1e3:.3f} ms per step", file=sys.stderr, flush=True)
     k_ms = run.s.call_times(args.steps)
     assert len(k_ms) == args.steps
     info = run.s.info()
@@ -345,13 +346,13 @@ def main():
 # ---------------------------------------------------------------------------
 
 def _median_device_ms(fn, s, reps):
-    """Median and min device time (library events) of `reps` calls of fn."""
+    """Median and min device time (library events) of `reps` calls of fn,
+    each of which records exactly one timed call on s."""
     ms = []
     for _ in range(reps):
-        s.set_timing(True)
         fn()
-        s.set_timing(False)
         ms.extend(s.call_times(1))
+    assert len(ms) == reps, f"{len(ms)} timed calls recorded, {reps} expected"
     return float(np.median(ms)), float(np.min(ms)), len(ms)
 
 
@@ -484,7 +485,7 @@ def extra_c3_split(errors):
     for _ in range(3):
         run.step()
     torch.cuda.synchronize()
-    med, mn, reps = _median_device_ms(run.step, run.s, 5)
+    med, mn, reps = _median_device_ms(lambda: run.step(timed=True), run.s, 5)
     res = {"workload": "same shape as the main step (64 channels x 240000, L=262144, B=512), "
                        "split-BF16 Toeplitz MFMA with FP32 accumulation per chunk and FP64 tail",
            "kernel_ms_median": round(med, 3), "kernel_ms_min": round(mn, 3), "runs": reps,
@@ -670,6 +671,52 @@ def extra_c5_serving(errors, duration_s=30.0, warmup_s=10.0):
     return st
 
 
+def extra_tail_policy(errors):
+    """Error of the FP32 and the FP64 tail against the FP64 oracle on one
+    mono stream (2 s of Gaussian input, flat white-noise IR: the paper's IR
+    shape, which gives the largest errors), at 512 to 4096 chunk sums per
+    output for B = 32, 64, 128 and 256: the measurements behind the AUTO
+    tail rule (FP64 above 1024 chunk sums per output, or for IRs of >= 2^18
+    taps)."""
+    import torch
+    from oracle import oracle as O
+    from paper_2401_01607_amd import taches as T
+    from paper_2401_01607_amd import workloads as W
+    n = 96_000
+    x = W.signal_gauss(n, 4242)
+    rows = []
+    for B in (32, 64, 128, 256):
+        for adds in (512, 1024, 2048, 4096):
+            L = adds * min(B, 256)
+            if L >= (1 << 18):
+                continue
+            h = W.impulse_response(L, 4343 + adds, decay=0.0)
+            nb, nbd = -(-n // B), -(-(L - 1) // B)
+            xp = np.zeros(nb * B, np.float32)
+            xp[:n] = x
+            xd = torch.from_numpy(xp).cuda()[None]
+            y64 = O.fft_outputs(x, [h], [(0, 0)], B, n + L - 1)
+            cfg = T.taches_config_default(B, L)
+            rec = {"B": B, "L": L, "chunk_sums_per_output": adds, "auto_tail": "fp64" if T.taches_tail_is_fp64(cfg) else "fp32"}
+            for tail, name in ((T.TACHES_TAIL_FP32, "fp32"), (T.TACHES_TAIL_FP64, "fp64")):
+                s = T.Stream(B, L, max_blocks_per_call=max(nb, nbd), tail=tail)
+                s.set_ir(h)
+                yd = torch.empty_like(xd)
+                yt = torch.empty((1, nbd * B), device="cuda")
+                s.process_blocks(xd, yd, nb)
+                s.process_blocks(None, yt, nbd)
+                y = torch.cat([yd, yt], 1)[0, :n + L - 1].cpu().numpy()
+                s.close()
+                e = err_stats(y, y64)
+                rec[name + "_tail"] = [e["max_abs_over_rms"], e["rms_err_over_rms"]]
+            rows.append(rec)
+    if errors is not None:
+        errors["tail_policy"] = {"sample": "every output of each stream; [max |err| / RMS(y64), RMS(err) / RMS(y64)]",
+                                 "rows": rows}
+    return {"workload": "1 mono stream, 96000 Gaussian samples, flat white-noise IR, L = chunk sums x min(B, 256)",
+            "configurations": len(rows)}
+
+
 def extra_f4_zero_bypass():
     """The mono stream with IR swaps, every other 4 800-sample period silent
     (exact zeros): chunks of zeros skip their multiply-adds (exact-zero
@@ -812,7 +859,7 @@ def extra_f3_capacity(block_sizes=(256, 1024, 4096, 16384, 65536),
     buffers (PCIe round trip included): for each block size, the longest
     real-time IR, bracketed by measured lengths (the largest measured in
     real time and the smallest measured not in real time).  The library
-    accepts IRs up to 2^30 - B taps; where even that length runs in real
+    accepts IRs up to 2^30 - 1 - B taps; where even that length runs in real
     time the limit is reported as at least that length.
 
     B: pools of N identical mono streams, each advancing one block per step
@@ -824,7 +871,8 @@ def extra_f3_capacity(block_sizes=(256, 1024, 4096, 16384, 65536),
     from paper_2401_01607_amd import workloads as W
     fs = float(W.FS)
     out = {"criterion": "mean block processing time < block period B/48000", "single_stream": [], "pool": []}
-    L_cap = (1 << 30) - max(block_sizes)
+    # a stream needs block_size + max_ir_len < 2^30 (one block per call)
+    L_cap = (1 << 30) - 1 - min(block_sizes)
     hbuf = torch.randn(L_cap, device="cuda") * 1e-4
     for B in block_sizes:
         period = B / fs
@@ -838,7 +886,7 @@ def extra_f3_capacity(block_sizes=(256, 1024, 4096, 16384, 65536),
             t, tmax = _single_stream_block_time(T, B, L, hbuf, x, y, warm, reps)
             times[L] = (t, tmax)
             return t
-        ok, bad, probes = _bracket(measure, 1 << 20, (1 << 30) - B, period)
+        ok, bad, probes = _bracket(measure, 1 << 20, (1 << 30) - 1 - B, period)
         rec = {"B": B, "period_ms": round(period * 1e3, 3),
                "longest_real_time_L_measured": ok, "shortest_non_real_time_L_measured": bad,
                "probes": [{"L": L, "ms_per_block": round(t * 1e3, 4), "max_ms": round(times[L][1] * 1e3, 4),
@@ -846,7 +894,7 @@ def extra_f3_capacity(block_sizes=(256, 1024, 4096, 16384, 65536),
         if ok is not None:
             rec["longest_real_time_ir_seconds_at_48k"] = round(ok / fs, 1)
         if bad is None:
-            rec["note"] = "real time up to the longest IR the library accepts (2^30 - B taps)"
+            rec["note"] = "real time up to the longest IR the library accepts (2^30 - 1 - B taps)"
         out["single_stream"].append(rec)
     del hbuf
     torch.cuda.empty_cache()
@@ -899,13 +947,14 @@ def extras(args, errors):
     sections = {"c1": lambda: extra_c1(errors), "c2": lambda: extra_c2(errors),
                 "c3split": lambda: extra_c3_split(errors), "c4": lambda: extra_c4_batched(errors),
                 "c5": lambda: extra_c5_serving(errors), "f2": extra_f2_offline, "f4": extra_f4_zero_bypass,
-                "f3": extra_f3_capacity}
+                "tail": lambda: extra_tail_policy(errors), "f3": extra_f3_capacity}
     for name, fn in sections.items():
         if args.only and args.only != name:
             continue
         t0 = time.perf_counter()
         out[name] = fn()
         out[name]["section_s"] = round(time.perf_counter() - t0, 1)
+        print(f"bench: section {name} done in {out[name]['section_s']} s", file=sys.stderr, flush=True)
     return out
 
 

@@ -57,7 +57,7 @@ extern "C" {
 #define TACHES_PREC_SPLIT_BF16 1 /* hi+lo BF16 on MFMA, FP32 accumulation     */
 
 /* ---- type of the circular tail accumulator ----------------------------- */
-#define TACHES_TAIL_AUTO 0 /* FP64 when L >= 2^18 or L/min(B,256) > 4096 */
+#define TACHES_TAIL_AUTO 0 /* FP64 when L >= 2^18 or L/min(B,256) > 1024 */
 #define TACHES_TAIL_FP32 1
 #define TACHES_TAIL_FP64 2
 
@@ -217,6 +217,14 @@ int taches_call_times(taches_stream* s, double* ms_out, int32_t n);
 
 /* Device bytes a stream with this config would own (for HBM admission). */
 int64_t taches_bytes_for(const taches_config* cfg);
+
+/* 1 if a stream opened with this config keeps an FP64 tail, 0 for FP32
+ * (TACHES_TAIL_AUTO resolved from block_size and max_ir_len: one output
+ * receives about max_ir_len / min(block_size, 256) chunk sums, and more
+ * than 1024 of them, or an IR of >= 2^18 taps, take FP64); TACHES_EINVAL for
+ * an invalid config.  Lets a caller that opens streams with a larger
+ * max_ir_len than the IRs it will load pick the tail from the IR length. */
+int taches_tail_is_fp64(const taches_config* cfg);
 
 /* Copy the pending sums for the next n output samples of channel c into
  * out[0..n) (host, FP64).  Synchronizes the handle.  Slot k is what the

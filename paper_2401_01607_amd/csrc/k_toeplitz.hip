@@ -35,6 +35,7 @@ namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int MT = 128;                    // output slots per workgroup (MT / 32 waves x 32 rows)
 constexpr int NT = 2 * MT;                 // threads per workgroup
@@ -86,17 +87,17 @@ __device__ __forceinline__ void split_fragment(const GatherCall& d, int64_t t) {
     for (int j = 0; j < 8; ++j) {
       const int s = kg * 8 + j;
       float v = 0.f;
-      if (c < d.channels && s < len) v = d.x[(int64_t)c * d.x_cstride + m_lo + s];
+      if (c < d.channels && s < len) v = gr(d.x)[(int64_t)c * d.x_cstride + m_lo + s];
       hv[j] = bf16_rn(v);
       lv[j] = bf16_rn(v - bf16_to_f(hv[j]));
     }
-    uint4 ph, pl;
+    u32x4 ph, pl;
     ph.x = hv[0] | ((uint32_t)hv[1] << 16); ph.y = hv[2] | ((uint32_t)hv[3] << 16);
     ph.z = hv[4] | ((uint32_t)hv[5] << 16); ph.w = hv[6] | ((uint32_t)hv[7] << 16);
     pl.x = lv[0] | ((uint32_t)lv[1] << 16); pl.y = lv[2] | ((uint32_t)lv[3] << 16);
     pl.z = lv[4] | ((uint32_t)lv[5] << 16); pl.w = lv[6] | ((uint32_t)lv[7] << 16);
-    *reinterpret_cast<uint4*>(d.xs_hi + t * 8) = ph;
-    *reinterpret_cast<uint4*>(d.xs_lo + t * 8) = pl;
+    *reinterpret_cast<GLB u32x4*>(gw(d.xs_hi) + t * 8) = ph;
+    *reinterpret_cast<GLB u32x4*>(gw(d.xs_lo) + t * 8) = pl;
   }
 }
 
@@ -169,7 +170,7 @@ __device__ __forceinline__ void toeplitz_tile(const GatherCall& d, const int til
   const int kg = l >> 5;  // k-group of 8 within a 16-deep K-step
   const int n0 = tile * MT;
   const int cpad = d.cpad;
-  TailT* ring = reinterpret_cast<TailT*>(d.ring);
+  GLB TailT* ring = gw(reinterpret_cast<TailT*>(d.ring));
   // this wave's tile: rows r0 .. r0 + 32*NM - 1, channels c0 .. c0 + 32*NN - 1
   constexpr int WN = 64 / (32 * NN) > 0 ? 64 / (32 * NN) : 1;   // wave columns for 64 channels
   const int wn = (cpad == 64) ? w % WN : 0;
@@ -211,8 +212,8 @@ __device__ __forceinline__ void toeplitz_tile(const GatherCall& d, const int til
     const int64_t xo = (((int64_t)chunk * 32 + 2 * t + kg) * cpad + c0 + i) * 8;
 #pragma unroll
     for (int nt = 0; nt < NN; ++nt) {
-      f.h[nt] = *reinterpret_cast<const bf16x8*>(d.xs_hi + xo + nt * 32 * 8);
-      f.l[nt] = *reinterpret_cast<const bf16x8*>(d.xs_lo + xo + nt * 32 * 8);
+      f.h[nt] = *reinterpret_cast<const GLB bf16x8*>(gr(d.xs_hi) + xo + nt * 32 * 8);
+      f.l[nt] = *reinterpret_cast<const GLB bf16x8*>(gr(d.xs_lo) + xo + nt * 32 * 8);
     }
   };
   if (d.x != nullptr) {
@@ -381,7 +382,7 @@ __device__ __forceinline__ void toeplitz_tile(const GatherCall& d, const int til
           int slot = d.head + n;
           if (slot >= d.Rcap) slot -= d.Rcap;
           if (n < d.S) {
-            if (c < d.channels) d.y[(int64_t)c * d.y_cstride + n] = (float)acc[mt][nt][q];
+            if (c < d.channels) gw(d.y)[(int64_t)c * d.y_cstride + n] = (float)acc[mt][nt][q];
             ring[(int64_t)slot * cpad + c] = (TailT)0;
           } else {
             ring[(int64_t)slot * cpad + c] = acc[mt][nt][q];

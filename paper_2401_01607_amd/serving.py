@@ -380,8 +380,10 @@ class GpuExecutor:
     shape, Section 5.1), each row of unit L2 norm over max_ir_len taps, so a
     swap is one device-to-device copy.  Outputs of the requests listed in
     keep_outputs go to a [C][n_total*B] buffer per request, the others to a
-    scratch buffer reused by every step.  Retired streams are reset and
-    reused for later requests with the same (B, channels, IR-length class);
+    scratch buffer reused by every step.  A stream's tail type follows the
+    library's AUTO rule applied to the request's own IR length.  Retired
+    streams are reset and reused for later requests with the same (B,
+    channels, IR-length class, tail type);
     idle ones count against the HBM budget and are closed when a new stream
     needs their bytes."""
 
@@ -445,9 +447,20 @@ class GpuExecutor:
         off = self.input_offset(req)
         return self.bank[:req.channels, off:off + self.n_input_blocks(req) * req.block]
 
+    def tail_for(self, req) -> int:
+        """The tail the library's AUTO rule gives the request's own IR length
+        (streams are opened with the longer capacity class, so AUTO on their
+        max_ir_len would pick FP64 for some IRs that do not need it)."""
+        T = self.T
+        cfg = T.taches_config_default(req.block, req.ir_len)
+        cfg.channels = req.channels
+        cfg.precision = self.precision
+        return T.TACHES_TAIL_FP64 if T.taches_tail_is_fp64(cfg) == 1 else T.TACHES_TAIL_FP32
+
     def admit(self, req) -> int:
         T = self.T
-        key = (req.block, req.channels, min(self.ir_class(req.ir_len), self.max_ir_len))
+        tail = self.tail_for(req)
+        key = (req.block, req.channels, min(self.ir_class(req.ir_len), self.max_ir_len), tail)
         if not self.free_handles:
             raise AdmissionRefused("slots")
         lst = self.free.get(key)
@@ -459,6 +472,7 @@ class GpuExecutor:
             cfg.channels = req.channels
             cfg.max_blocks_per_call = self.max_blocks_per_step
             cfg.precision = self.precision
+            cfg.tail = tail
             need = T.taches_bytes_for(cfg)
             used = self.pool.info().used_bytes
             # close idle recycled streams (largest first) until the new one fits
@@ -470,7 +484,7 @@ class GpuExecutor:
             if used + self.idle_bytes + need > self.budget:
                 raise AdmissionRefused("budget")
             s = T.Stream(req.block, key[2], channels=req.channels, max_blocks_per_call=self.max_blocks_per_step,
-                         precision=self.precision)
+                         precision=self.precision, tail=tail)
         rc = self.pool.attach(s)
         if rc != T.TACHES_OK:
             self.free.setdefault(key, []).append(s)

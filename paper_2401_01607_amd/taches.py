@@ -77,6 +77,7 @@ _SIGS = {
     "taches_process_blocks_at": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp, _vp]),
     "taches_get_info": (ctypes.c_int, [_vp, _P(taches_info)]),
     "taches_bytes_for": (_i64, [_P(taches_config)]),
+    "taches_tail_is_fp64": (ctypes.c_int, [_P(taches_config)]),
     "taches_read_tail": (ctypes.c_int, [_vp, _i32, _vp, _i32]),
     "taches_set_tile": (ctypes.c_int, [_vp, _i32, _i32]),
     "taches_set_timing": (ctypes.c_int, [_vp, _i32]),
@@ -217,6 +218,10 @@ def taches_get_info(s) -> taches_info:
 
 def taches_bytes_for(cfg: taches_config) -> int:
     return int(lib.taches_bytes_for(ctypes.byref(cfg)))
+
+
+def taches_tail_is_fp64(cfg: taches_config) -> int:
+    return int(lib.taches_tail_is_fp64(ctypes.byref(cfg)))
 
 
 def taches_read_tail(s, channel: int, n: int) -> np.ndarray:

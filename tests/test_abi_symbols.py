@@ -51,6 +51,27 @@ def test_config_default_and_bytes_need_no_gpu():
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libtaches.so not built")
+def test_auto_tail_rule_needs_no_gpu():
+    """AUTO keeps an FP64 tail for IRs of >= 2^18 taps or more than 1024
+    chunk sums per output (chunk = min(B, 256)); explicit tails win."""
+    from paper_2401_01607_amd import taches as T
+    cases = [(32, 32_768, 0), (32, 32_769, 1), (64, 65_536, 0), (64, 65_537, 1), (128, 131_072, 0),
+             (128, 131_073, 1), (256, 262_143, 0), (512, 262_143, 0), (512, 262_144, 1), (1024, 262_143, 0),
+             (64, 1024, 0)]
+    for B, L, want in cases:
+        c = T.taches_config_default(B, L)
+        assert T.taches_tail_is_fp64(c) == want, (B, L)
+    c = T.taches_config_default(32, 1 << 20)
+    c.tail = T.TACHES_TAIL_FP32
+    assert T.taches_tail_is_fp64(c) == 0
+    c = T.taches_config_default(512, 16)
+    c.tail = T.TACHES_TAIL_FP64
+    assert T.taches_tail_is_fp64(c) == 1
+    c.max_ir_len = 0
+    assert T.taches_tail_is_fp64(c) == T.TACHES_EINVAL
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libtaches.so not built")
 def test_binding_structs_match_the_header_layout(tmp_path):
     """Compile the header with the host C compiler and compare every
     struct's size and field offsets with the ctypes mirrors."""

@@ -191,12 +191,29 @@ def test_long_ir_auto_picks_fp64_tail():
     s = T.Stream(512, 1 << 18)
     assert s.info().tail_fp64 == 1
     s.close()
-    s = T.Stream(32, 131_072)
+    s = T.Stream(32, 32_768)
     assert s.info().tail_fp64 == 0
     s.close()
-    s = T.Stream(32, 131_073)
+    s = T.Stream(32, 32_769)
     assert s.info().tail_fp64 == 1
     s.close()
+
+
+@pytest.mark.parametrize("B,L", [(32, 32_768), (64, 65_536), (128, 131_072)])
+def test_fp32_tail_at_the_auto_limit_meets_the_tolerance(B, L):
+    """The longest IRs that AUTO leaves on an FP32 tail (1024 chunk sums per
+    output), with a flat white-noise IR (the paper's IR shape, which gives
+    the largest errors): every output within 1e-5 * RMS of the FP64 result."""
+    from oracle import oracle as O
+    n = 96_000
+    x = W.signal_gauss(n, 151)
+    h = W.impulse_response(L, 152, decay=0.0)
+    nb = -(-(n + L - 1) // B)
+    y, info = gpu_multi_block(x, [h], [(0, 0)], B, L, nb)
+    assert info.tail_fp64 == 0
+    n_out = n + L - 1
+    y64 = O.fft_outputs(x, [h], [(0, 0)], B, n_out)
+    assert rel_err(y[0][:n_out], y64) <= TOL
 
 
 def test_longest_ir_4m_taps_streaming_sampled_parity():
