@@ -186,6 +186,28 @@ int taches_process_blocks_at(taches_stream* s, const float* x_dev, float* y_dev,
 int taches_convolve(const float* x_dev, int64_t nx, int32_t channels, const float* h_dev, int32_t nh, float* y_dev,
                     int32_t precision, int32_t role_swap, int32_t device, void* hip_stream);
 
+/* taches_convolve for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  FP32 precision; same operands, role exchange and result as
+ * taches_convolve with TACHES_PREC_FP32, bit for bit.  Its work memory (the
+ * zero-padded input and the tail the kernel clears as it emits) is a fixed
+ * 64 MiB array per device, held from the first call on that device until
+ * the process ends: the call needs
+ *   align256(4 * channels * ceil(ns / 256) * 256) + w * channels * (nx + nh - 1)
+ * bytes of it (ns = the signal operand's length after any role exchange,
+ * w = 8 when the longer-lived operand, the IR, has >= 2^18 taps, else 4),
+ * and returns TACHES_EINVAL when that exceeds 64 MiB.  Allocates nothing
+ * (no hipMalloc, hipFree or allocating library call) and does not wait:
+ * the work is enqueued on hip_stream (NULL = HIP's null stream) of `device`
+ * and y_dev is written once that stream has run it; keep x_dev, h_dev and
+ * y_dev alive until then.  Every call on one device shares the one array:
+ * calls that may overlap on a device (on different HIP streams, or from
+ * different threads without ordering) race and give wrong results; calls
+ * ordered on one HIP stream are safe.  TACHES_EINVAL for NULL buffers, bad
+ * sizes or a device ordinal >= 64, TACHES_EDEVICE on a HIP error. */
+int taches_convolve_noalloc(const float* x_dev, int64_t nx, int32_t channels, const float* h_dev, int32_t nh,
+                            float* y_dev, int32_t role_swap, int32_t device, void* hip_stream);
+
 /* ---- state ------------------------------------------------------------- */
 
 typedef struct taches_info {

@@ -17,6 +17,10 @@
 using taches::BlockIR;
 using taches::GatherCall;
 
+// Work memory of taches_convolve_noalloc on each device (see below).
+constexpr size_t kNoallocScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
 namespace {
 
 // Message of the last failure on this thread: a fixed buffer, so that
@@ -661,6 +665,27 @@ int process_common(taches_stream* s, const float* x_dev, float* y_dev, int n_blo
   return TACHES_OK;
 }
 
+// ---- work memory of taches_convolve_noalloc ----
+// One fixed array per device, set aside when the code object is loaded on
+// that device and held until the process ends.  Host code never passes the
+// array's name to a kernel (on the host it is only a stand-in for the
+// symbol): the device address comes from hipGetSymbolAddress, once per
+// device, and is kept in g_scratch_dev.
+constexpr int kMaxDevices = 64;
+void* g_scratch_dev[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+// Zero-padded copy of planar signals: dst[c][i] = src[c][i] for i < ns, 0
+// for ns <= i < nd.
+__global__ __launch_bounds__(256) void k_pad_copy(const float* __restrict__ src, int64_t ns, float* __restrict__ dst,
+                                                  int64_t nd, int channels) {
+  const int64_t total = nd * channels;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = t / nd, i = t - c * nd;
+    dst[t] = i < ns ? src[c * ns + i] : 0.f;
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -865,6 +890,94 @@ int taches_convolve(const float* x_dev, int64_t nx, int32_t channels, const floa
   {
     ErrKeep keep;
     (void)taches_close(s);
+  }
+  return rc;
+}
+
+int taches_convolve_noalloc(const float* x_dev, int64_t nx, int32_t channels, const float* h_dev, int32_t nh,
+                            float* y_dev, int32_t role_swap, int32_t device, void* hip_stream) {
+  if (!x_dev || !h_dev || !y_dev) return fail(TACHES_EINVAL, "NULL buffer");
+  if (nx < 1 || nh < 1 || channels < 1) return fail(TACHES_EINVAL, "nx, nh and channels must be >= 1");
+  if (device < 0 || device >= kMaxDevices) return fail(TACHES_EINVAL, "device %d outside [0, %d)", device, kMaxDevices);
+  // the same operands, block size, chunks and tail type as taches_convolve,
+  // so both give the same bits
+  const bool swap = role_swap != 0 && channels == 1 && (int64_t)nh > nx;
+  const float* sig = swap ? h_dev : x_dev;
+  const float* ir = swap ? x_dev : h_dev;
+  const int64_t ns = swap ? nh : nx;
+  const int64_t L = swap ? nx : nh;
+  const int64_t n_out = nx + nh - 1;
+  const int B = 256;
+  const int64_t n_in = (ns + B - 1) / B;
+  const int64_t S_in = n_in * B;
+  if (S_in + L >= ((int64_t)1 << 30)) return fail(TACHES_EINVAL, "signal too long");
+  taches_config cfg;
+  taches_config_default(&cfg, B, (int32_t)L);
+  const bool fp64 = want_fp64(cfg);
+  // work memory: the zero-padded input [C][S_in] (FP32) and a tail of
+  // [C][n_out] slots that the kernel clears as it emits (every output of the
+  // single call is emitted, none is kept)
+  const size_t x_bytes = (size_t)round_up((int64_t)channels * S_in * 4, 256);
+  const size_t need = x_bytes + (size_t)channels * (size_t)n_out * (fp64 ? 8 : 4);
+  if ((int64_t)channels * n_out > ((int64_t)1 << 32) || need > kNoallocScratchBytes)
+    return fail(TACHES_EINVAL, "needs %zu bytes of work memory, the limit is %zu", need, kNoallocScratchBytes);
+  int prev = -1;
+  HIPCHK(hipGetDevice(&prev));
+  if (prev != device) HIPCHK(hipSetDevice(device));
+  int rc = TACHES_OK;
+  unsigned char* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[device]) {
+      void* ptr = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !ptr)
+        rc = fail(TACHES_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+      else
+        g_scratch_dev[device] = ptr;
+    }
+    base = static_cast<unsigned char*>(g_scratch_dev[device]);
+  }
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  float* xp = reinterpret_cast<float*>(base);
+  if (rc == TACHES_OK) {
+    const int64_t total = (int64_t)channels * S_in;
+    const int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_pad_copy, dim3(blocks), dim3(256), 0, st, sig, ns, xp, S_in, channels);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) rc = fail(TACHES_EDEVICE, "input copy: %s", hipGetErrorString(e));
+  }
+  if (rc == TACHES_OK) {
+    GatherCall g{};
+    g.x = xp;
+    g.y = y_dev;
+    g.ring = base + x_bytes;
+    g.irs = nullptr;
+    g.ir0.h = ir;
+    g.ir0.L = (int32_t)L;
+    g.x_cstride = S_in;
+    g.y_cstride = n_out;
+    g.ring_cstride = n_out;
+    g.S = (int32_t)n_out;          // every output is emitted by this call
+    g.B = B;
+    g.n_blocks = (int32_t)n_in;
+    g.cpb = (B + taches::CHUNK_MAX - 1) / taches::CHUNK_MAX;
+    g.Rcap = (int32_t)n_out;
+    g.head = 0;
+    g.live_in = 0;
+    g.n_out = (int32_t)n_out;
+    g.Lmax_call = (int32_t)L;
+    g.channels = channels;
+    g.cpad = channels;
+    const int span_blocks = (int)std::min<int64_t>(n_in, (64 * 16 + L - 1 + B - 1) / B + 1);
+    const TilePlan plan = plan_tile(0, channels, S_in, n_out, L, span_blocks * g.cpb);
+    g.tile_order = plan.order;
+    const hipError_t e = taches::launch_gather(g, fp64, plan.r, plan.w, st);
+    if (e != hipSuccess) rc = fail(TACHES_EDEVICE, "gather launch: %s", hipGetErrorString(e));
+  }
+  if (prev != device) {
+    ErrKeep keep;
+    (void)hipSetDevice(prev);
   }
   return rc;
 }

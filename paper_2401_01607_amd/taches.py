@@ -96,6 +96,7 @@ _SIGS = {
     "taches_pool_get_info": (ctypes.c_int, [_vp, _P(taches_pool_info)]),
     "taches_fp32_fma_ceiling": (ctypes.c_int, [_i32, _P(ctypes.c_double)]),
     "taches_convolve": (ctypes.c_int, [_vp, _i64, _i32, _vp, _i32, _vp, _i32, _i32, _i32, _vp]),
+    "taches_convolve_noalloc": (ctypes.c_int, [_vp, _i64, _i32, _vp, _i32, _vp, _i32, _i32, _vp]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(lib, _name)
@@ -328,6 +329,22 @@ def taches_convolve(x_dev, h_dev, y_dev, precision: int = TACHES_PREC_FP32, role
         hip_stream = torch.cuda.current_stream(device).cuda_stream
     return lib.taches_convolve(_dev_ptr(x_dev), nx, C, _dev_ptr(h_dev), nh, _dev_ptr(y_dev), precision,
                                1 if role_swap else 0, device, ctypes.c_void_p(hip_stream) if hip_stream else None)
+
+
+def taches_convolve_noalloc(x_dev, h_dev, y_dev, role_swap: bool = False, device: int = 0, hip_stream=None) -> int:
+    """taches_convolve (FP32) without allocation: same tensors as
+    taches_convolve; the work is only enqueued (synchronize the stream
+    before reading y_dev)."""
+    C = 1 if x_dev.dim() == 1 else int(x_dev.shape[0])
+    nx = int(x_dev.shape[-1])
+    nh = int(h_dev.numel())
+    if tuple(y_dev.shape[-1:]) != (nx + nh - 1,) or (x_dev.dim() > 1 and int(y_dev.shape[0]) != C):
+        raise ValueError("y must be [C][nx + nh - 1]")
+    if hip_stream is None:
+        hip_stream = torch.cuda.current_stream(device).cuda_stream
+    return lib.taches_convolve_noalloc(_dev_ptr(x_dev), nx, C, _dev_ptr(h_dev), nh, _dev_ptr(y_dev),
+                                       1 if role_swap else 0, device,
+                                       ctypes.c_void_p(hip_stream) if hip_stream else None)
 
 
 def taches_fp32_fma_ceiling(device: int = 0) -> float:
