@@ -344,6 +344,100 @@ typedef struct taches_pool_info {
 
 int taches_pool_get_info(const taches_pool* p, taches_pool_info* out);
 
+/* ---- a7: serving tick — real-time streams of a pool, one call per tick ----
+ *
+ * A server drives attached streams of one pool in real time (continuous
+ * batching for low-latency real-time use with changing IRs, Section 6).  A
+ * registered stream delivers one block of B samples per channel every
+ * B / fs seconds from its start time; after its n_in input blocks, its
+ * temporal overflow (Section 4.1) is drained with zero-input blocks paced
+ * the same way, up to n_total blocks.  taches_server_tick takes every block
+ * whose last sample has arrived by the server clock, over all registered
+ * streams (at most max_blocks_per_step per stream), and runs them as one
+ * pool step: the arrived input is gathered from each stream's host buffer
+ * into pinned memory and copied to the device in one transfer; every output
+ * block is copied back in one transfer and written to the stream's host
+ * buffer (if any) before the call returns.  An IR change scheduled at time
+ * t (seconds from the stream's start) applies to the first block that
+ * starts at or after t (the IR is replaced for the next samples, Abstract
+ * and Section 6).  Latency of a block = the tick's completion time (outputs
+ * in host memory) minus the arrival time of its last sample; the deadline
+ * is one block period.  The server does not own streams: register an
+ * attached stream, and detach it after its tag is reported finished.  A
+ * server is not thread-safe.  After TACHES_EDEVICE from a tick, destroy the
+ * server and its pool. */
+
+typedef struct taches_server taches_server;
+
+typedef struct taches_server_tick_info {
+  int32_t streams;  /* streams advanced (0: no block was due, nothing ran) */
+  int32_t pad_;
+  int64_t blocks;   /* blocks processed */
+  double now_s;     /* server clock when the tick started */
+  double done_s;    /* server clock when every output block was in host memory */
+  double host_ms;   /* host work before the first transfer (ranges, IR changes, input gather) */
+  double step_ms;   /* the whole tick */
+  double next_due_s;/* server clock at which the next block of a registered
+                       stream is complete (HUGE_VAL if none is registered) */
+} taches_server_tick_info;
+
+typedef struct taches_server_stats {
+  int64_t ticks;                  /* ticks that ran a step */
+  int64_t blocks;                 /* blocks processed */
+  int64_t macs;                   /* direct-equivalent MACs of the input blocks */
+  int64_t max_blocks_in_a_range;  /* most blocks of one stream in one step */
+  int64_t bytes_in, bytes_out;    /* host-to-device input and device-to-host output bytes */
+  double busy_s;                  /* summed duration of the ticks that ran a step */
+  int32_t streams;                /* streams registered and not finished */
+  int32_t pad_;
+} taches_server_stats;
+
+/* NULL on failure.  fs > 0 (samples per second), max_blocks_per_step >= 1
+ * (every registered stream must accept that many blocks per call); blocks
+ * whose last sample arrives before warmup_s (server clock) are not
+ * recorded.  The server clock starts at 0 when the server is created. */
+taches_server* taches_server_create(taches_pool* pool, double fs, int32_t max_blocks_per_step, double warmup_s);
+
+/* Waits for the pool's queued work and frees the staging.  NULL is a no-op. */
+int taches_server_destroy(taches_server* sv);
+
+/* Seconds since taches_server_create (steady clock); -1 for NULL. */
+double taches_server_clock(const taches_server* sv);
+
+/* Register stream s (attached to the server's pool, its IR for the first
+ * block already set) under `tag` (unique per server).  start_s: server-clock
+ * time of its first sample.  x_host: [C][x_cstride] host input, n_in_blocks
+ * * B samples per channel (caller-owned, alive until the stream finishes).
+ * y_host: [C][y_cstride] host output of n_total_blocks * B samples per
+ * channel, or NULL to discard the outputs after their transfer.
+ * n_swaps IR changes: ascending times swap_times_s (seconds from the
+ * stream's start), device IRs swap_ir_dev[i] of swap_len[i] taps (alive
+ * until applied).  TACHES_EINVAL for bad sizes or a duplicate tag. */
+int taches_server_add(taches_server* sv, taches_stream* s, int64_t tag, double start_s, int64_t n_in_blocks,
+                      int64_t n_total_blocks, const float* x_host, int64_t x_cstride, float* y_host, int64_t y_cstride,
+                      int32_t n_swaps, const double* swap_times_s, const float* const* swap_ir_dev,
+                      const int32_t* swap_len);
+
+/* One tick at the current server clock: runs one step if any block is due,
+ * waits for it and fills *out (may be NULL).  Streams whose last block was
+ * processed leave the server (see taches_server_take_finished). */
+int taches_server_tick(taches_server* sv, taches_server_tick_info* out);
+
+/* Tags of streams that finished since the last call (at most cap, oldest
+ * first); returns how many were written. */
+int taches_server_take_finished(taches_server* sv, int64_t* tags, int32_t cap);
+
+/* Recorded block latencies (seconds) and their block sizes since the last
+ * call (at most cap, oldest first); returns how many were written. */
+int taches_server_take_latencies(taches_server* sv, float* latency_s, int32_t* block_size, int32_t cap);
+
+/* Next block of a registered (or finished) stream, and the blocks at which
+ * its IR changes took effect (at most cap written); returns the number of
+ * changes applied so far. */
+int taches_server_stream_state(taches_server* sv, int64_t tag, int64_t* next_block, int64_t* swap_blocks, int32_t cap);
+
+int taches_server_get_stats(const taches_server* sv, taches_server_stats* out);
+
 /* ---- diagnostics -----------------------------------------------------------
  *
  * FP32 fused-multiply-add rate (TFLOP/s, 2 FLOP per FMA) that independent

@@ -133,6 +133,13 @@ int toeplitz_rows_per_tile();
 hipError_t launch_toeplitz_batched(const unsigned char* table_dev, const ToeplitzBatch& b, bool tail_fp64, bool wide,
                                    hipStream_t st);
 
+// Runtime services for the serving tick (taches_runtime.hip): set the
+// thread's error message and return `code`; the HIP stream a pool's steps
+// run on; whether a stream is attached to a pool.
+int set_error(int code, const char* fmt, ...);
+hipStream_t pool_stream(const taches_pool* p);
+bool stream_in_pool(const taches_stream* s, const taches_pool* p);
+
 // FP32 FMA issue ceiling of the device (k_diag.hip): TFLOP/s reached by
 // independent v_fmac_f32 chains.
 hipError_t measure_fmac_ceiling(int device, double* tflops);

@@ -1794,3 +1794,19 @@ int taches_pool_step_strided(taches_pool* p, int32_t n, taches_stream* const* st
 }
 
 }  // extern "C"
+
+namespace taches {
+
+int set_error(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, kErrLen, fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+hipStream_t pool_stream(const taches_pool* p) { return p->stream; }
+
+bool stream_in_pool(const taches_stream* s, const taches_pool* p) { return s->pool == p; }
+
+}  // namespace taches

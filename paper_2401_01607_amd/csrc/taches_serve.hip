@@ -1,0 +1,386 @@
+// Serving tick of libtaches: real-time streams of a pool advanced by one
+// library call per tick.
+//
+// Each registered stream delivers one block of B samples per channel every
+// B / fs seconds from its start time (real-time pacing); after its input,
+// the temporal overflow (L - 1 samples, Section 4.1) is drained with
+// zero-input blocks paced the same way.  A tick takes every block whose
+// last sample has arrived by the tick's clock reading, over all streams,
+// and runs them as one pool step: the arrived input is gathered from each
+// stream's host buffer into pinned memory, copied to the device in one
+// transfer, processed by the pool's batched launch, and every output block
+// is copied back in one transfer and handed to the stream's host buffer.
+// An IR change scheduled at time t of a stream applies to its first block
+// that starts at or after t (the IR is replaced "for next samples",
+// Abstract and Section 6): a step's range of blocks ends before such a
+// block, which starts the next range.
+//
+// Latency of a block = the tick's completion time (outputs in host memory)
+// minus the arrival time of the block's last sample; the deadline is one
+// block period.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "taches.h"
+#include "taches_internal.h"
+
+namespace {
+
+struct ServeStream {
+  taches_stream* s = nullptr;
+  int64_t tag = 0;
+  double start_s = 0.0;
+  int32_t B = 0, C = 0;
+  int64_t n_in = 0, n_total = 0, next = 0;
+  const float* x = nullptr;
+  int64_t x_cs = 0;
+  float* y = nullptr;
+  int64_t y_cs = 0;
+  std::vector<double> swap_t;
+  std::vector<const float*> swap_h;
+  std::vector<int32_t> swap_L;
+  size_t swap_next = 0;
+  std::vector<int64_t> swap_blocks;   // block index at which each applied swap took effect
+};
+
+// First block k of a stream with start time k * B / fs >= t (k >= k_min).
+int64_t first_block_at(double t, int32_t B, double fs, int64_t k_min) {
+  int64_t k = (int64_t)std::ceil(t * fs / B - 1e-9);
+  k = std::max(k, k_min);
+  while (k > k_min && (double)((k - 1) * B) / fs >= t) --k;
+  while ((double)(k * B) / fs < t) ++k;
+  return k;
+}
+
+}  // namespace
+
+struct taches_server {
+  taches_pool* pool = nullptr;
+  double fs = 48000.0;
+  int32_t max_blocks = 1;
+  double warmup_s = 0.0;
+  std::chrono::steady_clock::time_point t0;
+  std::vector<ServeStream> st;
+  // pinned host and device staging of one tick's input and output blocks
+  float* x_pin = nullptr;
+  float* y_pin = nullptr;
+  size_t pin_cap = 0;     // floats per buffer
+  float* x_dev = nullptr;
+  float* y_dev = nullptr;
+  size_t dev_cap = 0;
+  // per-tick argument arrays of the pool step (kept to avoid reallocation)
+  std::vector<taches_stream*> a_s;
+  std::vector<const float*> a_x;
+  std::vector<float*> a_y;
+  std::vector<int32_t> a_n;
+  std::vector<int32_t> a_idx;
+  std::vector<int64_t> a_k0, a_xoff, a_yoff;
+  // records
+  std::vector<float> lat_s;
+  std::vector<int32_t> lat_B;
+  std::vector<int64_t> finished;     // tags not yet taken by the caller
+  std::vector<ServeStream> done;     // records of finished streams (state queries)
+  taches_server_stats stats{};
+};
+
+namespace {
+
+double clock_s(const taches_server* sv) {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now() - sv->t0).count();
+}
+
+ServeStream* find_tag(taches_server* sv, int64_t tag, bool with_done = false) {
+  for (ServeStream& r : sv->st)
+    if (r.tag == tag) return &r;
+  if (with_done)
+    for (ServeStream& r : sv->done)
+      if (r.tag == tag) return &r;
+  return nullptr;
+}
+
+int grow(taches_server* sv, size_t floats) {
+  if (floats > sv->pin_cap) {
+    const size_t cap = std::max(floats, 2 * sv->pin_cap);
+    (void)hipHostFree(sv->x_pin);
+    (void)hipHostFree(sv->y_pin);
+    sv->x_pin = sv->y_pin = nullptr;
+    sv->pin_cap = 0;
+    if (hipHostMalloc((void**)&sv->x_pin, cap * 4, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&sv->y_pin, cap * 4, hipHostMallocDefault) != hipSuccess)
+      return taches::set_error(TACHES_ENOMEM, "serving: pinned staging of %zu floats", cap);
+    sv->pin_cap = cap;
+  }
+  if (floats > sv->dev_cap) {
+    const size_t cap = std::max(floats, 2 * sv->dev_cap);
+    (void)hipFree(sv->x_dev);
+    (void)hipFree(sv->y_dev);
+    sv->x_dev = sv->y_dev = nullptr;
+    sv->dev_cap = 0;
+    if (hipMalloc((void**)&sv->x_dev, cap * 4) != hipSuccess || hipMalloc((void**)&sv->y_dev, cap * 4) != hipSuccess)
+      return taches::set_error(TACHES_ENOMEM, "serving: device staging of %zu floats", cap);
+    sv->dev_cap = cap;
+  }
+  return TACHES_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+taches_server* taches_server_create(taches_pool* pool, double fs, int32_t max_blocks_per_step, double warmup_s) {
+  if (!pool || !(fs > 0.0) || max_blocks_per_step < 1) {
+    taches::set_error(TACHES_EINVAL, "serving: bad pool, sample rate or block limit");
+    return nullptr;
+  }
+  taches_server* sv = new taches_server;
+  sv->pool = pool;
+  sv->fs = fs;
+  sv->max_blocks = max_blocks_per_step;
+  sv->warmup_s = warmup_s;
+  sv->t0 = std::chrono::steady_clock::now();
+  return sv;
+}
+
+int taches_server_destroy(taches_server* sv) {
+  if (!sv) return TACHES_OK;
+  (void)taches_pool_synchronize(sv->pool);
+  (void)hipHostFree(sv->x_pin);
+  (void)hipHostFree(sv->y_pin);
+  (void)hipFree(sv->x_dev);
+  (void)hipFree(sv->y_dev);
+  delete sv;
+  return TACHES_OK;
+}
+
+double taches_server_clock(const taches_server* sv) { return sv ? clock_s(sv) : -1.0; }
+
+int taches_server_add(taches_server* sv, taches_stream* s, int64_t tag, double start_s, int64_t n_in_blocks,
+                      int64_t n_total_blocks, const float* x_host, int64_t x_cstride, float* y_host, int64_t y_cstride,
+                      int32_t n_swaps, const double* swap_times_s, const float* const* swap_ir_dev,
+                      const int32_t* swap_len) {
+  if (!sv || !s) return taches::set_error(TACHES_EINVAL, "serving: NULL server or stream");
+  taches_info inf;
+  int rc = taches_get_info(s, &inf);
+  if (rc != TACHES_OK) return rc;
+  if (!taches::stream_in_pool(s, sv->pool)) return taches::set_error(TACHES_EINVAL, "serving: stream not attached to the pool");
+  if (find_tag(sv, tag, true)) return taches::set_error(TACHES_EINVAL, "serving: tag %lld already registered", (long long)tag);
+  if (n_in_blocks < 1 || n_total_blocks < n_in_blocks) return taches::set_error(TACHES_EINVAL, "serving: block counts");
+  if (sv->max_blocks > inf.max_blocks_per_call)
+    return taches::set_error(TACHES_EINVAL, "serving: stream takes %d blocks per call, the server %d",
+                             inf.max_blocks_per_call, sv->max_blocks);
+  const int64_t need = n_in_blocks * inf.block_size;
+  if (!x_host || x_cstride < need)
+    return taches::set_error(TACHES_EINVAL, "serving: input buffer shorter than the input blocks");
+  if (y_host && y_cstride < n_total_blocks * inf.block_size)
+    return taches::set_error(TACHES_EINVAL, "serving: output buffer shorter than the stream");
+  if (n_swaps < 0 || (n_swaps > 0 && (!swap_times_s || !swap_ir_dev || !swap_len)))
+    return taches::set_error(TACHES_EINVAL, "serving: swap arrays");
+  for (int i = 0; i < n_swaps; ++i) {
+    if (!swap_ir_dev[i] || swap_len[i] < 1 || swap_len[i] > inf.max_ir_len)
+      return taches::set_error(TACHES_EINVAL, "serving: swap %d IR", i);
+    if (i > 0 && swap_times_s[i] < swap_times_s[i - 1])
+      return taches::set_error(TACHES_EINVAL, "serving: swap times not ascending");
+  }
+  ServeStream r;
+  r.s = s;
+  r.tag = tag;
+  r.start_s = start_s;
+  r.B = inf.block_size;
+  r.C = inf.channels;
+  r.n_in = n_in_blocks;
+  r.n_total = n_total_blocks;
+  r.x = x_host;
+  r.x_cs = x_cstride;
+  r.y = y_host;
+  r.y_cs = y_cstride;
+  r.swap_t.assign(swap_times_s, swap_times_s + n_swaps);
+  r.swap_h.assign(swap_ir_dev, swap_ir_dev + n_swaps);
+  r.swap_L.assign(swap_len, swap_len + n_swaps);
+  sv->st.push_back(std::move(r));
+  return TACHES_OK;
+}
+
+int taches_server_tick(taches_server* sv, taches_server_tick_info* out) {
+  if (!sv) return taches::set_error(TACHES_EINVAL, "server is NULL");
+  taches_server_tick_info info{};
+  const double now = clock_s(sv);
+  info.now_s = now;
+  const double fs = sv->fs;
+  // ---- ranges: every arrived block of each stream, in order ----
+  sv->a_s.clear();
+  sv->a_n.clear();
+  sv->a_idx.clear();
+  sv->a_k0.clear();
+  sv->a_xoff.clear();
+  sv->a_yoff.clear();
+  size_t xf = 0, yf = 0;
+  for (size_t i = 0; i < sv->st.size(); ++i) {
+    ServeStream& r = sv->st[i];
+    int64_t arrived = (int64_t)std::floor((now - r.start_s) * fs / r.B);
+    arrived = std::min(std::max<int64_t>(arrived, 0), r.n_total);
+    if (arrived <= r.next) continue;
+    const int64_t k0 = r.next;
+    const bool is_in = k0 < r.n_in;
+    // IR changes due by the start of this range's first block apply to it
+    if (is_in) {
+      while (r.swap_next < r.swap_t.size() && r.swap_t[r.swap_next] <= (double)(k0 * r.B) / fs) {
+        int rc = taches_set_ir_device(r.s, r.swap_h[r.swap_next], r.swap_L[r.swap_next]);
+        if (rc != TACHES_OK) return rc;
+        r.swap_blocks.push_back(k0);
+        ++r.swap_next;
+      }
+    }
+    int64_t end = std::min<int64_t>(arrived, k0 + sv->max_blocks);
+    if (is_in) {
+      end = std::min(end, r.n_in);
+      if (r.swap_next < r.swap_t.size()) end = std::min(end, first_block_at(r.swap_t[r.swap_next], r.B, fs, k0 + 1));
+    }
+    const int32_t n = (int32_t)(end - k0);
+    sv->a_s.push_back(r.s);
+    sv->a_n.push_back(n);
+    sv->a_idx.push_back((int32_t)i);
+    sv->a_k0.push_back(k0);
+    const size_t len = (size_t)r.C * n * r.B;
+    sv->a_xoff.push_back(is_in ? (int64_t)xf : -1);
+    if (is_in) xf += len;
+    sv->a_yoff.push_back((int64_t)yf);
+    yf += len;
+  }
+  const size_t m = sv->a_s.size();
+  auto next_due = [&]() {
+    double t = HUGE_VAL;
+    for (const ServeStream& r : sv->st) t = std::min(t, r.start_s + (double)((r.next + 1) * r.B) / fs);
+    return t;
+  };
+  if (m == 0) {
+    info.next_due_s = next_due();
+    if (out) *out = info;
+    return TACHES_OK;
+  }
+  int rc = grow(sv, std::max(xf, yf));
+  if (rc != TACHES_OK) return rc;
+  // ---- gather the arrived input into pinned memory ----
+  for (size_t j = 0; j < m; ++j) {
+    if (sv->a_xoff[j] < 0) continue;
+    const ServeStream& r = sv->st[sv->a_idx[j]];
+    const size_t row = (size_t)sv->a_n[j] * r.B;
+    float* dst = sv->x_pin + sv->a_xoff[j];
+    for (int c = 0; c < r.C; ++c)
+      std::memcpy(dst + c * row, r.x + c * r.x_cs + sv->a_k0[j] * r.B, row * 4);
+  }
+  sv->a_x.resize(m);
+  sv->a_y.resize(m);
+  for (size_t j = 0; j < m; ++j) {
+    sv->a_x[j] = sv->a_xoff[j] >= 0 ? sv->x_dev + sv->a_xoff[j] : nullptr;
+    sv->a_y[j] = sv->y_dev + sv->a_yoff[j];
+  }
+  const hipStream_t hs = taches::pool_stream(sv->pool);
+  const double t_launch = clock_s(sv);
+  if (xf > 0) {
+    const hipError_t e = hipMemcpyAsync(sv->x_dev, sv->x_pin, xf * 4, hipMemcpyHostToDevice, hs);
+    if (e != hipSuccess) return taches::set_error(TACHES_EDEVICE, "serving: input copy: %s", hipGetErrorString(e));
+  }
+  rc = taches_pool_step(sv->pool, (int32_t)m, sv->a_s.data(), sv->a_x.data(), sv->a_y.data(), sv->a_n.data());
+  if (rc != TACHES_OK) return rc;
+  {
+    const hipError_t e = hipMemcpyAsync(sv->y_pin, sv->y_dev, yf * 4, hipMemcpyDeviceToHost, hs);
+    if (e != hipSuccess) return taches::set_error(TACHES_EDEVICE, "serving: output copy: %s", hipGetErrorString(e));
+    // the step is committed on the host: from here on, state advances even
+    // if the wait reports an error
+    for (size_t j = 0; j < m; ++j) sv->st[sv->a_idx[j]].next = sv->a_k0[j] + sv->a_n[j];
+    const hipError_t w = hipStreamSynchronize(hs);
+    if (w != hipSuccess) return taches::set_error(TACHES_EDEVICE, "serving: wait: %s", hipGetErrorString(w));
+  }
+  // ---- outputs to the streams' host buffers ----
+  for (size_t j = 0; j < m; ++j) {
+    const ServeStream& r = sv->st[sv->a_idx[j]];
+    if (!r.y) continue;
+    const size_t row = (size_t)sv->a_n[j] * r.B;
+    const float* src = sv->y_pin + sv->a_yoff[j];
+    for (int c = 0; c < r.C; ++c) std::memcpy(r.y + c * r.y_cs + sv->a_k0[j] * r.B, src + c * row, row * 4);
+  }
+  const double done = clock_s(sv);
+  // ---- records ----
+  int64_t blocks = 0, macs = 0;
+  for (size_t j = 0; j < m; ++j) {
+    const ServeStream& r = sv->st[sv->a_idx[j]];
+    const int32_t n = sv->a_n[j];
+    blocks += n;
+    if (sv->a_k0[j] < r.n_in) {
+      taches_info inf;
+      if (taches_get_info(r.s, &inf) == TACHES_OK) macs += (int64_t)n * r.B * inf.active_len * r.C;
+    }
+    const double per = (double)r.B / fs;
+    for (int32_t q = 0; q < n; ++q) {
+      const double arrival = r.start_s + (double)(sv->a_k0[j] + q + 1) * per;
+      if (arrival < sv->warmup_s) continue;
+      sv->lat_s.push_back((float)(done - arrival));
+      sv->lat_B.push_back(r.B);
+    }
+  }
+  // ---- finished streams leave the server (the caller detaches them) ----
+  for (size_t i = sv->st.size(); i-- > 0;) {
+    if (sv->st[i].next >= sv->st[i].n_total) {
+      sv->finished.push_back(sv->st[i].tag);
+      sv->done.push_back(std::move(sv->st[i]));
+      sv->st[i] = std::move(sv->st.back());
+      sv->st.pop_back();
+    }
+  }
+  info.next_due_s = next_due();
+  info.streams = (int32_t)m;
+  info.blocks = blocks;
+  info.done_s = done;
+  info.host_ms = (t_launch - now) * 1e3;
+  info.step_ms = (done - now) * 1e3;
+  sv->stats.ticks += 1;
+  sv->stats.blocks += blocks;
+  sv->stats.macs += macs;
+  sv->stats.busy_s += done - now;
+  sv->stats.max_blocks_in_a_range = std::max<int64_t>(
+      sv->stats.max_blocks_in_a_range, *std::max_element(sv->a_n.begin(), sv->a_n.end()));
+  sv->stats.bytes_in += (int64_t)xf * 4;
+  sv->stats.bytes_out += (int64_t)yf * 4;
+  if (out) *out = info;
+  return TACHES_OK;
+}
+
+int taches_server_take_finished(taches_server* sv, int64_t* tags, int32_t cap) {
+  if (!sv || (cap > 0 && !tags) || cap < 0) return taches::set_error(TACHES_EINVAL, "bad arguments");
+  const int32_t n = (int32_t)std::min<size_t>(cap, sv->finished.size());
+  std::copy(sv->finished.begin(), sv->finished.begin() + n, tags);
+  sv->finished.erase(sv->finished.begin(), sv->finished.begin() + n);
+  return n;
+}
+
+int taches_server_take_latencies(taches_server* sv, float* latency_s, int32_t* block_size, int32_t cap) {
+  if (!sv || cap < 0 || (cap > 0 && (!latency_s || !block_size))) return taches::set_error(TACHES_EINVAL, "bad arguments");
+  const int32_t n = (int32_t)std::min<size_t>(cap, sv->lat_s.size());
+  std::copy(sv->lat_s.begin(), sv->lat_s.begin() + n, latency_s);
+  std::copy(sv->lat_B.begin(), sv->lat_B.begin() + n, block_size);
+  sv->lat_s.erase(sv->lat_s.begin(), sv->lat_s.begin() + n);
+  sv->lat_B.erase(sv->lat_B.begin(), sv->lat_B.begin() + n);
+  return n;
+}
+
+int taches_server_stream_state(taches_server* sv, int64_t tag, int64_t* next_block, int64_t* swap_blocks, int32_t cap) {
+  if (!sv || !next_block || cap < 0 || (cap > 0 && !swap_blocks)) return taches::set_error(TACHES_EINVAL, "bad arguments");
+  const ServeStream* r = find_tag(sv, tag, true);
+  if (!r) return taches::set_error(TACHES_EINVAL, "serving: tag %lld not registered", (long long)tag);
+  *next_block = r->next;
+  const int32_t n = (int32_t)std::min<size_t>(cap, r->swap_blocks.size());
+  std::copy(r->swap_blocks.begin(), r->swap_blocks.begin() + n, swap_blocks);
+  return (int)r->swap_blocks.size();
+}
+
+int taches_server_get_stats(const taches_server* sv, taches_server_stats* out) {
+  if (!sv || !out) return taches::set_error(TACHES_EINVAL, "bad arguments");
+  *out = sv->stats;
+  out->streams = (int32_t)sv->st.size();
+  return TACHES_OK;
+}
+
+}  // extern "C"

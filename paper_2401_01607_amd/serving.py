@@ -367,6 +367,16 @@ class Scheduler:
         return max(min(cands), self._last_step_s + self.min_tick_s)
 
 
+def tail_for(T, req, precision: int) -> int:
+    """The tail the library's AUTO rule gives a request's own IR length
+    (streams are opened with a longer capacity class, on which AUTO would
+    pick FP64 for some IRs that do not need it)."""
+    cfg = T.taches_config_default(req.block, req.ir_len)
+    cfg.channels = req.channels
+    cfg.precision = precision
+    return T.TACHES_TAIL_FP64 if T.taches_tail_is_fp64(cfg) == 1 else T.TACHES_TAIL_FP32
+
+
 class GpuExecutor:
     """Runs the scheduler's steps on the library's pool.
 
@@ -448,14 +458,7 @@ class GpuExecutor:
         return self.bank[:req.channels, off:off + self.n_input_blocks(req) * req.block]
 
     def tail_for(self, req) -> int:
-        """The tail the library's AUTO rule gives the request's own IR length
-        (streams are opened with the longer capacity class, so AUTO on their
-        max_ir_len would pick FP64 for some IRs that do not need it)."""
-        T = self.T
-        cfg = T.taches_config_default(req.block, req.ir_len)
-        cfg.channels = req.channels
-        cfg.precision = self.precision
-        return T.TACHES_TAIL_FP64 if T.taches_tail_is_fp64(cfg) == 1 else T.TACHES_TAIL_FP32
+        return tail_for(self.T, req, self.precision)
 
     def admit(self, req) -> int:
         T = self.T
@@ -580,6 +583,234 @@ class GpuExecutor:
 
     def close(self):
         for s, *_ in self.live.values():
+            self.pool.detach(s)
+            s.close()
+        self.live.clear()
+        for lst in self.free.values():
+            for s in lst:
+                s.close()
+        self.free.clear()
+        self.pool.close()
+
+
+class RealtimeServer:
+    """Serving with one library call per tick (taches_server_tick).
+
+    Python keeps what happens per request: FIFO admission when a stream
+    slot is free and the stream's device bytes fit the HBM budget (streams
+    recycled as in GpuExecutor), registration of the request's host input,
+    output buffer and IR-change schedule with the library's server, and
+    retirement of finished streams.  Everything per tick (which blocks
+    have arrived, IR changes due, the ranges of blocks, gathering the
+    arrived input into pinned memory, the host-to-device copy, the pool
+    step, the device-to-host copy of every output block, latency records)
+    runs in one library call.
+
+    Input audio lives in host memory: a seeded two-channel noise bank,
+    planar [2][70 s]; request r reads channels [0, C) from a seeded offset.
+    IR version v of request r is the first L taps of row (r.seed + v) mod NB
+    of a device bank of flat white-noise IRs (the paper's IR shape).
+    Outputs of requests listed in keep_outputs are written to host arrays;
+    the others are copied back and dropped."""
+
+    BANK_SECONDS = 70.0
+
+    def __init__(self, requests, max_streams: int, hbm_budget_bytes: int, precision: int = 0,
+                 use_graph: bool = True, ir_bank: int = 16, max_ir_len: int = 262_144, seed: int = 9,
+                 keep_outputs=(), max_blocks_per_step: int = 64, warmup_s: float = 0.0):
+        import torch
+        from . import taches as T
+        self.T, self.torch = T, torch
+        self.pending = deque(sorted(requests, key=lambda r: r.arrival_s))
+        self.queue: deque = deque()
+        self.pool = T.Pool(max_streams, hbm_budget_bytes, use_graph=use_graph)
+        self.sv = T.taches_server_create(self.pool.h, float(W.FS), max_blocks_per_step, warmup_s)
+        self.precision = precision
+        self.max_blocks_per_step = max_blocks_per_step
+        self.warmup_s = warmup_s
+        n = int(self.BANK_SECONDS * W.FS)
+        self.bank = np.stack([W.signal_gauss(n, seed * 100 + c) for c in range(2)])
+        self.bank_len = n
+        self.irbank = torch.from_numpy(np.stack([W.impulse_response(max_ir_len, seed * 1000 + k, decay=0.0)
+                                                 for k in range(ir_bank)])).cuda()
+        self.max_ir_len = max_ir_len
+        self.max_streams = max_streams
+        self.budget = hbm_budget_bytes
+        self.keep = set(keep_outputs)
+        self.kept: dict = {}         # rid -> host output array
+        self.free: dict = {}         # recycled streams by (B, C, IR class, tail)
+        self.idle_bytes = 0
+        self.live: dict = {}         # rid -> (stream, key, req)
+        self.req_by_rid = {r.rid: r for r in requests}
+        self.stats = Stats()
+        self.lat, self.lat_b = [], []
+        self.refused = 0
+
+    # -- requests ------------------------------------------------------------
+    def ir(self, req, version: int):
+        return self.irbank[(req.seed + version) % self.irbank.shape[0], :req.ir_len]
+
+    @staticmethod
+    def n_input_blocks(req) -> int:
+        return max(1, math.ceil(req.n_samples() / req.block))
+
+    def input_offset(self, req) -> int:
+        span = self.n_input_blocks(req) * req.block
+        return ((req.seed * 7919) % ((self.bank_len - span) // 64 + 1)) * 64
+
+    def input_signal(self, req) -> np.ndarray:
+        off = self.input_offset(req)
+        return self.bank[:req.channels, off:off + self.n_input_blocks(req) * req.block]
+
+    def tail_for(self, req) -> int:
+        return tail_for(self.T, req, self.precision)
+
+    @staticmethod
+    def ir_class(L: int) -> int:
+        return GpuExecutor.ir_class(L)
+
+    def _open(self, req):
+        T = self.T
+        tail = self.tail_for(req)
+        key = (req.block, req.channels, min(GpuExecutor.ir_class(req.ir_len), self.max_ir_len), tail)
+        lst = self.free.get(key)
+        if lst:
+            s = lst.pop()
+            self.idle_bytes -= s.info().device_bytes
+            return s, key
+        cfg = T.taches_config_default(req.block, key[2])
+        cfg.channels = req.channels
+        cfg.max_blocks_per_call = self.max_blocks_per_step
+        cfg.precision = self.precision
+        cfg.tail = tail
+        need = T.taches_bytes_for(cfg)
+        used = self.pool.info().used_bytes
+        while used + self.idle_bytes + need > self.budget and self.idle_bytes > 0:
+            k_big = max((k for k in self.free if self.free[k]), key=lambda k: k[2])
+            victim = self.free[k_big].pop()
+            self.idle_bytes -= victim.info().device_bytes
+            victim.close()
+        if used + self.idle_bytes + need > self.budget:
+            raise AdmissionRefused("budget")
+        return T.Stream(req.block, key[2], channels=req.channels, max_blocks_per_call=self.max_blocks_per_step,
+                        precision=self.precision, tail=tail), key
+
+    def _recycle(self, s, key):
+        s.reset()
+        self.free.setdefault(key, []).append(s)
+        self.idle_bytes += s.info().device_bytes
+
+    def _admit(self, now: float) -> None:
+        T = self.T
+        while self.pending and self.pending[0].arrival_s <= now:
+            self.queue.append(self.pending.popleft())
+        while self.queue:
+            req = self.queue[0]
+            if len(self.live) >= self.max_streams:
+                self.refused += 1
+                return
+            try:
+                s, key = self._open(req)
+            except AdmissionRefused:
+                self.refused += 1
+                return
+            if self.pool.attach(s) != T.TACHES_OK:
+                self._recycle(s, key)
+                self.refused += 1
+                return
+            self.queue.popleft()
+            s.set_ir(self.ir(req, 0))
+            n_in = self.n_input_blocks(req)
+            n_total = n_in + math.ceil((req.ir_len - 1) / req.block)
+            y = None
+            if req.rid in self.keep:
+                y = np.zeros((req.channels, n_total * req.block), np.float32)
+                self.kept[req.rid] = y
+            swaps = [self.ir(req, v + 1) for v in range(len(req.swap_times_s))]
+            _ = T._check(T.taches_server_add(self.sv, s.h, req.rid, now, n_in, n_total, self.input_signal(req), y,
+                                             req.swap_times_s, swaps), "taches_server_add")
+            self.live[req.rid] = (s, key, req)
+            self.stats.admitted += 1
+            if req.arrival_s >= self.warmup_s:
+                self.stats.queue_waits_s.append(now - req.arrival_s)
+        self.stats.max_active = max(self.stats.max_active, len(self.live))
+
+    def _retire(self) -> None:
+        for rid in self.T.taches_server_take_finished(self.sv).tolist():
+            s, key, req = self.live.pop(rid)
+            self.pool.detach(s)
+            self._recycle(s, key)
+            self.stats.completed += 1
+
+    def _drain_records(self) -> None:
+        lat, bs = self.T.taches_server_take_latencies(self.sv)
+        if lat.size:
+            self.lat.append(lat)
+            self.lat_b.append(bs)
+
+    # -- driver ----------------------------------------------------------------
+    def run_realtime(self, duration_s: float, sleep=time.sleep) -> dict:
+        T = self.T
+        sv = self.sv
+        last_drain = 0.0
+        while True:
+            now = T.taches_server_clock(sv)
+            if now >= duration_s:
+                break
+            self._admit(now)
+            tk = T.taches_server_tick(sv)
+            if tk.streams:
+                self._retire()
+            else:
+                nxt = tk.next_due_s
+                if self.pending:
+                    nxt = min(nxt, self.pending[0].arrival_s)
+                wait = min(nxt, duration_s) - T.taches_server_clock(sv)
+                if wait > 0:
+                    sleep(min(wait, 0.0005))
+            if now - last_drain > 1.0:
+                self._drain_records()
+                last_drain = now
+        wall = T.taches_server_clock(sv)
+        self._drain_records()
+        return self.summary(wall)
+
+    def summary(self, wall_s: float) -> dict:
+        T = self.T
+        st = T.taches_server_get_stats(self.sv)
+        self.stats.steps = int(st.ticks)
+        self.stats.blocks = int(st.blocks)
+        self.stats.macs = int(st.macs)
+        self.stats.busy_s = float(st.busy_s)
+        self.stats.max_range = int(st.max_blocks_in_a_range)
+        if self.lat:
+            lat = np.concatenate(self.lat).astype(np.float64)
+            bs = np.concatenate(self.lat_b).astype(np.int64)
+            self.stats._lat, self.stats._dl, self.stats._bs = [lat], [bs / W.FS], [bs]
+        out = self.stats.summary(wall_s)
+        out["refused_attempts"] = self.refused
+        out["bytes_h2d"] = int(st.bytes_in)
+        out["bytes_d2h"] = int(st.bytes_out)
+        out["gpu_busy_fraction"] = round(self.pool.info().device_ms_total / 1e3 / wall_s, 3) if wall_s > 0 else 0.0
+        return out
+
+    def kept_outputs(self, rid):
+        """(input [C][n_in*B], outputs so far [C][blocks done*B], blocks of the
+        applied IR swaps) of a request listed in keep_outputs; None if it was
+        never admitted."""
+        if rid not in self.kept:
+            return None
+        req = self.req_by_rid[rid]
+        nxt, swaps = self.T.taches_server_stream_state(self.sv, rid)
+        y = self.kept[rid][:, :nxt * req.block]
+        return np.ascontiguousarray(self.input_signal(req)), y, swaps
+
+    def close(self):
+        T = self.T
+        if self.sv:
+            T.taches_server_destroy(self.sv)
+            self.sv = None
+        for s, _, _ in self.live.values():
             self.pool.detach(s)
             s.close()
         self.live.clear()

@@ -57,6 +57,19 @@ class taches_pool_info(ctypes.Structure):
                 ("last_device_ms", ctypes.c_double), ("device_ms_total", ctypes.c_double)]
 
 
+class taches_server_tick_info(ctypes.Structure):
+    _fields_ = [("streams", ctypes.c_int32), ("pad_", ctypes.c_int32), ("blocks", ctypes.c_int64),
+                ("now_s", ctypes.c_double), ("done_s", ctypes.c_double), ("host_ms", ctypes.c_double),
+                ("step_ms", ctypes.c_double), ("next_due_s", ctypes.c_double)]
+
+
+class taches_server_stats(ctypes.Structure):
+    _fields_ = [("ticks", ctypes.c_int64), ("blocks", ctypes.c_int64), ("macs", ctypes.c_int64),
+                ("max_blocks_in_a_range", ctypes.c_int64), ("bytes_in", ctypes.c_int64),
+                ("bytes_out", ctypes.c_int64), ("busy_s", ctypes.c_double), ("streams", ctypes.c_int32),
+                ("pad_", ctypes.c_int32)]
+
+
 _vp, _i32, _i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
 _P = ctypes.POINTER
 _SIGS = {
@@ -97,6 +110,16 @@ _SIGS = {
     "taches_fp32_fma_ceiling": (ctypes.c_int, [_i32, _P(ctypes.c_double)]),
     "taches_convolve": (ctypes.c_int, [_vp, _i64, _i32, _vp, _i32, _vp, _i32, _i32, _i32, _vp]),
     "taches_convolve_noalloc": (ctypes.c_int, [_vp, _i64, _i32, _vp, _i32, _vp, _i32, _i32, _vp]),
+    "taches_server_create": (_vp, [_vp, ctypes.c_double, _i32, ctypes.c_double]),
+    "taches_server_destroy": (ctypes.c_int, [_vp]),
+    "taches_server_clock": (ctypes.c_double, [_vp]),
+    "taches_server_add": (ctypes.c_int, [_vp, _vp, _i64, ctypes.c_double, _i64, _i64, _vp, _i64, _vp, _i64, _i32,
+                                         _vp, _vp, _vp]),
+    "taches_server_tick": (ctypes.c_int, [_vp, _P(taches_server_tick_info)]),
+    "taches_server_take_finished": (ctypes.c_int, [_vp, _vp, _i32]),
+    "taches_server_take_latencies": (ctypes.c_int, [_vp, _vp, _vp, _i32]),
+    "taches_server_stream_state": (ctypes.c_int, [_vp, _i64, _P(_i64), _vp, _i32]),
+    "taches_server_get_stats": (ctypes.c_int, [_vp, _P(taches_server_stats)]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(lib, _name)
@@ -476,6 +499,91 @@ class Stream:
                 self.h = None
         except Exception:
             pass
+
+
+# ---- serving tick ------------------------------------------------------------
+
+def taches_server_create(pool, fs: float, max_blocks_per_step: int, warmup_s: float = 0.0):
+    h = lib.taches_server_create(pool, fs, max_blocks_per_step, warmup_s)
+    if not h:
+        raise TachesError(TACHES_EINVAL, "taches_server_create")
+    return h
+
+
+def taches_server_destroy(sv) -> int:
+    return lib.taches_server_destroy(sv)
+
+
+def taches_server_clock(sv) -> float:
+    return float(lib.taches_server_clock(sv))
+
+
+def taches_server_add(sv, stream, tag: int, start_s: float, n_in_blocks: int, n_total_blocks: int,
+                      x_host: np.ndarray, y_host, swap_times_s=(), swap_irs=()) -> int:
+    """x_host: [C][x_cstride] float32 host array (kept alive by the caller);
+    y_host: [C][y_cstride] float32 host array or None; swap_irs: device
+    tensors (kept alive by the caller until applied)."""
+    x_host = np.atleast_2d(x_host)
+    if x_host.dtype != np.float32 or x_host.strides[1] != 4 or x_host.strides[0] % 4:
+        raise TypeError("x_host must be a float32 array with contiguous rows")
+    x_cs = x_host.shape[1] if x_host.shape[0] == 1 else x_host.strides[0] // 4
+    y_ptr, y_cs = None, 0
+    if y_host is not None:
+        y_host = np.atleast_2d(y_host)
+        if y_host.dtype != np.float32 or not y_host.flags.c_contiguous:
+            raise TypeError("y_host must be a C-contiguous float32 array")
+        y_ptr, y_cs = _host_ptr(y_host), y_host.shape[1]
+    n = len(swap_times_s)
+    if len(swap_irs) != n:
+        raise ValueError("one IR per swap time")
+    t = np.ascontiguousarray(swap_times_s, np.float64)
+    hp = np.array([ir.data_ptr() for ir in swap_irs], np.uint64)
+    hl = np.array([ir.numel() for ir in swap_irs], np.int32)
+    return lib.taches_server_add(sv, stream, tag, start_s, n_in_blocks, n_total_blocks, _host_ptr(x_host),
+                                 x_cs, y_ptr, y_cs, n, _host_ptr(t) if n else None,
+                                 _host_ptr(hp) if n else None, _host_ptr(hl) if n else None)
+
+
+def taches_server_tick(sv) -> taches_server_tick_info:
+    out = taches_server_tick_info()
+    _check(lib.taches_server_tick(sv, ctypes.byref(out)), "taches_server_tick")
+    return out
+
+
+def taches_server_take_finished(sv, cap: int = 4096) -> np.ndarray:
+    buf = np.zeros(cap, np.int64)
+    n = lib.taches_server_take_finished(sv, _host_ptr(buf), cap)
+    _check(min(n, 0), "taches_server_take_finished")
+    return buf[:n]
+
+
+def taches_server_take_latencies(sv, cap: int = 1 << 20):
+    """(latencies in seconds, block sizes) recorded since the last call."""
+    lat, bs = [], []
+    while True:
+        a = np.zeros(cap, np.float32)
+        b = np.zeros(cap, np.int32)
+        n = lib.taches_server_take_latencies(sv, _host_ptr(a), _host_ptr(b), cap)
+        _check(min(n, 0), "taches_server_take_latencies")
+        lat.append(a[:n])
+        bs.append(b[:n])
+        if n < cap:
+            return np.concatenate(lat), np.concatenate(bs)
+
+
+def taches_server_stream_state(sv, tag: int, cap: int = 4096):
+    """(next block, blocks at which the IR changes took effect)."""
+    nxt = ctypes.c_int64()
+    buf = np.zeros(cap, np.int64)
+    n = lib.taches_server_stream_state(sv, tag, ctypes.byref(nxt), _host_ptr(buf), cap)
+    _check(min(n, 0), "taches_server_stream_state")
+    return int(nxt.value), buf[:min(n, cap)].tolist()
+
+
+def taches_server_get_stats(sv) -> taches_server_stats:
+    out = taches_server_stats()
+    _check(lib.taches_server_get_stats(sv, ctypes.byref(out)), "taches_server_get_stats")
+    return out
 
 
 class Pool:

@@ -82,7 +82,8 @@ def test_binding_structs_match_the_header_layout(tmp_path):
     if cc is None:
         pytest.skip("no host C compiler")
     structs = {"taches_config": T.taches_config, "taches_info": T.taches_info,
-               "taches_pool_info": T.taches_pool_info}
+               "taches_pool_info": T.taches_pool_info, "taches_server_tick_info": T.taches_server_tick_info,
+               "taches_server_stats": T.taches_server_stats}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "taches.h"', "int main(void) {"]
     for name, cls in structs.items():
         lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')

@@ -18,7 +18,8 @@ def _replay_alone(ex, req, hist, x_in, precision=0):
     import torch
     T = binding()
     B, C = req.block, req.channels
-    s = T.Stream(B, ex.ir_class(req.ir_len), channels=C, max_blocks_per_call=1, precision=precision)
+    s = T.Stream(B, ex.ir_class(req.ir_len), channels=C, max_blocks_per_call=1, precision=precision,
+                 tail=ex.tail_for(req))
     s.set_ir(ex.ir(req, 0))
     swaps = dict((b, v + 1) for v, b in enumerate(hist.swap_blocks))
     outs = []
@@ -164,3 +165,95 @@ def test_config5_full_load_sampled_parity():
         checked += 1
     assert checked >= 3
     ex.close()
+
+
+# ---- serving with one library call per tick (taches_server_tick) ----------
+
+def _swap_rule_blocks(req):
+    """Blocks at which a request's IR changes apply: the first block that
+    starts at or after each change time, within the input blocks."""
+    n_in = max(1, math.ceil(req.n_samples() / req.block))
+    out = []
+    for t in req.swap_times_s:
+        k = 0 if t <= 0 else math.ceil(t * 48000 / req.block - 1e-9)
+        while k > 0 and (k - 1) * req.block / 48000 >= t:
+            k -= 1
+        while k * req.block / 48000 < t:
+            k += 1
+        if k < n_in:
+            out.append(k)
+    return out
+
+
+def _server_check(precision, seed, tol_max):
+    from paper_2401_01607_amd.serving import RealtimeServer
+    T = binding()
+    reqs = W.config5_requests(horizon_s=1.0, rate_hz=40.0, seed=seed, dur=(0.2, 0.5), lrange=(256, 8192),
+                              swap_rate_hz=6.0)
+    keep = [r.rid for r in reqs[::3]]
+    srv = RealtimeServer(reqs, max_streams=16, hbm_budget_bytes=1 << 34, keep_outputs=keep, ir_bank=8,
+                         max_ir_len=8192, precision=precision)
+    st = srv.run_realtime(1.0 + 0.5 + 8192 / 48000 + 1.5)
+    assert st["completed"] == st["admitted"] == len(reqs)
+    assert st["steps"] > 0 and "latency_ms_p99" in st and st["bytes_h2d"] > 0 and st["bytes_d2h"] > 0
+    n_swapped = 0
+    for i, rid in enumerate(keep):
+        req = next(r for r in reqs if r.rid == rid)
+        x, y_mix, swaps = srv.kept_outputs(rid)
+        assert swaps == _swap_rule_blocks(req)
+        n_swapped += len(swaps)
+        n_in = max(1, math.ceil(req.n_samples() / req.block))
+        n_total = n_in + math.ceil((req.ir_len - 1) / req.block)
+        assert y_mix.shape == (req.channels, n_total * req.block)
+        B, C = req.block, req.channels
+        x_in = x.reshape(C, n_in, B).transpose(1, 0, 2)
+
+        class Hist:
+            pass
+        hist = Hist()
+        hist.n_in, hist.n_total, hist.swap_blocks = n_in, n_total, swaps
+        y_alone = _replay_alone(srv, req, hist, x_in, precision=precision)
+        assert np.array_equal(y_mix, y_alone.transpose(1, 0, 2).reshape(C, -1)), f"request {rid}"
+        if i < 2:
+            irs = [srv.ir(req, v).cpu().numpy() for v in range(len(swaps) + 1)]
+            sched = [(0, 0)] + [(b, v + 1) for v, b in enumerate(swaps)]
+            ref = oracle_run(x, irs, sched, B, req.ir_len, n_total)
+            for c in range(C):
+                assert rel_err(y_mix[c], ref[c]) <= tol_max
+    assert n_swapped > 0
+    srv.close()
+
+
+def test_server_tick_mix_equals_alone_and_oracle():
+    """One library call per tick (input gathered from host memory and copied
+    in, outputs copied back): each kept stream equals the same stream run
+    alone bit for bit and the FP64 oracle within 1e-5 * RMS, and its IR
+    changes apply at the first block starting at or after each change."""
+    _server_check(0, 177, 1e-5)
+
+
+def test_server_tick_split_bf16():
+    T = binding()
+    _server_check(T.TACHES_PREC_SPLIT_BF16, 179, 1e-4)
+
+
+def test_server_tick_small_budget_queues():
+    from paper_2401_01607_amd.serving import GpuExecutor, RealtimeServer
+    T = binding()
+    reqs = W.config5_requests(horizon_s=0.3, rate_hz=30.0, seed=78, dur=(0.2, 0.3), lrange=(4096, 4096),
+                              swap_rate_hz=0.0)
+
+    def nbytes(B, C):
+        cfg = T.taches_config_default(B, 4096)
+        cfg.channels = C
+        cfg.max_blocks_per_call = 64
+        return T.taches_bytes_for(cfg)
+    per_max = max(nbytes(r.block, r.channels) for r in reqs)
+    per_min = min(nbytes(r.block, r.channels) for r in reqs)
+    budget = int(2.2 * per_max)
+    srv = RealtimeServer(reqs, max_streams=64, hbm_budget_bytes=budget, ir_bank=4, max_ir_len=4096)
+    st = srv.run_realtime(4.0)
+    assert st["max_active_streams"] <= budget // per_min
+    assert st["completed"] == len(reqs)
+    assert st["refused_attempts"] > 0
+    srv.close()
