@@ -387,7 +387,11 @@ typedef struct taches_server_stats {
   int64_t macs;                   /* direct-equivalent MACs of the input blocks */
   int64_t max_blocks_in_a_range;  /* most blocks of one stream in one step */
   int64_t bytes_in, bytes_out;    /* host-to-device input and device-to-host output bytes */
-  double busy_s;                  /* summed duration of the ticks that ran a step */
+  double busy_s;                  /* summed duration of the ticks that ran a step, split into: */
+  double gather_s;                /*   ranges, IR changes and input gather on the host */
+  double launch_s;                /*   input copy and pool step enqueued (step planning included) */
+  double wait_s;                  /*   waiting for the device (step and output copy) */
+  double scatter_s;               /*   outputs to the streams' host buffers, latency records */
   int32_t streams;                /* streams registered and not finished */
   int32_t pad_;
 } taches_server_stats;

@@ -285,6 +285,7 @@ int taches_server_tick(taches_server* sv, taches_server_tick_info* out) {
   }
   rc = taches_pool_step(sv->pool, (int32_t)m, sv->a_s.data(), sv->a_x.data(), sv->a_y.data(), sv->a_n.data());
   if (rc != TACHES_OK) return rc;
+  const double t_queued = clock_s(sv);
   {
     const hipError_t e = hipMemcpyAsync(sv->y_pin, sv->y_dev, yf * 4, hipMemcpyDeviceToHost, hs);
     if (e != hipSuccess) return taches::set_error(TACHES_EDEVICE, "serving: output copy: %s", hipGetErrorString(e));
@@ -294,6 +295,7 @@ int taches_server_tick(taches_server* sv, taches_server_tick_info* out) {
     const hipError_t w = hipStreamSynchronize(hs);
     if (w != hipSuccess) return taches::set_error(TACHES_EDEVICE, "serving: wait: %s", hipGetErrorString(w));
   }
+  const double t_back = clock_s(sv);
   // ---- outputs to the streams' host buffers ----
   for (size_t j = 0; j < m; ++j) {
     const ServeStream& r = sv->st[sv->a_idx[j]];
@@ -340,6 +342,10 @@ int taches_server_tick(taches_server* sv, taches_server_tick_info* out) {
   sv->stats.blocks += blocks;
   sv->stats.macs += macs;
   sv->stats.busy_s += done - now;
+  sv->stats.gather_s += t_launch - now;
+  sv->stats.launch_s += t_queued - t_launch;
+  sv->stats.wait_s += t_back - t_queued;
+  sv->stats.scatter_s += done - t_back;
   sv->stats.max_blocks_in_a_range = std::max<int64_t>(
       sv->stats.max_blocks_in_a_range, *std::max_element(sv->a_n.begin(), sv->a_n.end()));
   sv->stats.bytes_in += (int64_t)xf * 4;

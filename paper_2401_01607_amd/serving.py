@@ -792,6 +792,9 @@ class RealtimeServer:
         out["bytes_h2d"] = int(st.bytes_in)
         out["bytes_d2h"] = int(st.bytes_out)
         out["gpu_busy_fraction"] = round(self.pool.info().device_ms_total / 1e3 / wall_s, 3) if wall_s > 0 else 0.0
+        if st.ticks:
+            out["tick_ms_mean"] = {k: round(getattr(st, k + "_s") / st.ticks * 1e3, 4)
+                                   for k in ("busy", "gather", "launch", "wait", "scatter")}
         return out
 
     def kept_outputs(self, rid):

@@ -66,8 +66,9 @@ class taches_server_tick_info(ctypes.Structure):
 class taches_server_stats(ctypes.Structure):
     _fields_ = [("ticks", ctypes.c_int64), ("blocks", ctypes.c_int64), ("macs", ctypes.c_int64),
                 ("max_blocks_in_a_range", ctypes.c_int64), ("bytes_in", ctypes.c_int64),
-                ("bytes_out", ctypes.c_int64), ("busy_s", ctypes.c_double), ("streams", ctypes.c_int32),
-                ("pad_", ctypes.c_int32)]
+                ("bytes_out", ctypes.c_int64), ("busy_s", ctypes.c_double), ("gather_s", ctypes.c_double),
+                ("launch_s", ctypes.c_double), ("wait_s", ctypes.c_double), ("scatter_s", ctypes.c_double),
+                ("streams", ctypes.c_int32), ("pad_", ctypes.c_int32)]
 
 
 _vp, _i32, _i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
