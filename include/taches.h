@@ -357,12 +357,13 @@ int taches_pool_get_info(const taches_pool* p, taches_pool_info* out);
  * pool step: the arrived input is gathered from each stream's host buffer
  * into pinned memory and copied to the device in one transfer; every output
  * block is copied back in one transfer and written to the stream's host
- * buffer (if any) before the call returns.  An IR change scheduled at time
+ * buffer (if any) when the step completes (during the next tick or flush).  An IR change scheduled at time
  * t (seconds from the stream's start) applies to the first block that
  * starts at or after t (the IR is replaced for the next samples, Abstract
- * and Section 6).  Latency of a block = the tick's completion time (outputs
- * in host memory) minus the arrival time of its last sample; the deadline
- * is one block period.  The server does not own streams: register an
+ * and Section 6).  Latency of a block = the time its step's output copy
+ * completed (outputs in host memory; a device event placed on the server
+ * clock) minus the arrival time of its last sample; the deadline is one
+ * block period.  The server does not own streams: register an
  * attached stream, and detach it after its tag is reported finished.  A
  * server is not thread-safe.  After TACHES_EDEVICE from a tick, destroy the
  * server and its pool. */
@@ -374,7 +375,7 @@ typedef struct taches_server_tick_info {
   int32_t pad_;
   int64_t blocks;   /* blocks processed */
   double now_s;     /* server clock when the tick started */
-  double done_s;    /* server clock when every output block was in host memory */
+  double done_s;    /* server clock when the tick returned (the previous step completed) */
   double host_ms;   /* host work before the first transfer (ranges, IR changes, input gather) */
   double step_ms;   /* the whole tick */
   double next_due_s;/* server clock at which the next block of a registered
@@ -422,10 +423,17 @@ int taches_server_add(taches_server* sv, taches_stream* s, int64_t tag, double s
                       int32_t n_swaps, const double* swap_times_s, const float* const* swap_ir_dev,
                       const int32_t* swap_len);
 
-/* One tick at the current server clock: runs one step if any block is due,
- * waits for it and fills *out (may be NULL).  Streams whose last block was
- * processed leave the server (see taches_server_take_finished). */
+/* One tick at the current server clock: if any block is due, enqueues its
+ * step (input copy, pool step, output copy) on the pool's stream; then waits
+ * for the previous tick's step, hands its outputs to the host buffers and
+ * records its latencies (so the host prepares step k + 1 while the device
+ * runs step k).  Fills *out (may be NULL).  A stream whose last block has
+ * been enqueued no longer takes part; it is reported by
+ * taches_server_take_finished once that step has completed. */
 int taches_server_tick(taches_server* sv, taches_server_tick_info* out);
+
+/* Wait for the step in flight (if any) and complete it as a tick would. */
+int taches_server_flush(taches_server* sv);
 
 /* Tags of streams that finished since the last call (at most cap, oldest
  * first); returns how many were written. */

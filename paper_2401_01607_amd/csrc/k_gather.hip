@@ -24,6 +24,8 @@
 // copy of h pads every R-float row so that the lanes' 16-byte window reads
 // fall in distinct banks; each group of R input samples starts on a 16-byte
 // boundary.
+#include <algorithm>
+
 #include "taches_internal.h"
 
 namespace taches {
@@ -690,21 +692,33 @@ hipError_t launch_gather(const GatherCall& call, bool tail_fp64, int r, int w, h
   }
 }
 
-template <int R>
-int batched_occupancy(bool mixed) {
-  int n = 0;
-  const hipError_t e =
-      mixed ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gather_batched<R, true>, 64, lds_bytes<R, 1>())
-            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gather_batched<R, false>, 64, lds_bytes<R, 1>());
-  return (e == hipSuccess && n > 0) ? n : 8;
+// Resident one-wave workgroups per CU, from the register count and LDS use
+// the runtime reports for the kernel: each SIMD holds 512 registers per
+// lane (in granules of 8) and at most 8 waves; a CU has 4 SIMDs and 160 KB
+// of LDS.  Computed once per kernel (the planner asks on every step).
+template <int R, bool MIXED>
+int batched_occupancy() {
+  static int cached = 0;
+  if (cached) return cached;
+  hipFuncAttributes a{};
+  int per_cu = 8;
+  if (hipFuncGetAttributes(&a, reinterpret_cast<const void*>(k_gather_batched<R, MIXED>)) == hipSuccess &&
+      a.numRegs > 0) {
+    const int regs = (a.numRegs + 7) / 8 * 8;
+    const int waves_simd = std::min(8, 512 / regs);
+    const int lds = lds_bytes<R, 1>() + (int)a.sharedSizeBytes;
+    per_cu = std::max(1, std::min(4 * waves_simd, lds > 0 ? 163840 / lds : 32));
+  }
+  cached = per_cu;
+  return per_cu;
 }
 
 int gather_batched_waves_per_cu(int r, bool mixed) {
   switch (r) {
-    case 4: return batched_occupancy<4>(mixed);
-    case 8: return batched_occupancy<8>(mixed);
-    case 12: return batched_occupancy<12>(mixed);
-    case 16: return batched_occupancy<16>(mixed);
+    case 4: return mixed ? batched_occupancy<4, true>() : batched_occupancy<4, false>();
+    case 8: return mixed ? batched_occupancy<8, true>() : batched_occupancy<8, false>();
+    case 12: return mixed ? batched_occupancy<12, true>() : batched_occupancy<12, false>();
+    case 16: return mixed ? batched_occupancy<16, true>() : batched_occupancy<16, false>();
     default: return 8;
   }
 }

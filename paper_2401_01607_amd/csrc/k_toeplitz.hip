@@ -131,11 +131,20 @@ __global__ __launch_bounds__(256) void k_split_input_batched(const GatherCall* c
   }
 }
 
-__device__ __forceinline__ int xcd_remap(int id, int n) {
-  const int x = id & 7;
-  const int k = id >> 3;
-  const int q = n >> 3, rem = n & 7;
-  return x * q + (x < rem ? x : rem) + k;
+// Launch order of the output tiles of one call: the middle tile first, then
+// alternately right and left of it.  Tile work follows the number of input
+// samples that reach the tile, which rises from the first tile, is flat
+// where every sample reaches and falls to the last, so this order launches
+// the heaviest tiles first and leaves the light ones to fill the end.
+// Workgroups go to the 8 XCDs round-robin in launch order, so every XCD
+// gets the same mix of heavy and light tiles (giving each XCD a contiguous
+// range of tiles instead left the XCDs that held the middle of the output
+// with 1.75 times the mean work in a 64-channel call of 2^18 taps), and the
+// tiles running together on one XCD are near each other, so they read
+// nearly the same input chunks through its L2.
+__device__ __forceinline__ int center_out(int id, int n) {
+  const int mid = (n - 1) >> 1;
+  return (id & 1) ? mid + ((id + 1) >> 1) : mid - (id >> 1);
 }
 
 // A thread's share of one chunk's reversed IR window (hi and lo halves).
@@ -393,15 +402,16 @@ __device__ __forceinline__ void toeplitz_tile(const GatherCall& d, const int til
 
 template <typename TailT, int NM, int NN>
 __global__ __launch_bounds__(NT) void k_toeplitz(GatherCall d, int n_tiles) {
-  toeplitz_tile<TailT, NM, NN>(d, xcd_remap(blockIdx.x, n_tiles));
+  toeplitz_tile<TailT, NM, NN>(d, center_out(blockIdx.x, n_tiles));
 }
 
 // The calls of one pool-step class: workgroup i takes tile i - tile_start[k]
-// of call k (tile_start: prefix sums of the calls' tile counts).
+// of call k (tile_start: prefix sums of the calls' tile counts), in launch
+// order, so consecutive tiles (and calls) go to different XCDs.
 template <typename TailT, int NM, int NN>
 __global__ __launch_bounds__(NT) void k_toeplitz_batched(const GatherCall* calls, const int32_t* tile_start,
                                                          int n_calls) {
-  const int id = xcd_remap(blockIdx.x, gridDim.x);
+  const int id = blockIdx.x;
   const int k = find_call(tile_start, n_calls, id);
   const GatherCall d = calls[k];
   toeplitz_tile<TailT, NM, NN>(d, id - gr(tile_start)[k]);

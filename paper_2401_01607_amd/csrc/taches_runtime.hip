@@ -1128,6 +1128,12 @@ int taches_set_tile(taches_stream* s, int32_t r, int32_t w) {
 
 using taches::WorkItem;
 
+// One unit of a batched step's plan: a work item and its estimated work.
+struct PoolItem {
+  WorkItem w;
+  int64_t work;
+};
+
 struct taches_pool {
   int max_streams = 0;
   int64_t budget = 0, used = 0;
@@ -1164,6 +1170,15 @@ struct taches_pool {
   mutable bool ev_pending[kRing] = {};
   mutable double dev_ms_total = 0.0;
   int ev_next = 0, ev_last = -1;
+  // per-step planning buffers, kept from step to step so that a step
+  // allocates no host memory once the pool has seen its largest step
+  std::vector<CallPlan> plans;
+  std::vector<int> gather_ids, split_ids[4], owner, count;
+  std::vector<const GatherCall*> gcalls;
+  std::vector<char> enqueued;
+  std::vector<PoolItem> items;
+  std::vector<int64_t> load;
+  std::vector<int32_t> fill;
 };
 
 namespace {
@@ -1435,7 +1450,8 @@ int taches_pool_step_strided(taches_pool* p, int32_t n, taches_stream* const* st
     streams[i]->step_mark = mark;
   }
   // plan every call (validation first: an error leaves every stream untouched)
-  std::vector<CallPlan> plans(n);
+  std::vector<CallPlan>& plans = p->plans;
+  if ((int)plans.size() < n) plans.resize(n);
   for (int i = 0; i < n; ++i) {
     int rc = plan_call(streams[i], x_dev ? x_dev[i] : nullptr, x_cstride ? x_cstride[i] : 0, y_dev[i],
                        y_cstride ? y_cstride[i] : 0, n_blocks[i], nullptr, nullptr, &plans[i]);
@@ -1448,9 +1464,12 @@ int taches_pool_step_strided(taches_pool* p, int32_t n, taches_stream* const* st
   // device's.  FP32 streams share one persistent gather launch; split-BF16
   // streams share one split-input launch and one Toeplitz MFMA launch per
   // class (tail type, padded channel count), after the gather launch.
-  std::vector<int> gather_ids;
-  std::vector<const GatherCall*> gcalls;
-  std::vector<int> split_ids[4];   // class = 2 * tail_fp64 + (cpad > 32)
+  std::vector<int>& gather_ids = p->gather_ids;
+  std::vector<const GatherCall*>& gcalls = p->gcalls;
+  std::vector<int>* split_ids = p->split_ids;   // class = 2 * tail_fp64 + (cpad > 32)
+  gather_ids.clear();
+  gcalls.clear();
+  for (int k = 0; k < 4; ++k) split_ids[k].clear();
   for (int i = 0; i < n; ++i) {
     taches_stream* s = streams[i];
     if (s->cfg.precision == TACHES_PREC_SPLIT_BF16) {
@@ -1460,7 +1479,8 @@ int taches_pool_step_strided(taches_pool* p, int32_t n, taches_stream* const* st
       gcalls.push_back(&plans[i].g);
     }
   }
-  std::vector<char> enqueued(n, 0);
+  std::vector<char>& enqueued = p->enqueued;
+  enqueued.assign(n, 0);
   auto finish = [&](int rc) {
     for (int i = 0; i < n; ++i)
       if (enqueued[i]) commit_call(streams[i], plans[i]);
@@ -1468,12 +1488,11 @@ int taches_pool_step_strided(taches_pool* p, int32_t n, taches_stream* const* st
   };
   const bool has_gather = !gather_ids.empty();
   // ---- gather planning: work items over the resident workgroups ----
-  struct Item {
-    WorkItem w;
-    int64_t work;
-  };
-  std::vector<Item> items;
-  std::vector<int> owner, count;
+  typedef PoolItem Item;
+  std::vector<Item>& items = p->items;
+  std::vector<int>& owner = p->owner;
+  std::vector<int>& count = p->count;
+  items.clear();
   int nwg = 0, r = 0;
   bool mixed = false;   // some gather stream keeps an FP64 tail
   const int ng = (int)gather_ids.size();
@@ -1573,7 +1592,8 @@ int taches_pool_step_strided(taches_pool* p, int32_t n, taches_stream* const* st
                                            std::min<int64_t>(256LL * per_cu, by_work));
     owner.assign(items.size(), 0);
     count.assign(nwg, 0);
-    std::vector<int64_t> load(nwg, 0);
+    std::vector<int64_t>& load = p->load;
+    load.assign(nwg, 0);
     const size_t n_items = items.size();
     if ((span_work > 0 && n_items >= 8 * (size_t)nwg) ||
         (total_work >= 8 * max_work * (int64_t)nwg && n_items >= 16 * (size_t)nwg)) {
@@ -1695,7 +1715,8 @@ int taches_pool_step_strided(taches_pool* p, int32_t n, taches_stream* const* st
     }
     wgb[0] = 0;
     for (int b = 0; b < nwg; ++b) wgb[b + 1] = wgb[b] + count[b];
-    std::vector<int32_t> fill(wgb, wgb + nwg);
+    std::vector<int32_t>& fill = p->fill;
+    fill.assign(wgb, wgb + nwg);
     for (size_t i = 0; i < items.size(); ++i) wit[fill[owner[i]]++] = items[i].w;
   }
   for (int k = 0; k < 4; ++k) {

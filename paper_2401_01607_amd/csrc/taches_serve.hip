@@ -15,9 +15,13 @@
 // Abstract and Section 6): a step's range of blocks ends before such a
 // block, which starts the next range.
 //
-// Latency of a block = the tick's completion time (outputs in host memory)
-// minus the arrival time of the block's last sample; the deadline is one
-// block period.
+// Ticks overlap with the device: a tick enqueues its step (input copy, pool
+// step, output copy) and then waits for the previous tick's step, so the
+// host gathers and plans step k + 1 while the device runs step k, and the
+// device always has the next step queued.  Latency of a block = the time
+// its outputs are in host memory (the output copy's completion event,
+// placed on the host clock) minus the arrival time of the block's last
+// sample; the deadline is one block period.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -57,6 +61,26 @@ int64_t first_block_at(double t, int32_t B, double fs, int64_t k_min) {
 
 }  // namespace
 
+// One block range of a step in flight: what completing the step needs.
+struct FlightRange {
+  int64_t tag;
+  float* y;
+  int64_t y_cs;
+  int32_t C, B;
+  int64_t k0;
+  int32_t n;
+  int64_t yoff;
+  double start_s;
+  bool last;   // the stream's last block: it finishes when this step completes
+};
+
+struct Flight {
+  bool active = false;
+  int buf = 0;        // pinned buffer pair used
+  int ev = 0;         // completion event (after the output copy)
+  std::vector<FlightRange> ranges;
+};
+
 struct taches_server {
   taches_pool* pool = nullptr;
   double fs = 48000.0;
@@ -64,13 +88,26 @@ struct taches_server {
   double warmup_s = 0.0;
   std::chrono::steady_clock::time_point t0;
   std::vector<ServeStream> st;
-  // pinned host and device staging of one tick's input and output blocks
-  float* x_pin = nullptr;
-  float* y_pin = nullptr;
+  // staging of one step's input and output blocks: two pinned pairs used in
+  // turn (a step's input copy may still be queued while the next gathers;
+  // its outputs are read after the next step is enqueued); one device pair
+  // (copies and steps are ordered on the pool's stream)
+  float* x_pin[2] = {nullptr, nullptr};
+  float* y_pin[2] = {nullptr, nullptr};
   size_t pin_cap = 0;     // floats per buffer
   float* x_dev = nullptr;
   float* y_dev = nullptr;
   size_t dev_cap = 0;
+  // completion events (a ring: the previous completed one is the time
+  // reference for the next), and the host time of the last completed one
+  static constexpr int kEv = 4;
+  hipEvent_t ev[kEv] = {};
+  int ev_next = 0;
+  int ref_ev = -1;
+  double ref_t = 0.0;
+  hipEvent_t anchor = nullptr;
+  Flight fl;
+  int tick_buf = 0;
   // per-tick argument arrays of the pool step (kept to avoid reallocation)
   std::vector<taches_stream*> a_s;
   std::vector<const float*> a_x;
@@ -101,16 +138,20 @@ ServeStream* find_tag(taches_server* sv, int64_t tag, bool with_done = false) {
   return nullptr;
 }
 
+// Larger staging (called with no step in flight).
 int grow(taches_server* sv, size_t floats) {
   if (floats > sv->pin_cap) {
     const size_t cap = std::max(floats, 2 * sv->pin_cap);
-    (void)hipHostFree(sv->x_pin);
-    (void)hipHostFree(sv->y_pin);
-    sv->x_pin = sv->y_pin = nullptr;
+    for (int k = 0; k < 2; ++k) {
+      (void)hipHostFree(sv->x_pin[k]);
+      (void)hipHostFree(sv->y_pin[k]);
+      sv->x_pin[k] = sv->y_pin[k] = nullptr;
+    }
     sv->pin_cap = 0;
-    if (hipHostMalloc((void**)&sv->x_pin, cap * 4, hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void**)&sv->y_pin, cap * 4, hipHostMallocDefault) != hipSuccess)
-      return taches::set_error(TACHES_ENOMEM, "serving: pinned staging of %zu floats", cap);
+    for (int k = 0; k < 2; ++k)
+      if (hipHostMalloc((void**)&sv->x_pin[k], cap * 4, hipHostMallocDefault) != hipSuccess ||
+          hipHostMalloc((void**)&sv->y_pin[k], cap * 4, hipHostMallocDefault) != hipSuccess)
+        return taches::set_error(TACHES_ENOMEM, "serving: pinned staging of %zu floats", cap);
     sv->pin_cap = cap;
   }
   if (floats > sv->dev_cap) {
@@ -123,6 +164,58 @@ int grow(taches_server* sv, size_t floats) {
       return taches::set_error(TACHES_ENOMEM, "serving: device staging of %zu floats", cap);
     sv->dev_cap = cap;
   }
+  return TACHES_OK;
+}
+
+// Wait for the step in flight, place its completion on the host clock, hand
+// its outputs to the streams' host buffers, record its block latencies and
+// report streams whose last block it held.
+int complete_flight(taches_server* sv) {
+  Flight& f = sv->fl;
+  if (!f.active) return TACHES_OK;
+  const double t0 = clock_s(sv);
+  hipError_t e = hipEventSynchronize(sv->ev[f.ev]);
+  if (e != hipSuccess) return taches::set_error(TACHES_EDEVICE, "serving: wait: %s", hipGetErrorString(e));
+  const double t1 = clock_s(sv);
+  float ms = 0.f;
+  double done = t1;
+  if (sv->ref_ev >= 0 && hipEventElapsedTime(&ms, sv->ev[sv->ref_ev], sv->ev[f.ev]) == hipSuccess)
+    done = std::min(t1, sv->ref_t + (double)ms * 1e-3);
+  sv->ref_ev = f.ev;
+  sv->ref_t = done;
+  const double fs = sv->fs;
+  for (const FlightRange& q : f.ranges) {
+    if (q.y) {
+      const size_t row = (size_t)q.n * q.B;
+      const float* src = sv->y_pin[f.buf] + q.yoff;
+      for (int c = 0; c < q.C; ++c) std::memcpy(q.y + c * q.y_cs + q.k0 * q.B, src + c * row, row * 4);
+    }
+    const double per = (double)q.B / fs;
+    for (int32_t k = 0; k < q.n; ++k) {
+      const double arrival = q.start_s + (double)(q.k0 + k + 1) * per;
+      if (arrival < sv->warmup_s) continue;
+      sv->lat_s.push_back((float)(done - arrival));
+      sv->lat_B.push_back(q.B);
+    }
+    if (q.last) sv->finished.push_back(q.tag);
+  }
+  f.active = false;
+  f.ranges.clear();
+  sv->stats.wait_s += t1 - t0;
+  sv->stats.scatter_s += clock_s(sv) - t1;
+  return TACHES_OK;
+}
+
+// With nothing in flight, tie a fresh event on the pool's (idle) stream to
+// the host clock: the time reference for the next completion.
+int anchor_clock(taches_server* sv, hipStream_t hs) {
+  const int k = sv->ev_next;
+  sv->ev_next = (sv->ev_next + 1) % taches_server::kEv;
+  hipError_t e = hipEventRecord(sv->ev[k], hs);
+  if (e == hipSuccess) e = hipEventSynchronize(sv->ev[k]);
+  if (e != hipSuccess) return taches::set_error(TACHES_EDEVICE, "serving: clock anchor: %s", hipGetErrorString(e));
+  sv->ref_ev = k;
+  sv->ref_t = clock_s(sv);
   return TACHES_OK;
 }
 
@@ -141,18 +234,35 @@ taches_server* taches_server_create(taches_pool* pool, double fs, int32_t max_bl
   sv->max_blocks = max_blocks_per_step;
   sv->warmup_s = warmup_s;
   sv->t0 = std::chrono::steady_clock::now();
+  for (int k = 0; k < taches_server::kEv; ++k) {
+    if (hipEventCreate(&sv->ev[k]) != hipSuccess) {
+      taches::set_error(TACHES_EDEVICE, "serving: event creation failed");
+      for (int j = 0; j < k; ++j) (void)hipEventDestroy(sv->ev[j]);
+      delete sv;
+      return nullptr;
+    }
+  }
   return sv;
 }
 
 int taches_server_destroy(taches_server* sv) {
   if (!sv) return TACHES_OK;
   (void)taches_pool_synchronize(sv->pool);
-  (void)hipHostFree(sv->x_pin);
-  (void)hipHostFree(sv->y_pin);
+  for (int k = 0; k < 2; ++k) {
+    (void)hipHostFree(sv->x_pin[k]);
+    (void)hipHostFree(sv->y_pin[k]);
+  }
   (void)hipFree(sv->x_dev);
   (void)hipFree(sv->y_dev);
+  for (hipEvent_t e : sv->ev)
+    if (e) (void)hipEventDestroy(e);
   delete sv;
   return TACHES_OK;
+}
+
+int taches_server_flush(taches_server* sv) {
+  if (!sv) return taches::set_error(TACHES_EINVAL, "server is NULL");
+  return complete_flight(sv);
 }
 
 double taches_server_clock(const taches_server* sv) { return sv ? clock_s(sv) : -1.0; }
@@ -256,18 +366,27 @@ int taches_server_tick(taches_server* sv, taches_server_tick_info* out) {
     return t;
   };
   if (m == 0) {
+    // nothing new: finish the step in flight (its outputs are due)
+    int rc = complete_flight(sv);
+    if (rc != TACHES_OK) return rc;
     info.next_due_s = next_due();
     if (out) *out = info;
     return TACHES_OK;
   }
-  int rc = grow(sv, std::max(xf, yf));
-  if (rc != TACHES_OK) return rc;
+  const hipStream_t hs = taches::pool_stream(sv->pool);
+  int rc = TACHES_OK;
+  if (std::max(xf, yf) > std::min(sv->pin_cap, sv->dev_cap)) {
+    rc = complete_flight(sv);   // staging in use by the step in flight
+    if (rc == TACHES_OK) rc = grow(sv, std::max(xf, yf));
+    if (rc != TACHES_OK) return rc;
+  }
+  const int buf = sv->tick_buf;
   // ---- gather the arrived input into pinned memory ----
   for (size_t j = 0; j < m; ++j) {
     if (sv->a_xoff[j] < 0) continue;
     const ServeStream& r = sv->st[sv->a_idx[j]];
     const size_t row = (size_t)sv->a_n[j] * r.B;
-    float* dst = sv->x_pin + sv->a_xoff[j];
+    float* dst = sv->x_pin[buf] + sv->a_xoff[j];
     for (int c = 0; c < r.C; ++c)
       std::memcpy(dst + c * row, r.x + c * r.x_cs + sv->a_k0[j] * r.B, row * 4);
   }
@@ -277,35 +396,34 @@ int taches_server_tick(taches_server* sv, taches_server_tick_info* out) {
     sv->a_x[j] = sv->a_xoff[j] >= 0 ? sv->x_dev + sv->a_xoff[j] : nullptr;
     sv->a_y[j] = sv->y_dev + sv->a_yoff[j];
   }
-  const hipStream_t hs = taches::pool_stream(sv->pool);
+  if (!sv->fl.active) {
+    rc = anchor_clock(sv, hs);
+    if (rc != TACHES_OK) return rc;
+  }
   const double t_launch = clock_s(sv);
   if (xf > 0) {
-    const hipError_t e = hipMemcpyAsync(sv->x_dev, sv->x_pin, xf * 4, hipMemcpyHostToDevice, hs);
+    const hipError_t e = hipMemcpyAsync(sv->x_dev, sv->x_pin[buf], xf * 4, hipMemcpyHostToDevice, hs);
     if (e != hipSuccess) return taches::set_error(TACHES_EDEVICE, "serving: input copy: %s", hipGetErrorString(e));
   }
   rc = taches_pool_step(sv->pool, (int32_t)m, sv->a_s.data(), sv->a_x.data(), sv->a_y.data(), sv->a_n.data());
   if (rc != TACHES_OK) return rc;
-  const double t_queued = clock_s(sv);
+  // the step is committed on the host: from here on, state advances even if
+  // a later call reports an error
+  const int evk = sv->ev_next;
+  sv->ev_next = (sv->ev_next + 1) % taches_server::kEv;
   {
-    const hipError_t e = hipMemcpyAsync(sv->y_pin, sv->y_dev, yf * 4, hipMemcpyDeviceToHost, hs);
-    if (e != hipSuccess) return taches::set_error(TACHES_EDEVICE, "serving: output copy: %s", hipGetErrorString(e));
-    // the step is committed on the host: from here on, state advances even
-    // if the wait reports an error
+    hipError_t e = hipMemcpyAsync(sv->y_pin[buf], sv->y_dev, yf * 4, hipMemcpyDeviceToHost, hs);
+    if (e == hipSuccess) e = hipEventRecord(sv->ev[evk], hs);
     for (size_t j = 0; j < m; ++j) sv->st[sv->a_idx[j]].next = sv->a_k0[j] + sv->a_n[j];
-    const hipError_t w = hipStreamSynchronize(hs);
-    if (w != hipSuccess) return taches::set_error(TACHES_EDEVICE, "serving: wait: %s", hipGetErrorString(w));
+    if (e != hipSuccess) return taches::set_error(TACHES_EDEVICE, "serving: output copy: %s", hipGetErrorString(e));
   }
-  const double t_back = clock_s(sv);
-  // ---- outputs to the streams' host buffers ----
-  for (size_t j = 0; j < m; ++j) {
-    const ServeStream& r = sv->st[sv->a_idx[j]];
-    if (!r.y) continue;
-    const size_t row = (size_t)sv->a_n[j] * r.B;
-    const float* src = sv->y_pin + sv->a_yoff[j];
-    for (int c = 0; c < r.C; ++c) std::memcpy(r.y + c * r.y_cs + sv->a_k0[j] * r.B, src + c * row, row * 4);
-  }
-  const double done = clock_s(sv);
-  // ---- records ----
+  const double t_queued = clock_s(sv);
+  // ---- the new step's book-keeping; finished streams leave the server ----
+  Flight nf;
+  nf.active = true;
+  nf.buf = buf;
+  nf.ev = evk;
+  nf.ranges.reserve(m);
   int64_t blocks = 0, macs = 0;
   for (size_t j = 0; j < m; ++j) {
     const ServeStream& r = sv->st[sv->a_idx[j]];
@@ -315,23 +433,22 @@ int taches_server_tick(taches_server* sv, taches_server_tick_info* out) {
       taches_info inf;
       if (taches_get_info(r.s, &inf) == TACHES_OK) macs += (int64_t)n * r.B * inf.active_len * r.C;
     }
-    const double per = (double)r.B / fs;
-    for (int32_t q = 0; q < n; ++q) {
-      const double arrival = r.start_s + (double)(sv->a_k0[j] + q + 1) * per;
-      if (arrival < sv->warmup_s) continue;
-      sv->lat_s.push_back((float)(done - arrival));
-      sv->lat_B.push_back(r.B);
-    }
+    nf.ranges.push_back(FlightRange{r.tag, r.y, r.y_cs, r.C, r.B, sv->a_k0[j], n, sv->a_yoff[j], r.start_s,
+                                    sv->a_k0[j] + n >= r.n_total});
   }
-  // ---- finished streams leave the server (the caller detaches them) ----
   for (size_t i = sv->st.size(); i-- > 0;) {
     if (sv->st[i].next >= sv->st[i].n_total) {
-      sv->finished.push_back(sv->st[i].tag);
       sv->done.push_back(std::move(sv->st[i]));
       sv->st[i] = std::move(sv->st.back());
       sv->st.pop_back();
     }
   }
+  // ---- then wait for the previous step (the device works on this one) ----
+  rc = complete_flight(sv);
+  sv->fl = std::move(nf);
+  sv->tick_buf ^= 1;
+  if (rc != TACHES_OK) return rc;
+  const double done = clock_s(sv);
   info.next_due_s = next_due();
   info.streams = (int32_t)m;
   info.blocks = blocks;
@@ -344,8 +461,6 @@ int taches_server_tick(taches_server* sv, taches_server_tick_info* out) {
   sv->stats.busy_s += done - now;
   sv->stats.gather_s += t_launch - now;
   sv->stats.launch_s += t_queued - t_launch;
-  sv->stats.wait_s += t_back - t_queued;
-  sv->stats.scatter_s += done - t_back;
   sv->stats.max_blocks_in_a_range = std::max<int64_t>(
       sv->stats.max_blocks_in_a_range, *std::max_element(sv->a_n.begin(), sv->a_n.end()));
   sv->stats.bytes_in += (int64_t)xf * 4;

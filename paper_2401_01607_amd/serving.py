@@ -604,7 +604,8 @@ class RealtimeServer:
     have arrived, IR changes due, the ranges of blocks, gathering the
     arrived input into pinned memory, the host-to-device copy, the pool
     step, the device-to-host copy of every output block, latency records)
-    runs in one library call.
+    runs in one library call, which enqueues its step and then completes
+    the previous one, so host and device work overlap.
 
     Input audio lives in host memory: a seeded two-channel noise bank,
     planar [2][70 s]; request r reads channels [0, C) from a seeded offset.
@@ -759,9 +760,8 @@ class RealtimeServer:
                 break
             self._admit(now)
             tk = T.taches_server_tick(sv)
-            if tk.streams:
-                self._retire()
-            else:
+            self._retire()
+            if not tk.streams:
                 nxt = tk.next_due_s
                 if self.pending:
                     nxt = min(nxt, self.pending[0].arrival_s)
@@ -771,6 +771,8 @@ class RealtimeServer:
             if now - last_drain > 1.0:
                 self._drain_records()
                 last_drain = now
+        T.taches_server_flush(sv)
+        self._retire()
         wall = T.taches_server_clock(sv)
         self._drain_records()
         return self.summary(wall)

@@ -117,6 +117,7 @@ _SIGS = {
     "taches_server_add": (ctypes.c_int, [_vp, _vp, _i64, ctypes.c_double, _i64, _i64, _vp, _i64, _vp, _i64, _i32,
                                          _vp, _vp, _vp]),
     "taches_server_tick": (ctypes.c_int, [_vp, _P(taches_server_tick_info)]),
+    "taches_server_flush": (ctypes.c_int, [_vp]),
     "taches_server_take_finished": (ctypes.c_int, [_vp, _vp, _i32]),
     "taches_server_take_latencies": (ctypes.c_int, [_vp, _vp, _vp, _i32]),
     "taches_server_stream_state": (ctypes.c_int, [_vp, _i64, _P(_i64), _vp, _i32]),
@@ -549,6 +550,10 @@ def taches_server_tick(sv) -> taches_server_tick_info:
     out = taches_server_tick_info()
     _check(lib.taches_server_tick(sv, ctypes.byref(out)), "taches_server_tick")
     return out
+
+
+def taches_server_flush(sv) -> None:
+    _check(lib.taches_server_flush(sv), "taches_server_flush")
 
 
 def taches_server_take_finished(sv, cap: int = 4096) -> np.ndarray:
