@@ -344,17 +344,52 @@ __device__ __forceinline__ void toeplitz_tile(const GatherCall& d, const int til
           load_b(0, bf[0]);
           load_b(1, bf[1]);
         }
-        // A fragments come from LDS one K-step ahead (two-slot ring)
-        AF af[2];
-        load_a(0, af[0]);
+        if constexpr (NM == 2) {
+          // A is Toeplitz: the fragment of the lower 32-row tile at K-step t
+          // is the upper tile's fragment of K-step t - 2 (32 rows down = 32
+          // samples later).  Only the upper tile's fragments come from LDS
+          // (one K-step ahead), kept in a four-slot ring; the lower tile
+          // reads LDS for K-steps 0 and 1 only.
+          struct A1 {
+            bf16x8 h, l;
+          };
+          auto load_a0 = [&](int t, int mt, A1& f) {
+            const int a = MT - 1 - r0 - 32 * mt - i + 16 * t + 8 * kg;
+            const int aoff = (a & 7) * CP_LEN + (a & ~7);
+            f.h = *reinterpret_cast<const bf16x8*>(cp_hi + aoff);
+            f.l = *reinterpret_cast<const bf16x8*>(cp_lo + aoff);
+          };
+          A1 up[4], low01[2];
+          load_a0(0, 0, up[0]);
+          load_a0(0, 1, low01[0]);
 #pragma unroll
-        for (int t = 0; t < KC / 16; ++t) {
-          if (t + 2 < KC / 16) load_b(t + 2, bf[(t + 2) % 3]);
-          if (t == KC / 16 - 3) prefetch_next();
-          if (t + 1 < KC / 16) load_a(t + 1, af[(t + 1) % 2]);
-          __builtin_amdgcn_sched_barrier(0);
-          mfmas(af[t % 2], bf[t % 3]);
-          __builtin_amdgcn_sched_barrier(0);
+          for (int t = 0; t < KC / 16; ++t) {
+            if (t + 2 < KC / 16) load_b(t + 2, bf[(t + 2) % 3]);
+            if (t == KC / 16 - 3) prefetch_next();
+            if (t + 1 < KC / 16) load_a0(t + 1, 0, up[(t + 1) % 4]);
+            if (t + 1 < 2) load_a0(t + 1, 1, low01[t + 1]);
+            __builtin_amdgcn_sched_barrier(0);
+            AF af;
+            af.h[0] = up[t % 4].h;
+            af.l[0] = up[t % 4].l;
+            af.h[1] = t < 2 ? low01[t < 2 ? t : 0].h : up[(t + 2) % 4].h;
+            af.l[1] = t < 2 ? low01[t < 2 ? t : 0].l : up[(t + 2) % 4].l;
+            mfmas(af, bf[t % 3]);
+            __builtin_amdgcn_sched_barrier(0);
+          }
+        } else {
+          // A fragments come from LDS one K-step ahead (two-slot ring)
+          AF af[2];
+          load_a(0, af[0]);
+#pragma unroll
+          for (int t = 0; t < KC / 16; ++t) {
+            if (t + 2 < KC / 16) load_b(t + 2, bf[(t + 2) % 3]);
+            if (t == KC / 16 - 3) prefetch_next();
+            if (t + 1 < KC / 16) load_a(t + 1, af[(t + 1) % 2]);
+            __builtin_amdgcn_sched_barrier(0);
+            mfmas(af[t % 2], bf[t % 3]);
+            __builtin_amdgcn_sched_barrier(0);
+          }
         }
       } else {
         for (int t = 0; t < ksteps; ++t) {
