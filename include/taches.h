@@ -269,11 +269,12 @@ int taches_set_tile(taches_stream* s, int32_t r, int32_t w);
  * A pool admits streams up to a stream count and an HBM byte budget (the
  * sum of the attached streams' device_bytes).  taches_pool_step advances a
  * set of attached streams by n_blocks[i] blocks each in one persistent
- * launch: the host cuts every stream's call into output tiles and spreads
- * them over the resident workgroups: when tiles are many, runs of
- * consecutive tiles are cut in stream order into shares of equal work;
- * otherwise the largest are dealt first.  Each stream's result is
- * bit-identical to processing it alone, whatever the assignment.  While attached, a stream's
+ * launch: the host cuts every stream's call into work items (output tiles,
+ * or runs of consecutive tiles when tiles are many) and lists them in the
+ * order the resident workgroups take them from a shared counter: stream
+ * order for many similar items, largest first otherwise.  Each stream's
+ * result is bit-identical to processing it alone, whatever workgroup
+ * computes which tile.  While attached, a stream's
  * device work runs on the pool's HIP stream; taches_set_ir and
  * taches_load_ir_slot stay usable (a pending IR applies at the stream's next
  * step); taches_process* and taches_close return TACHES_EBUSY. */
@@ -335,7 +336,8 @@ typedef struct taches_pool_info {
   int32_t pad_;
   int64_t graph_replays;
   double last_plan_ms;      /* host time to plan the last step */
-  double last_imbalance;    /* busiest workgroup's work / mean work */
+  double last_imbalance;    /* estimated busiest workgroup's work / mean work
+                               (workgroups take work items from a queue) */
   double last_device_ms;    /* device time of the last step's batched launch
                                (table copy + kernel); -1 until it has run */
   double device_ms_total;   /* device time of all batched launches found

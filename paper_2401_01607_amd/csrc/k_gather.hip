@@ -612,23 +612,33 @@ __global__ __launch_bounds__(64 * W) void k_gather(GatherCall d, int n_tiles) {
 }
 
 // Batched: one packed table (header, call descriptors, per-call tail type,
-// per-workgroup item ranges, work items).  Workgroup b walks items
-// [wg_begin[b], wg_begin[b+1]) of a host-built list (balanced over
-// workgroups), each item a run of consecutive output tiles of one channel of
-// one call; each call's tail type is chosen per stream.
+// work items, a counter).  The persistent workgroups take items one at a
+// time from the shared counter (a work queue; the host lists the items in
+// the order they should be taken: largest first when sizes differ much),
+// so a workgroup that finishes early takes more, whatever the items really
+// cost.  Each item is a run of consecutive output tiles of one channel of
+// one call; each call's tail type is chosen per stream.  Which workgroup
+// computes a tile does not change its result (one wave computes a tile,
+// summing in the fixed chunk order).
 // MIXED: some calls keep an FP64 tail (both tail types compiled in);
 // otherwise the FP32-tail code alone, which needs fewer registers.
 template <int R, bool MIXED>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_gather_batched(
-    const unsigned char* __restrict__ table) {
+    unsigned char* __restrict__ table) {
   const BatchHeader hd = *reinterpret_cast<const BatchHeader*>(table);
   const GatherCall* __restrict__ calls = reinterpret_cast<const GatherCall*>(table + hd.off_calls);
   const int32_t* __restrict__ call_fp64 = reinterpret_cast<const int32_t*>(table + hd.off_fp64);
-  const int32_t* __restrict__ wg_begin = reinterpret_cast<const int32_t*>(table + hd.off_wgb);
   const WorkItem* __restrict__ items = reinterpret_cast<const WorkItem*>(table + hd.off_items);
-  const int b = blockIdx.x;
-  const int it0 = wg_begin[b], it1 = wg_begin[b + 1];
-  for (int it = it0; it < it1; ++it) {
+  int* next = reinterpret_cast<int*>(table + hd.off_next);
+  const int lane = threadIdx.x & 63;
+  auto take = [&]() {
+    int v = 0;
+    if (lane == 0) v = atomicAdd(next, 1);
+    return __builtin_amdgcn_readfirstlane(v);
+  };
+  int it = take();
+  while (it < hd.n_items) {
+    const int it_next = take();   // in flight while this item runs
     const WorkItem wi = items[it];
     const GatherCall& d = calls[wi.call];   // read in place (a local copy would spill)
     const bool f64 = MIXED && call_fp64[wi.call] != 0;
@@ -643,6 +653,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
       }
       __syncthreads();
     }
+    it = it_next;
   }
 }
 
@@ -669,7 +680,7 @@ hipError_t launch_r(const GatherCall& call, bool fp64, int w, hipStream_t st) {
 }
 
 template <int R>
-hipError_t launch_batched_r(const unsigned char* table_dev, int n_wg, bool mixed, hipStream_t st) {
+hipError_t launch_batched_r(unsigned char* table_dev, int n_wg, bool mixed, hipStream_t st) {
   constexpr int shmem = lds_bytes<R, 1>();
   if (mixed)
     hipLaunchKernelGGL((k_gather_batched<R, true>), dim3(n_wg), dim3(64), shmem, st, table_dev);
@@ -723,7 +734,7 @@ int gather_batched_waves_per_cu(int r, bool mixed) {
   }
 }
 
-hipError_t launch_gather_batched(const unsigned char* table_dev, int n_wg, int r, bool mixed, hipStream_t st) {
+hipError_t launch_gather_batched(unsigned char* table_dev, int n_wg, int r, bool mixed, hipStream_t st) {
   if (n_wg <= 0) return hipSuccess;
   switch (r) {
     case 4: return launch_batched_r<4>(table_dev, n_wg, mixed, st);

@@ -94,12 +94,14 @@ struct WorkItem {
 hipError_t launch_gather(const GatherCall& call, bool tail_fp64, int r, int w, hipStream_t st);
 // Packed table of a batched launch: this header, then the sub-tables at the
 // given byte offsets (GatherCall[n_calls], int32 tail-is-FP64[n_calls],
-// int32 wg_begin[n_wg + 1], WorkItem[n_items]).
+// WorkItem[n_items] in the order workgroups take them, and an int32 counter
+// of items taken, 0 in the table the host copies in).
 struct BatchHeader {
-  int32_t off_calls, off_fp64, off_wgb, off_items;
+  int32_t off_calls, off_fp64, off_items, off_next;
+  int32_t n_items, pad_;
 };
 // mixed: some calls of the table keep an FP64 tail.
-hipError_t launch_gather_batched(const unsigned char* table_dev, int n_wg, int r, bool mixed, hipStream_t st);
+hipError_t launch_gather_batched(unsigned char* table_dev, int n_wg, int r, bool mixed, hipStream_t st);
 
 inline int tile_outputs(int r) { return 64 * r; }
 

@@ -1140,7 +1140,7 @@ struct taches_pool {
   int device = 0;
   std::vector<taches_stream*> attached;
   hipStream_t own = nullptr, stream = nullptr, capture = nullptr;
-  // one packed table: [calls][fp64 flags][wg_begin][items], pinned and device.
+  // one packed table: [header][calls][fp64 flags][items][counter], pinned and device.
   // Two pinned buffers are used in turn, so the host can build a step's
   // table while the previous step (and its copy) is still queued.
   unsigned char* tab_pin[2] = {nullptr, nullptr};
@@ -1173,12 +1173,12 @@ struct taches_pool {
   // per-step planning buffers, kept from step to step so that a step
   // allocates no host memory once the pool has seen its largest step
   std::vector<CallPlan> plans;
-  std::vector<int> gather_ids, split_ids[4], owner, count;
+  std::vector<int> gather_ids, split_ids[4];
   std::vector<const GatherCall*> gcalls;
   std::vector<char> enqueued;
   std::vector<PoolItem> items;
-  std::vector<int64_t> load;
-  std::vector<int32_t> fill;
+  std::vector<uint32_t> order;
+  std::vector<int64_t> heap;
 };
 
 namespace {
@@ -1490,8 +1490,6 @@ int taches_pool_step_strided(taches_pool* p, int32_t n, taches_stream* const* st
   // ---- gather planning: work items over the resident workgroups ----
   typedef PoolItem Item;
   std::vector<Item>& items = p->items;
-  std::vector<int>& owner = p->owner;
-  std::vector<int>& count = p->count;
   items.clear();
   int nwg = 0, r = 0;
   bool mixed = false;   // some gather stream keeps an FP64 tail
@@ -1590,73 +1588,49 @@ int taches_pool_step_strided(taches_pool* p, int32_t n, taches_stream* const* st
     const int64_t by_work = std::max<int64_t>(1, total_work / max_work);
     nwg = (int)std::max<int64_t>(std::min<int64_t>(256, (int64_t)items.size()),
                                            std::min<int64_t>(256LL * per_cu, by_work));
-    owner.assign(items.size(), 0);
-    count.assign(nwg, 0);
-    std::vector<int64_t>& load = p->load;
-    load.assign(nwg, 0);
+    // Workgroups take the items from a shared counter in list order.  With
+    // merged runs or many small items, the list stays in stream and tile
+    // order (neighbouring tiles share IR windows and inputs in L2);
+    // otherwise it is sorted largest first, so the queue hands out the
+    // heaviest items while every workgroup is still busy and the small
+    // ones fill the end (greedy largest-first: no workgroup ends more
+    // than one item after the mean).
     const size_t n_items = items.size();
-    if ((span_work > 0 && n_items >= 8 * (size_t)nwg) ||
-        (total_work >= 8 * max_work * (int64_t)nwg && n_items >= 16 * (size_t)nwg)) {
-      // merged runs (at most one merge span each) or many small items: cut
-      // the list, in stream and tile order, into nwg runs of near-equal work
-      // (item i goes to the workgroup holding the middle of its work).  O(n),
-      // no sort; no workgroup exceeds the mean by more than one item.  The
-      // owner never decreases along the list, so a moving boundary replaces
-      // a division per item.
-      // (128-bit products: work sums of very long calls times nwg exceed 2^63)
-      int64_t before = 0;
-      __int128 bound = 2 * (__int128)total_work;   // (b + 1) * 2 * total_work
-      int b = 0;
-      for (size_t i = 0; i < n_items; ++i) {
-        const int64_t mid2 = 2 * before + items[i].work;   // twice the item's midpoint
-        while (b < nwg - 1 && (__int128)mid2 * nwg >= bound) {
-          ++b;
-          bound += 2 * (__int128)total_work;
-        }
-        owner[i] = b;
-        load[b] += items[i].work;
-        before += items[i].work;
-      }
+    std::vector<uint32_t>& order = p->order;
+    const bool in_order = (span_work > 0 && n_items >= 8 * (size_t)nwg) ||
+                          (total_work >= 8 * max_work * (int64_t)nwg && n_items >= 16 * (size_t)nwg);
+    if (in_order) {
+      order.resize(n_items);
+      for (size_t k = 0; k < n_items; ++k) order[k] = (uint32_t)k;
     } else {
-      std::vector<uint32_t> order;
       sort_by_work_desc(items, order, [](const Item& it) { return it.work; });
-      if (n_items >= 8 * (size_t)nwg) {
-        // largest first, dealt out in serpentine order (0..nwg-1, nwg-1..0, ...)
-        for (size_t k = 0; k < n_items; ++k) {
-          const size_t row = k / nwg, col = k % nwg;
-          const int b = (int)((row & 1) ? nwg - 1 - col : col);
-          owner[order[k]] = b;
-          load[b] += items[order[k]].work;
+    }
+    // reported estimate of the busiest workgroup's work over the mean: the
+    // greedy bound (mean + largest item) / mean when items are many (at
+    // least 8 per workgroup), else the queue played out on the estimated
+    // works (a heap of workgroup loads)
+    const double mean = (double)total_work / nwg;
+    if (in_order || n_items >= 8 * (size_t)nwg) {
+      p->last_imbalance = mean > 0 ? (mean + (double)max_work) / mean : 1.0;
+    } else {
+      std::vector<int64_t>& heap = p->heap;   // min-heap of workgroup loads
+      heap.assign(nwg, 0);
+      for (uint32_t i : order) {
+        heap[0] += items[i].work;
+        size_t j = 0;
+        for (;;) {
+          const size_t l = 2 * j + 1, r = l + 1;
+          size_t m = j;
+          if (l < heap.size() && heap[l] < heap[m]) m = l;
+          if (r < heap.size() && heap[r] < heap[m]) m = r;
+          if (m == j) break;
+          std::swap(heap[j], heap[m]);
+          j = m;
         }
-      } else {
-        // largest item first onto the least-loaded workgroup (LPT); the
-        // heap's top takes the item and sinks to its place in one pass
-        std::vector<std::pair<int64_t, int>> heap(nwg);
-        for (int b = 0; b < nwg; ++b) heap[b] = {0, b};
-        for (uint32_t i : order) {
-          heap[0].first += items[i].work;
-          owner[i] = heap[0].second;
-          size_t j = 0;
-          for (;;) {
-            const size_t l = 2 * j + 1, r = l + 1;
-            size_t m = j;
-            if (l < heap.size() && heap[l].first < heap[m].first) m = l;
-            if (r < heap.size() && heap[r].first < heap[m].first) m = r;
-            if (m == j) break;
-            std::swap(heap[j], heap[m]);
-            j = m;
-          }
-        }
-        for (auto& h : heap) load[h.second] = h.first;
       }
+      const int64_t mx = *std::max_element(heap.begin(), heap.end());
+      p->last_imbalance = mean > 0 ? (double)mx / mean : 1.0;
     }
-    for (size_t i = 0; i < n_items; ++i) count[owner[i]] += 1;
-    int64_t mx = 0, sum = 0;
-    for (int b = 0; b < nwg; ++b) {
-      mx = std::max(mx, load[b]);
-      sum += load[b];
-    }
-    p->last_imbalance = sum > 0 ? (double)mx * nwg / (double)sum : 1.0;
   }
   // ---- split classes: calls, tile and fragment prefix sums ----
   const int mt = taches::toeplitz_rows_per_tile();
@@ -1673,15 +1647,15 @@ int taches_pool_step_strided(taches_pool* p, int32_t n, taches_stream* const* st
     split_tiles += sb[k].n_tiles;
   }
   if (split_tiles > INT32_MAX) return fail(TACHES_EINVAL, "step too large: %lld Toeplitz tiles", (long long)split_tiles);
-  // ---- table layout: [gather: header, calls, fp64 flags, wg_begin, items]
+  // ---- table layout: [gather: header, calls, fp64 flags, items, counter]
   // [per split class: calls, tile starts (int32), fragment starts (int64)] ----
-  size_t off_calls = 0, off_fp64 = 0, off_wgb = 0, off_items = 0, bytes = 0;
+  size_t off_calls = 0, off_fp64 = 0, off_items = 0, off_next = 0, bytes = 0;
   if (has_gather) {
     off_calls = align256(sizeof(taches::BatchHeader));
     off_fp64 = align256(off_calls + sizeof(GatherCall) * ng);
-    off_wgb = align256(off_fp64 + sizeof(int32_t) * ng);
-    off_items = align256(off_wgb + sizeof(int32_t) * (nwg + 1));
-    bytes = align256(off_items + sizeof(WorkItem) * items.size());
+    off_items = align256(off_fp64 + sizeof(int32_t) * ng);
+    off_next = align256(off_items + sizeof(WorkItem) * items.size());
+    bytes = align256(off_next + sizeof(int32_t));
   }
   for (int k = 0; k < 4; ++k) {
     if (!sb[k].n_calls) continue;
@@ -1702,22 +1676,21 @@ int taches_pool_step_strided(taches_pool* p, int32_t n, taches_stream* const* st
     taches::BatchHeader* hd = (taches::BatchHeader*)pin;
     hd->off_calls = (int32_t)off_calls;
     hd->off_fp64 = (int32_t)off_fp64;
-    hd->off_wgb = (int32_t)off_wgb;
     hd->off_items = (int32_t)off_items;
+    hd->off_next = (int32_t)off_next;
+    hd->n_items = (int32_t)items.size();
+    hd->pad_ = 0;
     GatherCall* calls = (GatherCall*)(pin + off_calls);
     int32_t* fp64 = (int32_t*)(pin + off_fp64);
-    int32_t* wgb = (int32_t*)(pin + off_wgb);
     WorkItem* wit = (WorkItem*)(pin + off_items);
     for (int k = 0; k < ng; ++k) {
       calls[k] = plans[gather_ids[k]].g;
       calls[k].tile_order = 2;
       fp64[k] = streams[gather_ids[k]]->tail_fp64 ? 1 : 0;
     }
-    wgb[0] = 0;
-    for (int b = 0; b < nwg; ++b) wgb[b + 1] = wgb[b] + count[b];
-    std::vector<int32_t>& fill = p->fill;
-    fill.assign(wgb, wgb + nwg);
-    for (size_t i = 0; i < items.size(); ++i) wit[fill[owner[i]]++] = items[i].w;
+    const std::vector<uint32_t>& order = p->order;
+    for (size_t k = 0; k < items.size(); ++k) wit[k] = items[order[k]].w;
+    *(int32_t*)(pin + off_next) = 0;   // items taken: reset by every table copy
   }
   for (int k = 0; k < 4; ++k) {
     if (!sb[k].n_calls) continue;
