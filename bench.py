@@ -48,8 +48,8 @@ U32 = 2.0 ** -24
 # source has changed.
 TRAFFIC_COUNTERS = {
     ("k_gather<16,4,double>", "c3"): {
-        "source_sha256": "4eadb2df24bf453250d4bf484c458d48a30bd9b2dbfab6b181c8c19c6b1f1556",
-        "fetch_kib": 244715.3, "fetch_scale": 2.0, "write_kib": 311168.0, "write_scale": 1.0},
+        "source_sha256": "4f01667d849e66701d8e7669a0c112e36386c48105e56011c14b009decf26f29",
+        "fetch_kib": 244734.7, "fetch_scale": 2.0, "write_kib": 311168.0, "write_scale": 1.0},
 }
 
 

@@ -190,9 +190,10 @@ int taches_convolve(const float* x_dev, int64_t nx, int32_t channels, const floa
  * under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc).  FP32 precision; same operands, role exchange and result as
  * taches_convolve with TACHES_PREC_FP32, bit for bit.  Its work memory (the
- * zero-padded input and the tail the kernel clears as it emits) is a fixed
- * 64 MiB array per device, held from the first call on that device until
- * the process ends: the call needs
+ * zero-padded input and the tail the kernel clears as it emits; nothing in
+ * it needs clearing between calls) is a fixed 64 MiB array in the library's
+ * device code, held on every device the library runs on until the process
+ * ends: the call needs
  *   align256(4 * channels * ceil(ns / 256) * 256) + w * channels * (nx + nh - 1)
  * bytes of it (ns = the signal operand's length after any role exchange,
  * w = 8 when the longer-lived operand, the IR, has >= 2^18 taps, else 4),

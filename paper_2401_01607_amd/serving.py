@@ -609,15 +609,17 @@ class RealtimeServer:
 
     Input audio lives in host memory: a seeded two-channel noise bank,
     planar [2][70 s]; request r reads channels [0, C) from a seeded offset.
-    IR version v of request r is the first L taps of row (r.seed + v) mod NB
-    of a device bank of flat white-noise IRs (the paper's IR shape).
-    Outputs of requests listed in keep_outputs are written to host arrays;
-    the others are copied back and dropped."""
+    Every request has IRs of its own: at admission its initial IR and one IR
+    per scheduled change are drawn on the device (flat white noise, the
+    paper's IR shape, unit L2 norm, from a generator seeded by the request)
+    and kept until the request finishes (the IRs of kept requests until
+    close).  Outputs of requests listed in keep_outputs are written to host
+    arrays; the others are copied back and dropped."""
 
     BANK_SECONDS = 70.0
 
     def __init__(self, requests, max_streams: int, hbm_budget_bytes: int, precision: int = 0,
-                 use_graph: bool = True, ir_bank: int = 16, max_ir_len: int = 262_144, seed: int = 9,
+                 use_graph: bool = True, max_ir_len: int = 262_144, seed: int = 9,
                  keep_outputs=(), max_blocks_per_step: int = 64, warmup_s: float = 0.0):
         import torch
         from . import taches as T
@@ -632,8 +634,7 @@ class RealtimeServer:
         n = int(self.BANK_SECONDS * W.FS)
         self.bank = np.stack([W.signal_gauss(n, seed * 100 + c) for c in range(2)])
         self.bank_len = n
-        self.irbank = torch.from_numpy(np.stack([W.impulse_response(max_ir_len, seed * 1000 + k, decay=0.0)
-                                                 for k in range(ir_bank)])).cuda()
+        self.irs: dict = {}          # rid -> [versions][L] device IRs of an admitted request
         self.max_ir_len = max_ir_len
         self.max_streams = max_streams
         self.budget = hbm_budget_bytes
@@ -648,8 +649,18 @@ class RealtimeServer:
         self.refused = 0
 
     # -- requests ------------------------------------------------------------
+    def _draw_irs(self, req):
+        """[1 + swaps][L] flat white-noise IRs of unit L2 norm for a request."""
+        torch = self.torch
+        g = torch.Generator(device="cuda")
+        g.manual_seed(int(req.seed))
+        h = torch.randn((1 + len(req.swap_times_s), req.ir_len), generator=g, device="cuda", dtype=torch.float32)
+        h /= torch.linalg.vector_norm(h, dim=1, keepdim=True)
+        return h
+
     def ir(self, req, version: int):
-        return self.irbank[(req.seed + version) % self.irbank.shape[0], :req.ir_len]
+        """IR version `version` of an admitted request (a device view, FP32)."""
+        return self.irs[req.rid][version]
 
     @staticmethod
     def n_input_blocks(req) -> int:
@@ -720,6 +731,7 @@ class RealtimeServer:
                 self.refused += 1
                 return
             self.queue.popleft()
+            self.irs[req.rid] = self._draw_irs(req)
             s.set_ir(self.ir(req, 0))
             n_in = self.n_input_blocks(req)
             n_total = n_in + math.ceil((req.ir_len - 1) / req.block)
@@ -737,10 +749,12 @@ class RealtimeServer:
         self.stats.max_active = max(self.stats.max_active, len(self.live))
 
     def _retire(self) -> None:
-        for rid in self.T.taches_server_take_finished(self.sv).tolist():
+        for rid in self.T.taches_server_take_finished(self.sv, 256).tolist():
             s, key, req = self.live.pop(rid)
             self.pool.detach(s)
             self._recycle(s, key)
+            if rid not in self.keep:
+                del self.irs[rid]   # every copy out of them has run: the stream's steps are done
             self.stats.completed += 1
 
     def _drain_records(self) -> None:

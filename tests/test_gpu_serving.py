@@ -191,7 +191,7 @@ def _server_check(precision, seed, tol_max):
     reqs = W.config5_requests(horizon_s=1.0, rate_hz=40.0, seed=seed, dur=(0.2, 0.5), lrange=(256, 8192),
                               swap_rate_hz=6.0)
     keep = [r.rid for r in reqs[::3]]
-    srv = RealtimeServer(reqs, max_streams=16, hbm_budget_bytes=1 << 34, keep_outputs=keep, ir_bank=8,
+    srv = RealtimeServer(reqs, max_streams=16, hbm_budget_bytes=1 << 34, keep_outputs=keep,
                          max_ir_len=8192, precision=precision)
     st = srv.run_realtime(1.0 + 0.5 + 8192 / 48000 + 1.5)
     assert st["completed"] == st["admitted"] == len(reqs)
@@ -251,7 +251,7 @@ def test_server_tick_small_budget_queues():
     per_max = max(nbytes(r.block, r.channels) for r in reqs)
     per_min = min(nbytes(r.block, r.channels) for r in reqs)
     budget = int(2.2 * per_max)
-    srv = RealtimeServer(reqs, max_streams=64, hbm_budget_bytes=budget, ir_bank=4, max_ir_len=4096)
+    srv = RealtimeServer(reqs, max_streams=64, hbm_budget_bytes=budget, max_ir_len=4096)
     st = srv.run_realtime(4.0)
     assert st["max_active_streams"] <= budget // per_min
     assert st["completed"] == len(reqs)
