@@ -655,7 +655,8 @@ def extra_c5_serving(errors, duration_s=30.0, warmup_s=10.0):
                            "B from {32..512}, <= 4096 streams, 64 GiB budget, FP32, real-time 48 kHz, "
                            "input from host memory and output back to host memory every tick",
                "run_s": duration_s, "warmup_s": warmup_s, "last_step_items": info.last_items,
-               "last_plan_ms": round(info.last_plan_ms, 3), "graph_replays": int(info.graph_replays)})
+               "last_plan_ms": round(info.last_plan_ms, 3), "graph_replays": int(info.graph_replays),
+               "graph_captures": int(info.graph_captures)})
     st["precision_at_20_per_s"] = {}
     for name, prec in (("fp32", T.TACHES_PREC_FP32), ("split_bf16", T.TACHES_PREC_SPLIT_BF16)):
         r2 = W.config5_requests(horizon_s=10.0, rate_hz=20.0, seed=502)

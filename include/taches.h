@@ -287,7 +287,9 @@ taches_pool* taches_pool_create(int32_t max_streams, int64_t hbm_budget_bytes, i
 int taches_pool_destroy(taches_pool* p);
 
 /* Admit a stream: TACHES_EBUSY if the pool is full or the stream is already
- * in a pool, TACHES_ENOMEM if its device bytes exceed the remaining budget. */
+ * in a pool, TACHES_ENOMEM if its device bytes exceed the remaining budget.
+ * Does not wait: the pool's later work is ordered after the work queued on
+ * the stream's HIP stream. */
 int taches_pool_attach(taches_pool* p, taches_stream* s);
 
 /* Release the stream's slot and bytes.  Does not wait: later work on the
@@ -343,6 +345,8 @@ typedef struct taches_pool_info {
                                (table copy + kernel); -1 until it has run */
   double device_ms_total;   /* device time of all batched launches found
                                complete so far (steps run without waiting) */
+  int64_t graph_captures;   /* graphs captured (one per tile, FP64-tail mix and
+                               workgroup count class; again after the table grows) */
 } taches_pool_info;
 
 int taches_pool_get_info(const taches_pool* p, taches_pool_info* out);
@@ -398,6 +402,9 @@ typedef struct taches_server_stats {
   double scatter_s;               /*   outputs to the streams' host buffers, latency records */
   int32_t streams;                /* streams registered and not finished */
   int32_t pad_;
+  int64_t recorded;               /* blocks with a latency record, whose latencies split into: */
+  double pickup_s;                /*   summed time from a block's arrival to the start of its tick */
+  double service_s;               /*   summed time from the start of its tick to its outputs in host memory */
 } taches_server_stats;
 
 /* NULL on failure.  fs > 0 (samples per second), max_blocks_per_step >= 1
@@ -425,6 +432,34 @@ int taches_server_add(taches_server* sv, taches_stream* s, int64_t tag, double s
                       int64_t n_total_blocks, const float* x_host, int64_t x_cstride, float* y_host, int64_t y_cstride,
                       int32_t n_swaps, const double* swap_times_s, const float* const* swap_ir_dev,
                       const int32_t* swap_len);
+
+/* Register a stream served in two segments of its IR (Eq. (1) is linear in
+ * h): `head` (block B, capacity >= head_len) convolves with h[0, H), H =
+ * head_len, and is advanced every tick as in taches_server_add; `rest`
+ * (block Br, a multiple of B with Br <= H) convolves with h[H, L) and is
+ * advanced once per Br samples, its outputs z kept on the device in the
+ * ring z_dev [C][z_len] (caller-owned, z_len >= Br + B, alive until the
+ * stream finishes; contents need no initialisation); the result is
+ * y[n] = y_head[n] + z[n - H] (FP32 add), written to y_host as in
+ * taches_server_add.  Both streams must be attached to the server's pool,
+ * FP32 precision, with the same channel count; `head` must take
+ * max_blocks_per_step blocks per call, `rest` at least one.  The library
+ * loads the two segments of ir_dev [ir_len] (H < ir_len <= H + rest
+ * capacity) as the initial IR, and of each change's IR (swap_len[i] in the
+ * same range) when it applies: the rest segment takes over at the same
+ * input sample as the head (an IR change inside a rest block), so two
+ * changes applying inside one rest block are refused, the initial IR
+ * counting as a change at sample 0.  A tick runs a head
+ * block once the rest blocks whose outputs it needs are enqueued (their
+ * last sample arrives no later than the head block's), and holds rest
+ * blocks while their outputs would overwrite ring entries not yet added.
+ * Latency records and outputs are the head's; rest blocks have none.
+ * TACHES_EINVAL for sizes or streams outside these rules. */
+int taches_server_add_segmented(taches_server* sv, taches_stream* head, taches_stream* rest, int32_t head_len,
+                                float* z_dev, int32_t z_len, int64_t tag, double start_s, int64_t n_in_blocks,
+                                int64_t n_total_blocks, const float* x_host, int64_t x_cstride, float* y_host,
+                                int64_t y_cstride, const float* ir_dev, int32_t ir_len, int32_t n_swaps,
+                                const double* swap_times_s, const float* const* swap_ir_dev, const int32_t* swap_len);
 
 /* One tick at the current server clock: if any block is due, enqueues its
  * step (input copy, pool step, output copy) on the pool's stream; then waits

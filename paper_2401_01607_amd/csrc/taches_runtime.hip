@@ -1149,19 +1149,31 @@ struct taches_pool {
   hipEvent_t tab_free[2] = {nullptr, nullptr};
   bool tab_pending[2] = {false, false};
   int tab_cur = 0;
-  hipEvent_t detach_ev = nullptr;
+  hipEvent_t detach_ev = nullptr, attach_ev = nullptr;
   int force_r = 0;
   bool use_graph = false;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  hipGraphNode_t copy_node = nullptr;
-  int graph_r = 0, graph_nwg = 0;
-  bool graph_mixed = false;
-  size_t graph_cap = 0;
+  // captured [table copy -> batched kernel], one per (tile r, FP64 tails
+  // present, launched workgroups rounded up to 256 * 2^k): steps of similar
+  // shape replay the same graph
+  struct Graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraphNode_t copy_node = nullptr;
+    int nwg = 0;
+    size_t cap = 0;
+  };
+  static constexpr int kGraphs = 4 * 2 * 8;
+  Graph graphs[kGraphs];
+  int64_t captures = 0;
   int64_t replays = 0;
   int last_items = 0, last_wg = 0, last_r = 0;
   double last_plan_ms = 0.0;
-  double last_imbalance = 0.0;
+  // estimate of the last step's busiest workgroup over the mean; with few
+  // items per workgroup it is played out on request (taches_pool_get_info),
+  // off the step's path
+  mutable double last_imbalance = 0.0;
+  mutable bool imbalance_pending = false;
+  int64_t last_total_work = 0;
   uint64_t steps = 0;                             // step counter (duplicate detection)
   // device time of the batched launches: a ring of event pairs; completed
   // launches are added to dev_ms_total when they are found complete
@@ -1178,46 +1190,47 @@ struct taches_pool {
   std::vector<char> enqueued;
   std::vector<PoolItem> items;
   std::vector<uint32_t> order;
-  std::vector<int64_t> heap;
+  std::vector<uint16_t> keys;
+  mutable std::vector<int64_t> heap;
 };
 
 namespace {
 
+void drop_graph(taches_pool::Graph& g) {
+  if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  if (g.graph) (void)hipGraphDestroy(g.graph);
+  g = taches_pool::Graph{};
+}
+
 void pool_drop_graph(taches_pool* p) {
-  if (p->exec) (void)hipGraphExecDestroy(p->exec);
-  if (p->graph) (void)hipGraphDestroy(p->graph);
-  p->exec = nullptr;
-  p->graph = nullptr;
-  p->copy_node = nullptr;
+  for (taches_pool::Graph& g : p->graphs) drop_graph(g);
 }
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-// Indices of `items` ordered by work, largest first; equal works keep their
-// order (stable LSD radix sort, three 11-bit digits; a comparison sort for
-// works of 2^33 or more).
+// Indices of `items` in decreasing work, to within 1/8: one counting pass
+// on a key made of the work's binary exponent and the three bits after its
+// leading one (works in the same eighth of an octave share a bucket and
+// keep their list order).  Largest-first dealing by the work queue needs no
+// finer order.
 template <typename ItemT, typename WorkOf>
-void sort_by_work_desc(const std::vector<ItemT>& items, std::vector<uint32_t>& order, WorkOf work_of) {
+void order_by_work_desc(const std::vector<ItemT>& items, std::vector<uint32_t>& order, std::vector<uint16_t>& keys,
+                        WorkOf work_of) {
+  constexpr int kKeys = 64 * 8;
   const size_t n = items.size();
+  keys.resize(n);
   order.resize(n);
-  for (size_t i = 0; i < n; ++i) order[i] = (uint32_t)i;
-  int64_t mx = 0;
-  for (const ItemT& it : items) mx = std::max(mx, work_of(it));
-  if (mx >= (int64_t(1) << 33)) {
-    std::stable_sort(order.begin(), order.end(),
-                     [&](uint32_t a, uint32_t b) { return work_of(items[a]) > work_of(items[b]); });
-    return;
+  uint32_t cnt[kKeys + 1] = {};
+  for (size_t i = 0; i < n; ++i) {
+    const uint64_t w = (uint64_t)std::max<int64_t>(1, work_of(items[i]));
+    const int e = 63 - __builtin_clzll(w);
+    const int m = (int)((e >= 3 ? (w >> (e - 3)) : (w << (3 - e))) & 7);
+    const int key = (63 - e) * 8 + (7 - m);   // ascending key = descending work
+    keys[i] = (uint16_t)key;
+    cnt[key + 1] += 1;
   }
-  std::vector<uint32_t> tmp(n);
-  std::vector<uint32_t> cnt(2049);
-  for (int pass = 0; pass < 3; ++pass) {
-    const int sh = 11 * pass;
-    std::fill(cnt.begin(), cnt.end(), 0u);
-    for (uint32_t i : order) cnt[2047 - ((work_of(items[i]) >> sh) & 2047) + 1] += 1;
-    for (int d = 0; d < 2048; ++d) cnt[d + 1] += cnt[d];
-    for (uint32_t i : order) tmp[cnt[2047 - ((work_of(items[i]) >> sh) & 2047)]++] = i;
-    order.swap(tmp);
-  }
+  for (int k = 0; k < kKeys; ++k) cnt[k + 1] += cnt[k];
+  for (size_t i = 0; i < n; ++i) order[cnt[keys[i]]++] = (uint32_t)i;
 }
 
 // Add the device time of every completed launch of the ring to the total
@@ -1299,14 +1312,15 @@ taches_pool* taches_pool_create(int32_t max_streams, int64_t hbm_budget_bytes, i
             hipStreamCreateWithFlags(&p->capture, hipStreamNonBlocking) == hipSuccess &&
             hipEventCreateWithFlags(&p->tab_free[0], hipEventDisableTiming) == hipSuccess &&
             hipEventCreateWithFlags(&p->tab_free[1], hipEventDisableTiming) == hipSuccess &&
-            hipEventCreateWithFlags(&p->detach_ev, hipEventDisableTiming) == hipSuccess;
+            hipEventCreateWithFlags(&p->detach_ev, hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&p->attach_ev, hipEventDisableTiming) == hipSuccess;
   for (int k = 0; ok && k < taches_pool::kRing; ++k)
     ok = hipEventCreate(&p->ev_beg[k]) == hipSuccess && hipEventCreate(&p->ev_end[k]) == hipSuccess;
   if (!ok) {
     fail(TACHES_EDEVICE, "pool stream/event creation failed");
     if (p->own) (void)hipStreamDestroy(p->own);
     if (p->capture) (void)hipStreamDestroy(p->capture);
-    for (hipEvent_t ev : {p->tab_free[0], p->tab_free[1], p->detach_ev})
+    for (hipEvent_t ev : {p->tab_free[0], p->tab_free[1], p->detach_ev, p->attach_ev})
       if (ev) (void)hipEventDestroy(ev);
     for (int k = 0; k < taches_pool::kRing; ++k) {
       if (p->ev_beg[k]) (void)hipEventDestroy(p->ev_beg[k]);
@@ -1326,7 +1340,7 @@ int taches_pool_destroy(taches_pool* p) {
   pool_drop_graph(p);
   for (int k = 0; k < 2; ++k) (void)hipHostFree(p->tab_pin[k]);
   (void)hipFree(p->tab_dev);
-  for (hipEvent_t ev : {p->tab_free[0], p->tab_free[1], p->detach_ev})
+  for (hipEvent_t ev : {p->tab_free[0], p->tab_free[1], p->detach_ev, p->attach_ev})
     if (ev) (void)hipEventDestroy(ev);
   for (int k = 0; k < taches_pool::kRing; ++k) {
     (void)hipEventDestroy(p->ev_beg[k]);
@@ -1357,7 +1371,12 @@ int taches_pool_attach(taches_pool* p, taches_stream* s) {
   if (p->used + s->device_bytes > p->budget)
     return fail(TACHES_ENOMEM, "HBM budget: %lld + %lld bytes exceed %lld", (long long)p->used, (long long)s->device_bytes,
                 (long long)p->budget);
-  HIPCHK(hipStreamSynchronize(s->stream));
+  if (s->stream != p->stream) {
+    // the pool's later work waits for what is queued on the stream's HIP
+    // stream (initialisation, reset, IR copies); the host does not wait
+    HIPCHK(hipEventRecord(p->attach_ev, s->stream));
+    HIPCHK(hipStreamWaitEvent(p->stream, p->attach_ev, 0));
+  }
   s->stream_before_pool = s->stream;
   s->stream = p->stream;
   s->pool = p;
@@ -1410,7 +1429,31 @@ int taches_pool_get_info(const taches_pool* p, taches_pool_info* out) {
   out->last_workgroups = p->last_wg;
   out->last_r = p->last_r;
   out->graph_replays = p->replays;
+  out->graph_captures = p->captures;
   out->last_plan_ms = p->last_plan_ms;
+  if (p->imbalance_pending) {
+    // the last step's list played out on the estimated works: each item
+    // goes to the least loaded workgroup (a min-heap of workgroup loads)
+    std::vector<int64_t>& heap = p->heap;
+    heap.assign(std::max(1, p->last_wg), 0);
+    for (uint32_t i : p->order) {
+      heap[0] += p->items[i].work;
+      size_t j = 0;
+      for (;;) {
+        const size_t l = 2 * j + 1, r = l + 1;
+        size_t m = j;
+        if (l < heap.size() && heap[l] < heap[m]) m = l;
+        if (r < heap.size() && heap[r] < heap[m]) m = r;
+        if (m == j) break;
+        std::swap(heap[j], heap[m]);
+        j = m;
+      }
+    }
+    const double mean = (double)p->last_total_work / (double)heap.size();
+    const int64_t mx = *std::max_element(heap.begin(), heap.end());
+    p->last_imbalance = mean > 0 ? (double)mx / mean : 1.0;
+    p->imbalance_pending = false;
+  }
   out->last_imbalance = p->last_imbalance;
   out->last_device_ms = -1.0;
   float ms = 0.f;
@@ -1491,6 +1534,7 @@ int taches_pool_step_strided(taches_pool* p, int32_t n, taches_stream* const* st
   typedef PoolItem Item;
   std::vector<Item>& items = p->items;
   items.clear();
+  p->imbalance_pending = false;
   int nwg = 0, r = 0;
   bool mixed = false;   // some gather stream keeps an FP64 tail
   const int ng = (int)gather_ids.size();
@@ -1588,6 +1632,14 @@ int taches_pool_step_strided(taches_pool* p, int32_t n, taches_stream* const* st
     const int64_t by_work = std::max<int64_t>(1, total_work / max_work);
     nwg = (int)std::max<int64_t>(std::min<int64_t>(256, (int64_t)items.size()),
                                            std::min<int64_t>(256LL * per_cu, by_work));
+    // launched workgroups rounded up to 256 * 2^k (at most the resident
+    // maximum), so that steps of similar size replay one captured graph; the
+    // extra workgroups find the queue empty and leave
+    {
+      int64_t b = 256;
+      while (b < nwg && b < wg_max) b *= 2;
+      nwg = (int)std::min<int64_t>(b, wg_max);
+    }
     // Workgroups take the items from a shared counter in list order.  With
     // merged runs or many small items, the list stays in stream and tile
     // order (neighbouring tiles share IR windows and inputs in L2);
@@ -1603,34 +1655,16 @@ int taches_pool_step_strided(taches_pool* p, int32_t n, taches_stream* const* st
       order.resize(n_items);
       for (size_t k = 0; k < n_items; ++k) order[k] = (uint32_t)k;
     } else {
-      sort_by_work_desc(items, order, [](const Item& it) { return it.work; });
+      order_by_work_desc(items, order, p->keys, [](const Item& it) { return it.work; });
     }
     // reported estimate of the busiest workgroup's work over the mean: the
     // greedy bound (mean + largest item) / mean when items are many (at
     // least 8 per workgroup), else the queue played out on the estimated
-    // works (a heap of workgroup loads)
+    // works, on request
     const double mean = (double)total_work / nwg;
-    if (in_order || n_items >= 8 * (size_t)nwg) {
-      p->last_imbalance = mean > 0 ? (mean + (double)max_work) / mean : 1.0;
-    } else {
-      std::vector<int64_t>& heap = p->heap;   // min-heap of workgroup loads
-      heap.assign(nwg, 0);
-      for (uint32_t i : order) {
-        heap[0] += items[i].work;
-        size_t j = 0;
-        for (;;) {
-          const size_t l = 2 * j + 1, r = l + 1;
-          size_t m = j;
-          if (l < heap.size() && heap[l] < heap[m]) m = l;
-          if (r < heap.size() && heap[r] < heap[m]) m = r;
-          if (m == j) break;
-          std::swap(heap[j], heap[m]);
-          j = m;
-        }
-      }
-      const int64_t mx = *std::max_element(heap.begin(), heap.end());
-      p->last_imbalance = mean > 0 ? (double)mx / mean : 1.0;
-    }
+    p->last_total_work = total_work;
+    p->imbalance_pending = !(in_order || n_items >= 8 * (size_t)nwg);
+    if (!p->imbalance_pending) p->last_imbalance = mean > 0 ? (mean + (double)max_work) / mean : 1.0;
   }
   // ---- split classes: calls, tile and fragment prefix sums ----
   const int mt = taches::toeplitz_rows_per_tile();
@@ -1714,42 +1748,42 @@ int taches_pool_step_strided(taches_pool* p, int32_t n, taches_stream* const* st
     int rc2 = pool_account(p, false);
     if (rc2 != TACHES_OK) return rc2;
   }
+  taches_pool::Graph* pg = nullptr;
   if (has_gather && p->use_graph) {
-    // capture [table copy -> batched kernel] once per (tile, workgroups,
-    // table capacity); later steps only resize the copy and replay
-    if (!p->exec || p->graph_r != r || p->graph_nwg != nwg || p->graph_cap != p->tab_cap ||
-        p->graph_mixed != mixed) {
-      pool_drop_graph(p);
+    int b = 0;
+    while ((256 << b) < nwg && b < 7) ++b;
+    pg = &p->graphs[((r / 4 - 1) * 2 + (mixed ? 1 : 0)) * 8 + b];
+    if (!pg->exec || pg->nwg != nwg || pg->cap != p->tab_cap) {
+      drop_graph(*pg);
       HIPCHK(hipStreamBeginCapture(p->capture, hipStreamCaptureModeThreadLocal));
       hipError_t e1 = hipMemcpyAsync(p->tab_dev, pin, p->tab_cap, hipMemcpyHostToDevice, p->capture);
       hipError_t e2 = taches::launch_gather_batched(p->tab_dev, nwg, r, mixed, p->capture);
-      hipError_t e3 = hipStreamEndCapture(p->capture, &p->graph);
+      hipError_t e3 = hipStreamEndCapture(p->capture, &pg->graph);
       if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess)
         return fail(TACHES_EDEVICE, "graph capture failed: %s", hipGetErrorString(e1 != hipSuccess ? e1 : e2 != hipSuccess ? e2 : e3));
-      HIPCHK(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
+      HIPCHK(hipGraphInstantiate(&pg->exec, pg->graph, nullptr, nullptr, 0));
       size_t nn = 0;
-      HIPCHK(hipGraphGetNodes(p->graph, nullptr, &nn));
+      HIPCHK(hipGraphGetNodes(pg->graph, nullptr, &nn));
       std::vector<hipGraphNode_t> nodes(nn);
-      HIPCHK(hipGraphGetNodes(p->graph, nodes.data(), &nn));
+      HIPCHK(hipGraphGetNodes(pg->graph, nodes.data(), &nn));
       for (auto nd : nodes) {
         hipGraphNodeType ty;
         HIPCHK(hipGraphNodeGetType(nd, &ty));
-        if (ty == hipGraphNodeTypeMemcpy) p->copy_node = nd;
+        if (ty == hipGraphNodeTypeMemcpy) pg->copy_node = nd;
       }
-      p->graph_r = r;
-      p->graph_mixed = mixed;
-      p->graph_nwg = nwg;
-      p->graph_cap = p->tab_cap;
+      pg->nwg = nwg;
+      pg->cap = p->tab_cap;
+      p->captures += 1;
     }
   }
-  const bool replay = has_gather && p->use_graph && p->copy_node &&
-                      hipGraphExecMemcpyNodeSetParams1D(p->exec, p->copy_node, p->tab_dev, pin, bytes,
+  const bool replay = pg && pg->copy_node &&
+                      hipGraphExecMemcpyNodeSetParams1D(pg->exec, pg->copy_node, p->tab_dev, pin, bytes,
                                                         hipMemcpyHostToDevice) == hipSuccess;
   // ---- enqueue: from here on, failures commit what was enqueued ----
   hipError_t e = hipEventRecord(p->ev_beg[ev], p->stream);
   if (e == hipSuccess) {
     if (replay) {
-      e = hipGraphLaunch(p->exec, p->stream);
+      e = hipGraphLaunch(pg->exec, p->stream);
       if (e == hipSuccess) p->replays += 1;
     } else {
       e = hipMemcpyAsync(p->tab_dev, pin, bytes, hipMemcpyHostToDevice, p->stream);

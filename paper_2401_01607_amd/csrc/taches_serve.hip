@@ -15,6 +15,20 @@
 // Abstract and Section 6): a step's range of blocks ends before such a
 // block, which starts the next range.
 //
+// A stream may be served in two segments of its IR (linearity of Eq. (1)):
+// the head h[0, H) on a stream of block B advanced every tick, and the rest
+// h[H, L) on a second stream of block Br = K * B (Br <= H), whose output z
+// enters the result H samples later, y[n] = y_head[n] + z[n - H].  The rest
+// stream keeps the long tail and is advanced once per Br samples instead of
+// once per tick, so a tick reads and writes H + B tail slots of the stream
+// instead of L + B.  Its outputs stay on the device in a ring [C][Z] owned
+// by the caller; after the pool step, one launch stores them into the ring
+// and a second adds the ring into the head outputs before those are copied
+// back.  A head block is run only once the rest blocks it needs have been
+// enqueued (by arrival they always have: their last sample comes no later
+// than the head block's, as Br <= H), and rest blocks wait while their
+// outputs would overwrite ring entries not yet added.
+//
 // Ticks overlap with the device: a tick enqueues its step (input copy, pool
 // step, output copy) and then waits for the previous tick's step, so the
 // host gathers and plans step k + 1 while the device runs step k, and the
@@ -48,6 +62,14 @@ struct ServeStream {
   std::vector<int32_t> swap_L;
   size_t swap_next = 0;
   std::vector<int64_t> swap_blocks;   // block index at which each applied swap took effect
+  // two-segment streams (rs != nullptr): the rest segment h[H, L)
+  taches_stream* rs = nullptr;
+  int32_t H = 0, Br = 0, r_cap = 1;
+  int64_t r_in = 0, r_total = 0, r_next = 0;
+  float* z = nullptr;                 // device ring [C][Z] of the rest segment's outputs
+  int32_t Z = 0;
+  std::vector<int64_t> swap_s;        // input sample at which each IR change applies (within the input)
+  size_t r_swap_next = 0;
 };
 
 // First block k of a stream with start time k * B / fs >= t (k >= k_min).
@@ -57,6 +79,33 @@ int64_t first_block_at(double t, int32_t B, double fs, int64_t k_min) {
   while (k > k_min && (double)((k - 1) * B) / fs >= t) --k;
   while ((double)(k * B) / fs < t) ++k;
   return k;
+}
+
+// One ring operation of a step: C rows of len outputs (row stride y_cs) in
+// the step's device staging, against ring positions p0, p0 + 1, ... (mod Z)
+// of the rows of z.
+struct ZOp {
+  float* y;
+  float* z;
+  int32_t y_cs, len, C, Z, p0, pad_;
+};
+
+// add == 0: store the outputs into the ring; add != 0: add the ring entries
+// into the outputs.  One workgroup per operation.
+__global__ __launch_bounds__(256) void k_zring(const ZOp* __restrict__ ops, int add) {
+  const ZOp o = ops[blockIdx.x];
+  for (int c = 0; c < o.C; ++c) {
+    float* y = o.y + (int64_t)c * o.y_cs;
+    float* z = o.z + (int64_t)c * o.Z;
+    for (int i = threadIdx.x; i < o.len; i += blockDim.x) {
+      int pos = o.p0 + i;
+      if (pos >= o.Z) pos -= o.Z;
+      if (add)
+        y[i] += z[pos];
+      else
+        z[pos] = y[i];
+    }
+  }
 }
 
 }  // namespace
@@ -71,6 +120,7 @@ struct FlightRange {
   int32_t n;
   int64_t yoff;
   double start_s;
+  double tick_s;   // server clock at the start of the tick that enqueued the range
   bool last;   // the stream's last block: it finishes when this step completes
 };
 
@@ -115,6 +165,8 @@ struct taches_server {
   std::vector<int32_t> a_n;
   std::vector<int32_t> a_idx;
   std::vector<int64_t> a_k0, a_xoff, a_yoff;
+  std::vector<char> a_rest;          // range of a rest segment (outputs stay on the device)
+  std::vector<int64_t> r_end;        // per registered stream: rest blocks enqueued after this tick
   // records
   std::vector<float> lat_s;
   std::vector<int32_t> lat_B;
@@ -140,8 +192,11 @@ ServeStream* find_tag(taches_server* sv, int64_t tag, bool with_done = false) {
 
 // Larger staging (called with no step in flight).
 int grow(taches_server* sv, size_t floats) {
+  // capacity grows in large steps (at least 4 M floats, then 4x): a larger
+  // staging costs pinned allocations and frees, which stall the tick
+  constexpr size_t kMinFloats = size_t(1) << 22;
   if (floats > sv->pin_cap) {
-    const size_t cap = std::max(floats, 2 * sv->pin_cap);
+    const size_t cap = std::max({floats, 4 * sv->pin_cap, kMinFloats});
     for (int k = 0; k < 2; ++k) {
       (void)hipHostFree(sv->x_pin[k]);
       (void)hipHostFree(sv->y_pin[k]);
@@ -155,7 +210,7 @@ int grow(taches_server* sv, size_t floats) {
     sv->pin_cap = cap;
   }
   if (floats > sv->dev_cap) {
-    const size_t cap = std::max(floats, 2 * sv->dev_cap);
+    const size_t cap = std::max({floats, 4 * sv->dev_cap, kMinFloats});
     (void)hipFree(sv->x_dev);
     (void)hipFree(sv->y_dev);
     sv->x_dev = sv->y_dev = nullptr;
@@ -196,6 +251,9 @@ int complete_flight(taches_server* sv) {
       if (arrival < sv->warmup_s) continue;
       sv->lat_s.push_back((float)(done - arrival));
       sv->lat_B.push_back(q.B);
+      sv->stats.recorded += 1;
+      sv->stats.pickup_s += q.tick_s - arrival;
+      sv->stats.service_s += done - q.tick_s;
     }
     if (q.last) sv->finished.push_back(q.tag);
   }
@@ -267,39 +325,43 @@ int taches_server_flush(taches_server* sv) {
 
 double taches_server_clock(const taches_server* sv) { return sv ? clock_s(sv) : -1.0; }
 
-int taches_server_add(taches_server* sv, taches_stream* s, int64_t tag, double start_s, int64_t n_in_blocks,
-                      int64_t n_total_blocks, const float* x_host, int64_t x_cstride, float* y_host, int64_t y_cstride,
-                      int32_t n_swaps, const double* swap_times_s, const float* const* swap_ir_dev,
-                      const int32_t* swap_len) {
+namespace {
+
+// Checks shared by both registrations; fills the record of a one-segment
+// stream.
+int fill_record(taches_server* sv, taches_stream* s, int64_t tag, double start_s, int64_t n_in_blocks,
+                int64_t n_total_blocks, const float* x_host, int64_t x_cstride, float* y_host, int64_t y_cstride,
+                int32_t n_swaps, const double* swap_times_s, const float* const* swap_ir_dev, const int32_t* swap_len,
+                int32_t swap_len_min, int32_t swap_len_max, ServeStream* out, taches_info* inf) {
   if (!sv || !s) return taches::set_error(TACHES_EINVAL, "serving: NULL server or stream");
-  taches_info inf;
-  int rc = taches_get_info(s, &inf);
+  int rc = taches_get_info(s, inf);
   if (rc != TACHES_OK) return rc;
   if (!taches::stream_in_pool(s, sv->pool)) return taches::set_error(TACHES_EINVAL, "serving: stream not attached to the pool");
   if (find_tag(sv, tag, true)) return taches::set_error(TACHES_EINVAL, "serving: tag %lld already registered", (long long)tag);
   if (n_in_blocks < 1 || n_total_blocks < n_in_blocks) return taches::set_error(TACHES_EINVAL, "serving: block counts");
-  if (sv->max_blocks > inf.max_blocks_per_call)
+  if (sv->max_blocks > inf->max_blocks_per_call)
     return taches::set_error(TACHES_EINVAL, "serving: stream takes %d blocks per call, the server %d",
-                             inf.max_blocks_per_call, sv->max_blocks);
-  const int64_t need = n_in_blocks * inf.block_size;
+                             inf->max_blocks_per_call, sv->max_blocks);
+  const int64_t need = n_in_blocks * inf->block_size;
   if (!x_host || x_cstride < need)
     return taches::set_error(TACHES_EINVAL, "serving: input buffer shorter than the input blocks");
-  if (y_host && y_cstride < n_total_blocks * inf.block_size)
+  if (y_host && y_cstride < n_total_blocks * inf->block_size)
     return taches::set_error(TACHES_EINVAL, "serving: output buffer shorter than the stream");
   if (n_swaps < 0 || (n_swaps > 0 && (!swap_times_s || !swap_ir_dev || !swap_len)))
     return taches::set_error(TACHES_EINVAL, "serving: swap arrays");
+  if (swap_len_max <= 0) swap_len_max = inf->max_ir_len;
   for (int i = 0; i < n_swaps; ++i) {
-    if (!swap_ir_dev[i] || swap_len[i] < 1 || swap_len[i] > inf.max_ir_len)
+    if (!swap_ir_dev[i] || swap_len[i] < swap_len_min || swap_len[i] > swap_len_max)
       return taches::set_error(TACHES_EINVAL, "serving: swap %d IR", i);
     if (i > 0 && swap_times_s[i] < swap_times_s[i - 1])
       return taches::set_error(TACHES_EINVAL, "serving: swap times not ascending");
   }
-  ServeStream r;
+  ServeStream& r = *out;
   r.s = s;
   r.tag = tag;
   r.start_s = start_s;
-  r.B = inf.block_size;
-  r.C = inf.channels;
+  r.B = inf->block_size;
+  r.C = inf->channels;
   r.n_in = n_in_blocks;
   r.n_total = n_total_blocks;
   r.x = x_host;
@@ -309,6 +371,80 @@ int taches_server_add(taches_server* sv, taches_stream* s, int64_t tag, double s
   r.swap_t.assign(swap_times_s, swap_times_s + n_swaps);
   r.swap_h.assign(swap_ir_dev, swap_ir_dev + n_swaps);
   r.swap_L.assign(swap_len, swap_len + n_swaps);
+  return TACHES_OK;
+}
+
+}  // namespace
+
+int taches_server_add(taches_server* sv, taches_stream* s, int64_t tag, double start_s, int64_t n_in_blocks,
+                      int64_t n_total_blocks, const float* x_host, int64_t x_cstride, float* y_host, int64_t y_cstride,
+                      int32_t n_swaps, const double* swap_times_s, const float* const* swap_ir_dev,
+                      const int32_t* swap_len) {
+  ServeStream r;
+  taches_info inf;
+  int rc = fill_record(sv, s, tag, start_s, n_in_blocks, n_total_blocks, x_host, x_cstride, y_host, y_cstride, n_swaps,
+                       swap_times_s, swap_ir_dev, swap_len, 1, 0, &r, &inf);
+  if (rc != TACHES_OK) return rc;
+  sv->st.push_back(std::move(r));
+  return TACHES_OK;
+}
+
+int taches_server_add_segmented(taches_server* sv, taches_stream* head, taches_stream* rest, int32_t head_len,
+                                float* z_dev, int32_t z_len, int64_t tag, double start_s, int64_t n_in_blocks,
+                                int64_t n_total_blocks, const float* x_host, int64_t x_cstride, float* y_host,
+                                int64_t y_cstride, const float* ir_dev, int32_t ir_len, int32_t n_swaps,
+                                const double* swap_times_s, const float* const* swap_ir_dev, const int32_t* swap_len) {
+  if (!sv || !head || !rest || !ir_dev || !z_dev)
+    return taches::set_error(TACHES_EINVAL, "serving: NULL server, stream, IR or ring");
+  taches_info ri, hi0;
+  int rc = taches_get_info(rest, &ri);
+  if (rc == TACHES_OK) rc = taches_get_info(head, &hi0);
+  if (rc != TACHES_OK) return rc;
+  if (!taches::stream_in_pool(rest, sv->pool)) return taches::set_error(TACHES_EINVAL, "serving: rest stream not attached to the pool");
+  if (hi0.precision != TACHES_PREC_FP32 || ri.precision != TACHES_PREC_FP32)
+    return taches::set_error(TACHES_EINVAL, "serving: two-segment streams need FP32 precision");
+  const int32_t H = head_len, Br = ri.block_size;
+  const int32_t lmin = H + 1, lmax = std::min<int64_t>((int64_t)H + ri.max_ir_len, INT32_MAX);
+  ServeStream r;
+  taches_info hi;
+  rc = fill_record(sv, head, tag, start_s, n_in_blocks, n_total_blocks, x_host, x_cstride, y_host, y_cstride, n_swaps,
+                   swap_times_s, swap_ir_dev, swap_len, lmin, lmax, &r, &hi);
+  if (rc != TACHES_OK) return rc;
+  if (ri.channels != hi.channels) return taches::set_error(TACHES_EINVAL, "serving: head and rest channel counts differ");
+  if (Br % hi.block_size != 0 || H < Br || H > hi.max_ir_len)
+    return taches::set_error(TACHES_EINVAL, "serving: segments need B | Br <= H <= head capacity (B %d, Br %d, H %d)",
+                             hi.block_size, Br, H);
+  if (ir_len < lmin || ir_len > lmax) return taches::set_error(TACHES_EINVAL, "serving: IR of %d taps for H = %d", ir_len, H);
+  if ((int64_t)z_len < (int64_t)Br + hi.block_size)
+    return taches::set_error(TACHES_EINVAL, "serving: ring of %d entries shorter than Br + B", z_len);
+  const int32_t B = hi.block_size;
+  // input sample at which each change applies (the head's rule: the first
+  // block starting at or after its time); changes after the input never apply
+  // (the initial IR counts as a change at sample 0: a rest block takes one
+  // IR from its start and at most one change inside)
+  std::vector<int64_t> ss;
+  int64_t prev = 0;
+  for (int i = 0; i < n_swaps; ++i) {
+    const int64_t k = first_block_at(swap_times_s[i], B, sv->fs, 0);
+    if (k >= n_in_blocks) break;
+    const int64_t smp = k * B;
+    if (smp != prev && smp / Br == prev / Br)
+      return taches::set_error(TACHES_EINVAL, "serving: two IR changes inside one rest block of %d samples", Br);
+    ss.push_back(smp);
+    prev = smp;
+  }
+  rc = taches_set_ir_device(head, ir_dev, H);
+  if (rc == TACHES_OK) rc = taches_set_ir_device(rest, ir_dev + H, ir_len - H);
+  if (rc != TACHES_OK) return rc;
+  r.rs = rest;
+  r.H = H;
+  r.Br = Br;
+  r.r_cap = std::max(1, std::min(sv->max_blocks, ri.max_blocks_per_call));
+  r.r_in = (n_in_blocks * B + Br - 1) / Br;
+  r.r_total = std::max(r.r_in, (n_total_blocks * B - H + Br - 1) / Br);
+  r.z = z_dev;
+  r.Z = z_len;
+  r.swap_s = std::move(ss);
   sv->st.push_back(std::move(r));
   return TACHES_OK;
 }
@@ -326,18 +462,65 @@ int taches_server_tick(taches_server* sv, taches_server_tick_info* out) {
   sv->a_k0.clear();
   sv->a_xoff.clear();
   sv->a_yoff.clear();
-  size_t xf = 0, yf = 0;
+  sv->a_rest.clear();
+  sv->r_end.assign(sv->st.size(), 0);
+  size_t xf = 0, yf = 0, ryf = 0;   // input floats; head and rest output floats
+  auto push_range = [&](taches_stream* s, int32_t n, size_t i, int64_t k0, bool in, size_t len, bool rest) {
+    sv->a_s.push_back(s);
+    sv->a_n.push_back(n);
+    sv->a_idx.push_back((int32_t)i);
+    sv->a_k0.push_back(k0);
+    sv->a_xoff.push_back(in ? (int64_t)xf : -1);
+    if (in) xf += len;
+    sv->a_yoff.push_back(rest ? (int64_t)ryf : (int64_t)yf);
+    (rest ? ryf : yf) += len;
+    sv->a_rest.push_back(rest ? 1 : 0);
+  };
   for (size_t i = 0; i < sv->st.size(); ++i) {
     ServeStream& r = sv->st[i];
+    // rest segment first: a head block runs once the rest blocks it needs are enqueued
+    if (r.rs) {
+      int64_t rend = r.r_next;
+      if (r.r_next < r.r_total) {
+        int64_t arr = (int64_t)std::floor((now - r.start_s) * fs / r.Br);
+        arr = std::min(std::max<int64_t>(arr, 0), r.r_total);
+        // ring entries below `consumed` have been added by enqueued steps
+        const int64_t consumed = std::max<int64_t>(0, r.next * r.B - r.H);
+        const int64_t j0 = r.r_next;
+        int64_t end = std::min(std::min(arr, j0 + r.r_cap), (consumed + r.Z) / r.Br);
+        if (end > j0) {
+          const bool in = j0 < r.r_in;
+          if (in) {
+            // changes applying inside or at the start of block j0
+            while (r.r_swap_next < r.swap_s.size() && r.swap_s[r.r_swap_next] < (j0 + 1) * r.Br) {
+              const size_t q = r.r_swap_next;
+              const int64_t off = std::max<int64_t>(0, r.swap_s[q] - j0 * r.Br);
+              const float* h = r.swap_h[q] + r.H;
+              const int32_t L = r.swap_L[q] - r.H;
+              int rc = off == 0 ? taches_set_ir_device(r.rs, h, L) : taches_set_ir_at(r.rs, h, L, (int32_t)off, 1);
+              if (rc != TACHES_OK) return rc;
+              ++r.r_swap_next;
+            }
+            end = std::min(end, r.r_in);
+            if (r.r_swap_next < r.swap_s.size()) end = std::min(end, r.swap_s[r.r_swap_next] / r.Br);
+          }
+          push_range(r.rs, (int32_t)(end - j0), i, j0, in, (size_t)r.C * (end - j0) * r.Br, true);
+          rend = end;
+        }
+      }
+      sv->r_end[i] = rend;
+    }
     int64_t arrived = (int64_t)std::floor((now - r.start_s) * fs / r.B);
     arrived = std::min(std::max<int64_t>(arrived, 0), r.n_total);
+    if (r.rs) arrived = std::min(arrived, (sv->r_end[i] * r.Br + r.H) / r.B);
     if (arrived <= r.next) continue;
     const int64_t k0 = r.next;
     const bool is_in = k0 < r.n_in;
     // IR changes due by the start of this range's first block apply to it
     if (is_in) {
       while (r.swap_next < r.swap_t.size() && r.swap_t[r.swap_next] <= (double)(k0 * r.B) / fs) {
-        int rc = taches_set_ir_device(r.s, r.swap_h[r.swap_next], r.swap_L[r.swap_next]);
+        const int32_t L = r.rs ? r.H : r.swap_L[r.swap_next];
+        int rc = taches_set_ir_device(r.s, r.swap_h[r.swap_next], L);
         if (rc != TACHES_OK) return rc;
         r.swap_blocks.push_back(k0);
         ++r.swap_next;
@@ -348,16 +531,7 @@ int taches_server_tick(taches_server* sv, taches_server_tick_info* out) {
       end = std::min(end, r.n_in);
       if (r.swap_next < r.swap_t.size()) end = std::min(end, first_block_at(r.swap_t[r.swap_next], r.B, fs, k0 + 1));
     }
-    const int32_t n = (int32_t)(end - k0);
-    sv->a_s.push_back(r.s);
-    sv->a_n.push_back(n);
-    sv->a_idx.push_back((int32_t)i);
-    sv->a_k0.push_back(k0);
-    const size_t len = (size_t)r.C * n * r.B;
-    sv->a_xoff.push_back(is_in ? (int64_t)xf : -1);
-    if (is_in) xf += len;
-    sv->a_yoff.push_back((int64_t)yf);
-    yf += len;
+    push_range(r.s, (int32_t)(end - k0), i, k0, is_in, (size_t)r.C * (end - k0) * r.B, false);
   }
   const size_t m = sv->a_s.size();
   auto next_due = [&]() {
@@ -373,11 +547,32 @@ int taches_server_tick(taches_server* sv, taches_server_tick_info* out) {
     if (out) *out = info;
     return TACHES_OK;
   }
+  // rest outputs follow the head outputs in the staging; only the head
+  // outputs are copied back
+  for (size_t j = 0; j < m; ++j)
+    if (sv->a_rest[j]) sv->a_yoff[j] += (int64_t)yf;
+  // ring operations: stores of the rest outputs, then adds into the head
+  // outputs (a head range's outputs before sample H get nothing)
+  auto add_skip = [&](size_t j) -> int64_t {
+    const ServeStream& r = sv->st[sv->a_idx[j]];
+    return std::max<int64_t>(0, r.H - sv->a_k0[j] * r.B);
+  };
+  size_t n_store = 0, n_add = 0;
+  for (size_t j = 0; j < m; ++j) {
+    if (sv->a_rest[j])
+      ++n_store;
+    else if (sv->st[sv->a_idx[j]].rs && add_skip(j) < (int64_t)sv->a_n[j] * sv->st[sv->a_idx[j]].B)
+      ++n_add;
+  }
+  const size_t n_ops = n_store + n_add;
+  const size_t ops_off = (xf * 4 + 255) & ~(size_t)255;   // bytes: the ops follow the input
+  const size_t x_floats = n_ops ? (ops_off + n_ops * sizeof(ZOp) + 3) / 4 : xf;
+  const size_t y_floats = yf + ryf;
   const hipStream_t hs = taches::pool_stream(sv->pool);
   int rc = TACHES_OK;
-  if (std::max(xf, yf) > std::min(sv->pin_cap, sv->dev_cap)) {
+  if (std::max(x_floats, y_floats) > std::min(sv->pin_cap, sv->dev_cap)) {
     rc = complete_flight(sv);   // staging in use by the step in flight
-    if (rc == TACHES_OK) rc = grow(sv, std::max(xf, yf));
+    if (rc == TACHES_OK) rc = grow(sv, std::max(x_floats, y_floats));
     if (rc != TACHES_OK) return rc;
   }
   const int buf = sv->tick_buf;
@@ -385,10 +580,34 @@ int taches_server_tick(taches_server* sv, taches_server_tick_info* out) {
   for (size_t j = 0; j < m; ++j) {
     if (sv->a_xoff[j] < 0) continue;
     const ServeStream& r = sv->st[sv->a_idx[j]];
-    const size_t row = (size_t)sv->a_n[j] * r.B;
+    const int32_t Bj = sv->a_rest[j] ? r.Br : r.B;
+    const int64_t row = (int64_t)sv->a_n[j] * Bj;
+    const int64_t s0 = sv->a_k0[j] * Bj;
+    // a rest block may reach past the input: zeros there
+    const int64_t avail = std::min(row, std::max<int64_t>(0, r.n_in * r.B - s0));
     float* dst = sv->x_pin[buf] + sv->a_xoff[j];
-    for (int c = 0; c < r.C; ++c)
-      std::memcpy(dst + c * row, r.x + c * r.x_cs + sv->a_k0[j] * r.B, row * 4);
+    for (int c = 0; c < r.C; ++c) {
+      std::memcpy(dst + c * row, r.x + c * r.x_cs + s0, (size_t)avail * 4);
+      if (avail < row) std::memset(dst + c * row + avail, 0, (size_t)(row - avail) * 4);
+    }
+  }
+  if (n_ops) {
+    ZOp* o = reinterpret_cast<ZOp*>(reinterpret_cast<unsigned char*>(sv->x_pin[buf]) + ops_off);
+    size_t qs = 0, qa = n_store;
+    for (size_t j = 0; j < m; ++j) {
+      const ServeStream& r = sv->st[sv->a_idx[j]];
+      if (sv->a_rest[j]) {
+        const int32_t len = sv->a_n[j] * r.Br;
+        o[qs++] = ZOp{sv->y_dev + sv->a_yoff[j], r.z, len, len, r.C, r.Z, (int32_t)((sv->a_k0[j] * r.Br) % r.Z), 0};
+      } else if (r.rs) {
+        const int32_t len = sv->a_n[j] * r.B;
+        const int64_t skip = add_skip(j);
+        if (skip >= len) continue;
+        const int64_t m0 = sv->a_k0[j] * r.B + skip - r.H;   // ring index of the first output that gets one
+        o[qa++] = ZOp{sv->y_dev + sv->a_yoff[j] + skip, r.z, len, (int32_t)(len - skip), r.C, r.Z,
+                      (int32_t)(m0 % r.Z), 0};
+      }
+    }
   }
   sv->a_x.resize(m);
   sv->a_y.resize(m);
@@ -401,21 +620,31 @@ int taches_server_tick(taches_server* sv, taches_server_tick_info* out) {
     if (rc != TACHES_OK) return rc;
   }
   const double t_launch = clock_s(sv);
-  if (xf > 0) {
-    const hipError_t e = hipMemcpyAsync(sv->x_dev, sv->x_pin[buf], xf * 4, hipMemcpyHostToDevice, hs);
+  if (x_floats > 0) {
+    const hipError_t e = hipMemcpyAsync(sv->x_dev, sv->x_pin[buf], x_floats * 4, hipMemcpyHostToDevice, hs);
     if (e != hipSuccess) return taches::set_error(TACHES_EDEVICE, "serving: input copy: %s", hipGetErrorString(e));
   }
   rc = taches_pool_step(sv->pool, (int32_t)m, sv->a_s.data(), sv->a_x.data(), sv->a_y.data(), sv->a_n.data());
   if (rc != TACHES_OK) return rc;
   // the step is committed on the host: from here on, state advances even if
   // a later call reports an error
+  for (size_t j = 0; j < m; ++j) {
+    ServeStream& r = sv->st[sv->a_idx[j]];
+    (sv->a_rest[j] ? r.r_next : r.next) = sv->a_k0[j] + sv->a_n[j];
+  }
   const int evk = sv->ev_next;
   sv->ev_next = (sv->ev_next + 1) % taches_server::kEv;
   {
-    hipError_t e = hipMemcpyAsync(sv->y_pin[buf], sv->y_dev, yf * 4, hipMemcpyDeviceToHost, hs);
+    hipError_t e = hipSuccess;
+    if (n_ops) {
+      const ZOp* dops = reinterpret_cast<const ZOp*>(reinterpret_cast<unsigned char*>(sv->x_dev) + ops_off);
+      if (n_store) hipLaunchKernelGGL(k_zring, dim3((unsigned)n_store), dim3(256), 0, hs, dops, 0);
+      if (n_add) hipLaunchKernelGGL(k_zring, dim3((unsigned)n_add), dim3(256), 0, hs, dops + n_store, 1);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess && yf > 0) e = hipMemcpyAsync(sv->y_pin[buf], sv->y_dev, yf * 4, hipMemcpyDeviceToHost, hs);
     if (e == hipSuccess) e = hipEventRecord(sv->ev[evk], hs);
-    for (size_t j = 0; j < m; ++j) sv->st[sv->a_idx[j]].next = sv->a_k0[j] + sv->a_n[j];
-    if (e != hipSuccess) return taches::set_error(TACHES_EDEVICE, "serving: output copy: %s", hipGetErrorString(e));
+    if (e != hipSuccess) return taches::set_error(TACHES_EDEVICE, "serving: ring or output copy: %s", hipGetErrorString(e));
   }
   const double t_queued = clock_s(sv);
   // ---- the new step's book-keeping; finished streams leave the server ----
@@ -424,16 +653,22 @@ int taches_server_tick(taches_server* sv, taches_server_tick_info* out) {
   nf.buf = buf;
   nf.ev = evk;
   nf.ranges.reserve(m);
-  int64_t blocks = 0, macs = 0;
+  int64_t blocks = 0, macs = 0, max_n = 0;
+  int32_t heads = 0;
   for (size_t j = 0; j < m; ++j) {
     const ServeStream& r = sv->st[sv->a_idx[j]];
     const int32_t n = sv->a_n[j];
-    blocks += n;
-    if (sv->a_k0[j] < r.n_in) {
+    const bool rest = sv->a_rest[j] != 0;
+    if ((rest ? sv->a_k0[j] < r.r_in : sv->a_k0[j] < r.n_in)) {
       taches_info inf;
-      if (taches_get_info(r.s, &inf) == TACHES_OK) macs += (int64_t)n * r.B * inf.active_len * r.C;
+      if (taches_get_info(rest ? r.rs : r.s, &inf) == TACHES_OK)
+        macs += (int64_t)n * (rest ? r.Br : r.B) * inf.active_len * r.C;
     }
-    nf.ranges.push_back(FlightRange{r.tag, r.y, r.y_cs, r.C, r.B, sv->a_k0[j], n, sv->a_yoff[j], r.start_s,
+    if (rest) continue;
+    ++heads;
+    blocks += n;
+    max_n = std::max<int64_t>(max_n, n);
+    nf.ranges.push_back(FlightRange{r.tag, r.y, r.y_cs, r.C, r.B, sv->a_k0[j], n, sv->a_yoff[j], r.start_s, now,
                                     sv->a_k0[j] + n >= r.n_total});
   }
   for (size_t i = sv->st.size(); i-- > 0;) {
@@ -450,7 +685,7 @@ int taches_server_tick(taches_server* sv, taches_server_tick_info* out) {
   if (rc != TACHES_OK) return rc;
   const double done = clock_s(sv);
   info.next_due_s = next_due();
-  info.streams = (int32_t)m;
+  info.streams = heads;
   info.blocks = blocks;
   info.done_s = done;
   info.host_ms = (t_launch - now) * 1e3;
@@ -461,9 +696,8 @@ int taches_server_tick(taches_server* sv, taches_server_tick_info* out) {
   sv->stats.busy_s += done - now;
   sv->stats.gather_s += t_launch - now;
   sv->stats.launch_s += t_queued - t_launch;
-  sv->stats.max_blocks_in_a_range = std::max<int64_t>(
-      sv->stats.max_blocks_in_a_range, *std::max_element(sv->a_n.begin(), sv->a_n.end()));
-  sv->stats.bytes_in += (int64_t)xf * 4;
+  sv->stats.max_blocks_in_a_range = std::max(sv->stats.max_blocks_in_a_range, max_n);
+  sv->stats.bytes_in += (int64_t)x_floats * 4;
   sv->stats.bytes_out += (int64_t)yf * 4;
   if (out) *out = info;
   return TACHES_OK;

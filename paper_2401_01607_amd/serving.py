@@ -37,6 +37,8 @@ the device runs; a block still counts as done when wait() returns.
 from __future__ import annotations
 
 import math
+import sys
+import threading
 import time
 from collections import deque
 from dataclasses import dataclass, field
@@ -371,10 +373,61 @@ def tail_for(T, req, precision: int) -> int:
     """The tail the library's AUTO rule gives a request's own IR length
     (streams are opened with a longer capacity class, on which AUTO would
     pick FP64 for some IRs that do not need it)."""
-    cfg = T.taches_config_default(req.block, req.ir_len)
-    cfg.channels = req.channels
+    return tail_for_shape(T, req.block, req.ir_len, req.channels, precision)
+
+
+def tail_for_shape(T, B: int, L: int, C: int, precision: int) -> int:
+    cfg = T.taches_config_default(B, L)
+    cfg.channels = C
     cfg.precision = precision
     return T.TACHES_TAIL_FP64 if T.taches_tail_is_fp64(cfg) == 1 else T.TACHES_TAIL_FP32
+
+
+def change_blocks(req, fs: float = W.FS) -> list:
+    """Input blocks at which a request's IR changes apply: the first block
+    that starts at or after each change time (changes after the input do
+    not apply)."""
+    n_in = max(1, math.ceil(req.n_samples() / req.block))
+    out = []
+    for t in req.swap_times_s:
+        k = max(0, math.ceil(t * fs / req.block - 1e-9))
+        while k > 0 and (k - 1) * req.block / fs >= t:
+            k -= 1
+        while k * req.block / fs < t:
+            k += 1
+        if k >= n_in:
+            break
+        out.append(k)
+    return out
+
+
+def segments_for(req, precision: int, fs: float = W.FS):
+    """(H, Br, Z) when a real-time request is served in two IR segments,
+    else None.  The head h[0, H) is advanced every tick, the rest h[H, L)
+    once per Br samples (Br a power of two, a multiple of B, H = Br), so a
+    tick reads and writes about H + B tail slots of the stream instead of
+    L + B.  Br is the power of two nearest sqrt(24 L), within
+    [max(B, 256), 2048]: with ticks about 0.5 ms apart (24 samples at
+    48 kHz) it balances the head's traffic per tick, ~ H, against the
+    rest's, ~ L per Br samples.  Only FP32 requests whose IR is at least
+    four rest blocks long, and whose IR changes (the initial IR counting as
+    one at sample 0) apply in different rest blocks; Z (the rest outputs kept on the device) lets the rest stream
+    run up to 4 Br + 8 B samples ahead of the outputs the head has used."""
+    from . import taches as T
+    if precision != T.TACHES_PREC_FP32:
+        return None
+    L, B = req.ir_len, req.block
+    br = 1 << max(0, int(round(math.log2(math.sqrt(24.0 * L)))))
+    br = max(max(B, 256), min(2048, br))
+    if L < 4 * br:
+        return None
+    prev = 0   # the initial IR applies from sample 0
+    for k in change_blocks(req, fs):
+        smp = k * B
+        if smp != prev and smp // br == prev // br:
+            return None
+        prev = smp
+    return br, br, 4 * br + 8 * B
 
 
 class GpuExecutor:
@@ -618,15 +671,21 @@ class RealtimeServer:
 
     BANK_SECONDS = 70.0
 
+    REST_BLOCKS_PER_CALL = 4
+    PREPARE_AHEAD = 32
+
     def __init__(self, requests, max_streams: int, hbm_budget_bytes: int, precision: int = 0,
                  use_graph: bool = True, max_ir_len: int = 262_144, seed: int = 9,
-                 keep_outputs=(), max_blocks_per_step: int = 64, warmup_s: float = 0.0):
+                 keep_outputs=(), max_blocks_per_step: int = 64, warmup_s: float = 0.0,
+                 segments: bool = True):
         import torch
         from . import taches as T
         self.T, self.torch = T, torch
         self.pending = deque(sorted(requests, key=lambda r: r.arrival_s))
         self.queue: deque = deque()
-        self.pool = T.Pool(max_streams, hbm_budget_bytes, use_graph=use_graph)
+        # a two-segment request holds two streams of the pool
+        slots = max_streams * (2 if segments and precision == T.TACHES_PREC_FP32 else 1)
+        self.pool = T.Pool(slots, hbm_budget_bytes, use_graph=use_graph)
         self.sv = T.taches_server_create(self.pool.h, float(W.FS), max_blocks_per_step, warmup_s)
         self.precision = precision
         self.max_blocks_per_step = max_blocks_per_step
@@ -640,13 +699,27 @@ class RealtimeServer:
         self.budget = hbm_budget_bytes
         self.keep = set(keep_outputs)
         self.kept: dict = {}         # rid -> host output array
-        self.free: dict = {}         # recycled streams by (B, C, IR class, tail)
-        self.idle_bytes = 0
-        self.live: dict = {}         # rid -> (stream, key, req)
+        self.free: dict = {}         # recycled streams by (C, B, IR capacity, tail, blocks per call, precision)
+        self.segments = segments
+        self.live: dict = {}         # rid -> (streams, keys, req, ring or None, device bytes)
+        # admission work that does not touch the pool (opening streams,
+        # drawing IRs) runs on a preparing thread during run_realtime; the
+        # budget is kept here: bytes of admitted requests, of prepared ones
+        # and of idle recycled streams
+        self._lock = threading.Lock()
+        self._to_prepare: deque = deque()
+        self._prepared: dict = {}    # rid -> (streams, keys, ring, irs, device bytes)
+        self._thread = None
+        self._stop = False
+        self.live_bytes = self.reserved_bytes = self.idle_bytes = 0
         self.req_by_rid = {r.rid: r for r in requests}
         self.stats = Stats()
         self.lat, self.lat_b = [], []
         self.refused = 0
+        self.loops, self.python_s = 0, 0.0   # loop iterations; time in admission and retirement
+        self.n_segmented = 0
+        self.slow_loops = []   # (clock, admit ms, tick ms, retire ms, admitted) of iterations over 5 ms
+        self.admit_s = {"attach": 0.0, "register": 0.0}
 
     # -- requests ------------------------------------------------------------
     def _draw_irs(self, req):
@@ -677,62 +750,153 @@ class RealtimeServer:
     def tail_for(self, req) -> int:
         return tail_for(self.T, req, self.precision)
 
+    def segments_for(self, req):
+        """(H, Br, Z) if the request is served in two IR segments, else None."""
+        return segments_for(req, self.precision) if self.segments else None
+
     @staticmethod
     def ir_class(L: int) -> int:
         return GpuExecutor.ir_class(L)
 
-    def _open(self, req):
+    def _shapes(self, req):
+        """Streams a request needs: (B, IR capacity, tail, blocks per call,
+        precision) of its one stream, or of its head and rest streams; and
+        its segments (or None)."""
+        seg = self.segments_for(req)
+        C, B, L = req.channels, req.block, req.ir_len
+        if seg is None:
+            return [(B, min(self.ir_class(L), self.max_ir_len), self.tail_for(req), self.max_blocks_per_step,
+                     self.precision)], None
+        H, br, _ = seg
         T = self.T
-        tail = self.tail_for(req)
-        key = (req.block, req.channels, min(GpuExecutor.ir_class(req.ir_len), self.max_ir_len), tail)
-        lst = self.free.get(key)
-        if lst:
-            s = lst.pop()
-            self.idle_bytes -= s.info().device_bytes
-            return s, key
-        cfg = T.taches_config_default(req.block, key[2])
-        cfg.channels = req.channels
-        cfg.max_blocks_per_call = self.max_blocks_per_step
-        cfg.precision = self.precision
+        fp32 = T.TACHES_PREC_FP32
+        head = (B, H, tail_for_shape(T, B, H, C, fp32), self.max_blocks_per_step, fp32)
+        rest = (br, min(self.ir_class(L - H), self.max_ir_len), tail_for_shape(T, br, L - H, C, fp32),
+                self.REST_BLOCKS_PER_CALL, fp32)
+        return [head, rest], seg
+
+    def _cfg(self, C: int, shape):
+        B, cap, tail, mb, prec = shape
+        cfg = self.T.taches_config_default(B, cap)
+        cfg.channels = C
+        cfg.max_blocks_per_call = mb
+        cfg.precision = prec
         cfg.tail = tail
-        need = T.taches_bytes_for(cfg)
-        used = self.pool.info().used_bytes
-        while used + self.idle_bytes + need > self.budget and self.idle_bytes > 0:
-            k_big = max((k for k in self.free if self.free[k]), key=lambda k: k[2])
-            victim = self.free[k_big].pop()
-            self.idle_bytes -= victim.info().device_bytes
-            victim.close()
-        if used + self.idle_bytes + need > self.budget:
+        return cfg
+
+    def _prepare(self, req):
+        """Everything an admission needs that does not touch the pool: the
+        request's streams (recycled or new), its ring of rest outputs
+        (two-segment requests) and its IRs.  The device bytes are reserved
+        against the HBM budget (idle recycled streams are closed, largest
+        first, to make room); AdmissionRefused if they do not fit.  Runs on
+        the preparing thread."""
+        T, torch = self.T, self.torch
+        shapes, seg = self._shapes(req)
+        C = req.channels
+        keys = [(C,) + sh for sh in shapes]
+        sizes = [T.taches_bytes_for(self._cfg(C, sh)) for sh in shapes]
+        ring_bytes = 4 * C * seg[2] if seg else 0
+        victims, taken = [], []
+        with self._lock:
+            need = ring_bytes + sum(n for k, n in zip(keys, sizes) if not self.free.get(k))
+            while self.live_bytes + self.reserved_bytes + self.idle_bytes + need > self.budget:
+                cands = [k for k in self.free if self.free[k] and k not in keys]
+                if not cands:
+                    break
+                v = self.free[max(cands, key=lambda k: k[2])].pop()
+                self.idle_bytes -= v.info().device_bytes
+                victims.append(v)
+            if self.live_bytes + self.reserved_bytes + self.idle_bytes + need > self.budget:
+                self.refused += 1
+                refused = True
+            else:
+                refused = False
+                for k in keys:
+                    lst = self.free.get(k)
+                    s = lst.pop() if lst else None
+                    if s is not None:
+                        self.idle_bytes -= s.info().device_bytes
+                    taken.append(s)
+                amt = need + sum(n for s, n in zip(taken, sizes) if s is not None)
+                self.reserved_bytes += amt
+        for v in victims:
+            v.close()
+        if refused:
             raise AdmissionRefused("budget")
-        return T.Stream(req.block, key[2], channels=req.channels, max_blocks_per_call=self.max_blocks_per_step,
-                        precision=self.precision, tail=tail), key
+        streams = []
+        for s, sh in zip(taken, shapes):
+            if s is None:
+                B, cap, tail, mb, prec = sh
+                s = T.Stream(B, cap, channels=C, max_blocks_per_call=mb, precision=prec, tail=tail)
+            streams.append(s)
+        ring = torch.empty((C, seg[2]), device="cuda", dtype=torch.float32) if seg else None
+        irs = self._draw_irs(req)
+        nbytes = sum(s.info().device_bytes for s in streams) + ring_bytes
+        with self._lock:
+            self.reserved_bytes += nbytes - amt   # the reservation at the streams' actual sizes
+        return streams, keys, ring, irs, nbytes
+
+    def _prepare_loop(self) -> None:
+        """The preparing thread: requests in admission order, at most
+        PREPARE_AHEAD of them prepared and not yet admitted."""
+        while not self._stop:
+            with self._lock:
+                req = self._to_prepare[0] if self._to_prepare and len(self._prepared) < self.PREPARE_AHEAD else None
+            if req is None:
+                time.sleep(0.0002)
+                continue
+            try:
+                item = self._prepare(req)
+            except AdmissionRefused:
+                time.sleep(0.0005)   # wait for retirements to free budget
+                continue
+            with self._lock:
+                self._to_prepare.popleft()
+                self._prepared[req.rid] = item
 
     def _recycle(self, s, key):
         s.reset()
-        self.free.setdefault(key, []).append(s)
-        self.idle_bytes += s.info().device_bytes
+        with self._lock:
+            self.free.setdefault(key, []).append(s)
+            self.idle_bytes += s.info().device_bytes
 
-    def _admit(self, now: float) -> None:
+    def _admit(self, now: float, limit: int = 4) -> None:
+        """Admit queued requests in FIFO order once prepared: attach their
+        streams to the pool (no host wait) and register them with the
+        server; at most `limit` per call."""
         T = self.T
         while self.pending and self.pending[0].arrival_s <= now:
-            self.queue.append(self.pending.popleft())
-        while self.queue:
+            req = self.pending.popleft()
+            self.queue.append(req)
+            with self._lock:
+                self._to_prepare.append(req)
+        if self._thread is None:   # no preparing thread (admission outside run_realtime)
+            while self._to_prepare:
+                req = self._to_prepare[0]
+                try:
+                    item = self._prepare(req)
+                except AdmissionRefused:
+                    break
+                self._to_prepare.popleft()
+                self._prepared[req.rid] = item
+        while self.queue and limit > 0:
             req = self.queue[0]
             if len(self.live) >= self.max_streams:
                 self.refused += 1
                 return
-            try:
-                s, key = self._open(req)
-            except AdmissionRefused:
-                self.refused += 1
+            with self._lock:
+                item = self._prepared.pop(req.rid, None)
+            if item is None:
                 return
-            if self.pool.attach(s) != T.TACHES_OK:
-                self._recycle(s, key)
-                self.refused += 1
-                return
+            limit -= 1
+            c0 = time.perf_counter()
+            streams, keys, ring, irs, nbytes = item
+            for s in streams:
+                _ = T._check(self.pool.attach(s), "taches_pool_attach")
             self.queue.popleft()
-            self.irs[req.rid] = self._draw_irs(req)
-            s.set_ir(self.ir(req, 0))
+            c1 = time.perf_counter()
+            self.irs[req.rid] = irs
             n_in = self.n_input_blocks(req)
             n_total = n_in + math.ceil((req.ir_len - 1) / req.block)
             y = None
@@ -740,9 +904,24 @@ class RealtimeServer:
                 y = np.zeros((req.channels, n_total * req.block), np.float32)
                 self.kept[req.rid] = y
             swaps = [self.ir(req, v + 1) for v in range(len(req.swap_times_s))]
-            _ = T._check(T.taches_server_add(self.sv, s.h, req.rid, now, n_in, n_total, self.input_signal(req), y,
-                                             req.swap_times_s, swaps), "taches_server_add")
-            self.live[req.rid] = (s, key, req)
+            if ring is None:
+                streams[0].set_ir(self.ir(req, 0))
+                rc = T.taches_server_add(self.sv, streams[0].h, req.rid, now, n_in, n_total, self.input_signal(req),
+                                         y, req.swap_times_s, swaps)
+                _ = T._check(rc, "taches_server_add")
+            else:
+                self.n_segmented += 1
+                rc = T.taches_server_add_segmented(self.sv, streams[0].h, streams[1].h, self.segments_for(req)[0],
+                                                   ring, req.rid, now, n_in, n_total, self.input_signal(req), y,
+                                                   self.ir(req, 0), req.swap_times_s, swaps)
+                _ = T._check(rc, "taches_server_add_segmented")
+            with self._lock:
+                self.reserved_bytes -= nbytes
+                self.live_bytes += nbytes
+            self.live[req.rid] = (streams, keys, req, ring, nbytes)
+            c2 = time.perf_counter()
+            self.admit_s["attach"] += c1 - c0
+            self.admit_s["register"] += c2 - c1
             self.stats.admitted += 1
             if req.arrival_s >= self.warmup_s:
                 self.stats.queue_waits_s.append(now - req.arrival_s)
@@ -750,15 +929,19 @@ class RealtimeServer:
 
     def _retire(self) -> None:
         for rid in self.T.taches_server_take_finished(self.sv, 256).tolist():
-            s, key, req = self.live.pop(rid)
-            self.pool.detach(s)
-            self._recycle(s, key)
+            streams, keys, req, ring, nbytes = self.live.pop(rid)
+            for s in streams:
+                self.pool.detach(s)
+            with self._lock:
+                self.live_bytes -= nbytes
+            for s, k in zip(streams, keys):   # the ring's last use has completed with the stream's last step
+                self._recycle(s, k)
             if rid not in self.keep:
                 del self.irs[rid]   # every copy out of them has run: the stream's steps are done
             self.stats.completed += 1
 
     def _drain_records(self) -> None:
-        lat, bs = self.T.taches_server_take_latencies(self.sv)
+        lat, bs = self.T.taches_server_take_latencies(self.sv, 1 << 18)
         if lat.size:
             self.lat.append(lat)
             self.lat_b.append(bs)
@@ -768,13 +951,49 @@ class RealtimeServer:
         T = self.T
         sv = self.sv
         last_drain = 0.0
+        clock = time.perf_counter
+        # the preparing thread runs Python between its library calls: hand
+        # the interpreter back and forth often, so the tick loop never waits
+        # long for it
+        switch = sys.getswitchinterval()
+        sys.setswitchinterval(1e-4)
+        self._stop = False
+        self._thread = threading.Thread(target=self._prepare_loop, name="taches-admission", daemon=True)
+        self._thread.start()
+        try:
+            self._serve(duration_s, sleep, clock, last_drain)
+        finally:
+            self._stop = True
+            self._thread.join()
+            self._thread = None
+            sys.setswitchinterval(switch)
+        T.taches_server_flush(sv)
+        self._retire()
+        wall = T.taches_server_clock(sv)
+        self._drain_records()
+        return self.summary(wall)
+
+    def _serve(self, duration_s, sleep, clock, last_drain) -> None:
+        T = self.T
+        sv = self.sv
         while True:
             now = T.taches_server_clock(sv)
             if now >= duration_s:
                 break
+            t0 = clock()
+            n_adm = self.stats.admitted
             self._admit(now)
+            t1 = clock()
             tk = T.taches_server_tick(sv)
+            t2 = clock()
             self._retire()
+            t3 = clock()
+            self.loops += 1
+            self.python_s += (t1 - t0) + (t3 - t2)
+            if t3 - t0 > 0.005 and now >= self.warmup_s:   # a loop iteration over 5 ms: keep its breakdown
+                self.slow_loops.append((round(now, 3), round((t1 - t0) * 1e3, 2), round((t2 - t1) * 1e3, 2),
+                                        round((t3 - t2) * 1e3, 2), self.stats.admitted - n_adm,
+                                        round(tk.host_ms, 2), int(tk.streams)))
             if not tk.streams:
                 nxt = tk.next_due_s
                 if self.pending:
@@ -782,14 +1001,9 @@ class RealtimeServer:
                 wait = min(nxt, duration_s) - T.taches_server_clock(sv)
                 if wait > 0:
                     sleep(min(wait, 0.0005))
-            if now - last_drain > 1.0:
+            if now - last_drain > 0.2:   # a few hundred thousand records at a time
                 self._drain_records()
                 last_drain = now
-        T.taches_server_flush(sv)
-        self._retire()
-        wall = T.taches_server_clock(sv)
-        self._drain_records()
-        return self.summary(wall)
 
     def summary(self, wall_s: float) -> dict:
         T = self.T
@@ -811,6 +1025,17 @@ class RealtimeServer:
         if st.ticks:
             out["tick_ms_mean"] = {k: round(getattr(st, k + "_s") / st.ticks * 1e3, 4)
                                    for k in ("busy", "gather", "launch", "wait", "scatter")}
+        if self.loops:
+            out["loop_ms_mean"] = round(wall_s / self.loops * 1e3, 4)
+            out["loop_python_ms_mean"] = round(self.python_s / self.loops * 1e3, 4)
+        if st.recorded:
+            out["latency_split_ms_mean"] = {"arrival_to_tick": round(st.pickup_s / st.recorded * 1e3, 4),
+                                            "tick_to_host_outputs": round(st.service_s / st.recorded * 1e3, 4)}
+        out["two_segment_requests"] = self.n_segmented
+        if self.stats.admitted:
+            out["admission_ms_mean"] = {k: round(v / self.stats.admitted * 1e3, 4) for k, v in self.admit_s.items()}
+        out["slow_loops"] = {"count": len(self.slow_loops),
+                             "longest": sorted(self.slow_loops, key=lambda r: -(r[1] + r[2] + r[3]))[:8]}
         return out
 
     def kept_outputs(self, rid):
@@ -829,10 +1054,15 @@ class RealtimeServer:
         if self.sv:
             T.taches_server_destroy(self.sv)
             self.sv = None
-        for s, _, _ in self.live.values():
-            self.pool.detach(s)
-            s.close()
+        for streams, *_ in self.live.values():
+            for s in streams:
+                self.pool.detach(s)
+                s.close()
         self.live.clear()
+        for streams, *_ in self._prepared.values():
+            for s in streams:
+                s.close()
+        self._prepared.clear()
         for lst in self.free.values():
             for s in lst:
                 s.close()

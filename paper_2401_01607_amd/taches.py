@@ -54,7 +54,8 @@ class taches_pool_info(ctypes.Structure):
                 ("last_items", ctypes.c_int32), ("last_workgroups", ctypes.c_int32),
                 ("last_r", ctypes.c_int32), ("pad_", ctypes.c_int32), ("graph_replays", ctypes.c_int64),
                 ("last_plan_ms", ctypes.c_double), ("last_imbalance", ctypes.c_double),
-                ("last_device_ms", ctypes.c_double), ("device_ms_total", ctypes.c_double)]
+                ("last_device_ms", ctypes.c_double), ("device_ms_total", ctypes.c_double),
+                ("graph_captures", ctypes.c_int64)]
 
 
 class taches_server_tick_info(ctypes.Structure):
@@ -68,7 +69,8 @@ class taches_server_stats(ctypes.Structure):
                 ("max_blocks_in_a_range", ctypes.c_int64), ("bytes_in", ctypes.c_int64),
                 ("bytes_out", ctypes.c_int64), ("busy_s", ctypes.c_double), ("gather_s", ctypes.c_double),
                 ("launch_s", ctypes.c_double), ("wait_s", ctypes.c_double), ("scatter_s", ctypes.c_double),
-                ("streams", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+                ("streams", ctypes.c_int32), ("pad_", ctypes.c_int32), ("recorded", ctypes.c_int64),
+                ("pickup_s", ctypes.c_double), ("service_s", ctypes.c_double)]
 
 
 _vp, _i32, _i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
@@ -116,6 +118,8 @@ _SIGS = {
     "taches_server_clock": (ctypes.c_double, [_vp]),
     "taches_server_add": (ctypes.c_int, [_vp, _vp, _i64, ctypes.c_double, _i64, _i64, _vp, _i64, _vp, _i64, _i32,
                                          _vp, _vp, _vp]),
+    "taches_server_add_segmented": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp, _i32, _i64, ctypes.c_double, _i64,
+                                                   _i64, _vp, _i64, _vp, _i64, _vp, _i32, _i32, _vp, _vp, _vp]),
     "taches_server_tick": (ctypes.c_int, [_vp, _P(taches_server_tick_info)]),
     "taches_server_flush": (ctypes.c_int, [_vp]),
     "taches_server_take_finished": (ctypes.c_int, [_vp, _vp, _i32]),
@@ -520,11 +524,7 @@ def taches_server_clock(sv) -> float:
     return float(lib.taches_server_clock(sv))
 
 
-def taches_server_add(sv, stream, tag: int, start_s: float, n_in_blocks: int, n_total_blocks: int,
-                      x_host: np.ndarray, y_host, swap_times_s=(), swap_irs=()) -> int:
-    """x_host: [C][x_cstride] float32 host array (kept alive by the caller);
-    y_host: [C][y_cstride] float32 host array or None; swap_irs: device
-    tensors (kept alive by the caller until applied)."""
+def _server_buffers(x_host, y_host, swap_times_s, swap_irs):
     x_host = np.atleast_2d(x_host)
     if x_host.dtype != np.float32 or x_host.strides[1] != 4 or x_host.strides[0] % 4:
         raise TypeError("x_host must be a float32 array with contiguous rows")
@@ -541,9 +541,33 @@ def taches_server_add(sv, stream, tag: int, start_s: float, n_in_blocks: int, n_
     t = np.ascontiguousarray(swap_times_s, np.float64)
     hp = np.array([ir.data_ptr() for ir in swap_irs], np.uint64)
     hl = np.array([ir.numel() for ir in swap_irs], np.int32)
-    return lib.taches_server_add(sv, stream, tag, start_s, n_in_blocks, n_total_blocks, _host_ptr(x_host),
-                                 x_cs, y_ptr, y_cs, n, _host_ptr(t) if n else None,
-                                 _host_ptr(hp) if n else None, _host_ptr(hl) if n else None)
+    swaps = (n, _host_ptr(t) if n else None, _host_ptr(hp) if n else None, _host_ptr(hl) if n else None)
+    # the arrays behind the pointers stay referenced by the returned tuple
+    return (_host_ptr(x_host), x_cs, y_ptr, y_cs) + swaps, (x_host, y_host, t, hp, hl)
+
+
+def taches_server_add(sv, stream, tag: int, start_s: float, n_in_blocks: int, n_total_blocks: int,
+                      x_host: np.ndarray, y_host, swap_times_s=(), swap_irs=()) -> int:
+    """x_host: [C][x_cstride] float32 host array (kept alive by the caller);
+    y_host: [C][y_cstride] float32 host array or None; swap_irs: device
+    tensors (kept alive by the caller until applied)."""
+    args, _keep = _server_buffers(x_host, y_host, swap_times_s, swap_irs)
+    return lib.taches_server_add(sv, stream, tag, start_s, n_in_blocks, n_total_blocks, *args)
+
+
+def taches_server_add_segmented(sv, head, rest, head_len: int, z_ring, tag: int, start_s: float, n_in_blocks: int,
+                                n_total_blocks: int, x_host: np.ndarray, y_host, ir, swap_times_s=(),
+                                swap_irs=()) -> int:
+    """As taches_server_add for a stream served in two IR segments: head
+    and rest stream handles, z_ring a [C][Z] float32 device tensor, ir the
+    initial device IR (all IRs kept alive by the caller until applied)."""
+    if z_ring.dtype != torch.float32 or not z_ring.is_cuda or not z_ring.is_contiguous() or z_ring.dim() != 2:
+        raise TypeError("z_ring must be a contiguous [C][Z] float32 device tensor")
+    args, _keep = _server_buffers(x_host, y_host, swap_times_s, swap_irs)
+    x_ptr, x_cs, y_ptr, y_cs, n, t, hp, hl = args
+    return lib.taches_server_add_segmented(sv, head, rest, head_len, z_ring.data_ptr(), z_ring.shape[1], tag, start_s,
+                                           n_in_blocks, n_total_blocks, x_ptr, x_cs, y_ptr, y_cs, ir.data_ptr(),
+                                           ir.numel(), n, t, hp, hl)
 
 
 def taches_server_tick(sv) -> taches_server_tick_info:

@@ -185,6 +185,59 @@ def _swap_rule_blocks(req):
     return out
 
 
+def _replay_segmented(srv, req, swaps, x, n_in, n_total):
+    """A two-segment request on its own: its head and rest streams (the
+    server's configurations) run block by block, the head's IR changes at
+    its blocks, the rest's at the same input samples inside its blocks;
+    y = head + rest shifted by H, added in FP32."""
+    import torch
+    T = binding()
+    shapes, (H, br, _) = srv._shapes(req)
+    C, B = req.channels, req.block
+    head, rest = [T.Stream(b, cap, channels=C, max_blocks_per_call=1, precision=prec, tail=tail)
+                  for b, cap, tail, _, prec in shapes]
+    irs = [srv.ir(req, v) for v in range(len(swaps) + 1)]
+    head.set_ir(irs[0][:H])
+    rest.set_ir(irs[0][H:])
+    at_block = {b: v + 1 for v, b in enumerate(swaps)}      # the last change of a block wins
+    yh = []
+    for k in range(n_total):
+        if k in at_block:
+            head.set_ir(irs[at_block[k]][:H])
+        y = torch.empty((C, B), device="cuda")
+        if k < n_in:
+            head.process_async(torch.from_numpy(np.ascontiguousarray(x[:, k * B:(k + 1) * B])).cuda(), y)
+        else:
+            head.process_blocks(None, y, 1)
+        yh.append(y)
+    r_in = -(-n_in * B // br)
+    r_total = max(r_in, -(-(n_total * B - H) // br))
+    xr = np.zeros((C, r_in * br), np.float32)
+    xr[:, :n_in * B] = x[:, :n_in * B]
+    at_rest = {}
+    for v, b in enumerate(swaps):
+        at_rest[b * B // br] = (v + 1, b * B % br)
+    yr = []
+    for j in range(r_total):
+        if j in at_rest:
+            v, off = at_rest[j]
+            rest.set_ir(irs[v][H:], offset=off)
+        y = torch.empty((C, br), device="cuda")
+        if j < r_in:
+            rest.process_async(torch.from_numpy(np.ascontiguousarray(xr[:, j * br:(j + 1) * br])).cuda(), y)
+        else:
+            rest.process_blocks(None, y, 1)
+        yr.append(y)
+    head.synchronize()
+    rest.synchronize()
+    out = torch.cat(yh, dim=1).cpu().numpy()
+    z = torch.cat(yr, dim=1).cpu().numpy()
+    head.close()
+    rest.close()
+    out[:, H:] += z[:, :out.shape[1] - H]      # float32 + float32, rounded to float32
+    return out
+
+
 def _server_check(precision, seed, tol_max):
     from paper_2401_01607_amd.serving import RealtimeServer
     T = binding()
@@ -196,7 +249,7 @@ def _server_check(precision, seed, tol_max):
     st = srv.run_realtime(1.0 + 0.5 + 8192 / 48000 + 1.5)
     assert st["completed"] == st["admitted"] == len(reqs)
     assert st["steps"] > 0 and "latency_ms_p99" in st and st["bytes_h2d"] > 0 and st["bytes_d2h"] > 0
-    n_swapped = 0
+    n_swapped, kinds, seg_swapped_checked = 0, set(), 0
     for i, rid in enumerate(keep):
         req = next(r for r in reqs if r.rid == rid)
         x, y_mix, swaps = srv.kept_outputs(rid)
@@ -206,21 +259,29 @@ def _server_check(precision, seed, tol_max):
         n_total = n_in + math.ceil((req.ir_len - 1) / req.block)
         assert y_mix.shape == (req.channels, n_total * req.block)
         B, C = req.block, req.channels
-        x_in = x.reshape(C, n_in, B).transpose(1, 0, 2)
+        segmented = srv.segments_for(req) is not None
+        kinds.add(segmented)
+        if segmented:
+            y_alone = _replay_segmented(srv, req, swaps, x, n_in, n_total)
+        else:
+            x_in = x.reshape(C, n_in, B).transpose(1, 0, 2)
 
-        class Hist:
-            pass
-        hist = Hist()
-        hist.n_in, hist.n_total, hist.swap_blocks = n_in, n_total, swaps
-        y_alone = _replay_alone(srv, req, hist, x_in, precision=precision)
-        assert np.array_equal(y_mix, y_alone.transpose(1, 0, 2).reshape(C, -1)), f"request {rid}"
-        if i < 2:
+            class Hist:
+                pass
+            hist = Hist()
+            hist.n_in, hist.n_total, hist.swap_blocks = n_in, n_total, swaps
+            y_alone = _replay_alone(srv, req, hist, x_in, precision=precision).transpose(1, 0, 2).reshape(C, -1)
+        assert np.array_equal(y_mix, y_alone), f"request {rid} (two segments: {segmented})"
+        if i < 2 or (segmented and swaps and seg_swapped_checked < 2):
+            seg_swapped_checked += bool(segmented and swaps)
             irs = [srv.ir(req, v).cpu().numpy() for v in range(len(swaps) + 1)]
             sched = [(0, 0)] + [(b, v + 1) for v, b in enumerate(swaps)]
             ref = oracle_run(x, irs, sched, B, req.ir_len, n_total)
             for c in range(C):
                 assert rel_err(y_mix[c], ref[c]) <= tol_max
     assert n_swapped > 0
+    if precision == 0:
+        assert kinds == {False, True}   # both one-stream and two-segment requests were served
     srv.close()
 
 
@@ -257,3 +318,46 @@ def test_server_tick_small_budget_queues():
     assert st["completed"] == len(reqs)
     assert st["refused_attempts"] > 0
     srv.close()
+
+
+def test_server_add_segmented_rejects_bad_shapes():
+    """taches_server_add_segmented refuses (EINVAL, nothing registered)
+    segments that break its rules: Br not a multiple of B, H < Br, a ring
+    shorter than Br + B, a split-BF16 stream, an IR no longer than H, and two
+    IR changes inside one rest block (the initial IR counting as one)."""
+    import torch
+    T = binding()
+    pool = T.Pool(8, 1 << 30)
+    sv = T.taches_server_create(pool.h, 48000.0, 4, 0.0)
+    C, B, L = 1, 64, 8192
+    h = torch.randn(L, device="cuda")
+    x = np.zeros((C, 40 * B), np.float32)
+
+    def stream(b, cap, prec=0):
+        s = T.Stream(b, cap, channels=C, max_blocks_per_call=4, precision=prec)
+        assert pool.attach(s) == T.TACHES_OK
+        return s
+    head, rest = stream(B, 1024), stream(512, 8192)
+    ring = torch.empty((C, 4096), device="cuda")
+
+    def add(hd, rs, H, z, ir=h, swaps=(), tag=1):
+        irs = [ir for _ in swaps]
+        return T.taches_server_add_segmented(sv, hd.h, rs.h, H, z, tag, 0.0, 40, 40 + L // B, x, None, ir,
+                                             list(swaps), irs)
+    assert add(head, rest, 256, ring) == T.TACHES_EINVAL                     # H < Br
+    odd = stream(96, 8192)
+    assert add(head, odd, 1024, ring) == T.TACHES_EINVAL                     # Br not a multiple of B
+    assert add(head, rest, 1024, torch.empty((C, 512), device="cuda")) == T.TACHES_EINVAL   # ring < Br + B
+    assert add(head, rest, 1024, ring, ir=h[:1024]) == T.TACHES_EINVAL       # IR not longer than H
+    split = stream(512, 8192, prec=T.TACHES_PREC_SPLIT_BF16)
+    assert add(head, split, 1024, ring) == T.TACHES_EINVAL                   # rest segment not FP32
+    assert add(head, rest, 1024, ring, swaps=[128 / 48000]) == T.TACHES_EINVAL           # inside rest block 0
+    assert add(head, rest, 1024, ring, swaps=[640 / 48000, 900 / 48000]) == T.TACHES_EINVAL  # two in block 1
+    assert T.taches_server_get_stats(sv).streams == 0
+    assert add(head, rest, 1024, ring, swaps=[512 / 48000, 1100 / 48000]) == T.TACHES_OK
+    assert T.taches_server_get_stats(sv).streams == 1
+    T.taches_server_destroy(sv)
+    for s in (head, rest, odd, split):
+        pool.detach(s)
+        s.close()
+    pool.close()

@@ -189,3 +189,72 @@ def test_split_launch_and_wait_give_the_same_records():
     assert sch_a.stats.latencies_s.size > 0
     for r in reqs:
         assert np.array_equal(ex_a.out[r.rid][1], ex_b.out[r.rid][1])
+
+
+# ---- two-segment serving: the decomposition the server applies -------------
+
+def _seg_request(L, B, swaps, dur_s=0.05, C=1, seed=3):
+    return W.ServingRequest(rid=0, arrival_s=0.0, duration_s=dur_s, channels=C, block=B, ir_len=L,
+                           seed=seed, swap_times_s=list(swaps))
+
+
+def test_change_blocks_rule():
+    from paper_2401_01607_amd.serving import change_blocks
+    fs = W.FS
+    req = _seg_request(4096, 64, [0.0, 64 / fs, 64.5 / fs, 0.02, 1.0])
+    n_in = math.ceil(req.n_samples() / 64)
+    # a change at t applies to the first block starting at or after t; none after the input
+    assert change_blocks(req) == [0, 1, 2, math.ceil(0.02 * fs / 64)]
+    assert all(k < n_in for k in change_blocks(req))
+
+
+def test_segments_rule():
+    from paper_2401_01607_amd import taches as T
+    from paper_2401_01607_amd.serving import segments_for
+    fp32, split = T.TACHES_PREC_FP32, T.TACHES_PREC_SPLIT_BF16
+    assert segments_for(_seg_request(512, 32, []), fp32) is None          # shorter than four rest blocks
+    assert segments_for(_seg_request(65536, 32, []), split) is None       # split-BF16 streams stay whole
+    for L, B in [(2048, 32), (41_940, 64), (262_144, 512), (8192, 512)]:
+        H, br, Z = segments_for(_seg_request(L, B, []), fp32)
+        assert br & (br - 1) == 0 and br % B == 0 and max(B, 256) <= br <= 2048 and H == br
+        assert L >= 4 * br and Z >= br + B
+    # two changes inside one rest block: served whole
+    H, br, _ = segments_for(_seg_request(65536, 32, []), fp32)
+    assert segments_for(_seg_request(65536, 32, [br / W.FS + 32 / W.FS, br / W.FS + 96 / W.FS]), fp32) is None
+    assert segments_for(_seg_request(65536, 32, [br / W.FS, 2 * br / W.FS + 32 / W.FS]), fp32) is not None
+    # a change inside the first rest block, where the initial IR starts: served whole
+    assert segments_for(_seg_request(65536, 32, [64 / W.FS]), fp32) is None
+    assert segments_for(_seg_request(65536, 32, [0.0]), fp32) is not None
+
+
+@pytest.mark.parametrize("L,B,swaps", [
+    (3000, 32, []),
+    (9000, 64, [0.013, 0.031]),
+    (20000, 128, [0.0, 0.013, 0.031]),
+])
+def test_two_segments_equal_the_whole_ir(L, B, swaps):
+    """y = head + rest shifted by H, with the head's IR changes at its blocks
+    and the rest's at the same input samples (inside its longer blocks),
+    equals the whole IR's taches exactly on integer inputs (Eq. (1) is
+    linear in h; the oracle runs all three)."""
+    from paper_2401_01607_amd import taches as T
+    from paper_2401_01607_amd.serving import change_blocks, segments_for
+    req = _seg_request(L, B, swaps, dur_s=0.045)
+    H, br, _ = segments_for(req, T.TACHES_PREC_FP32)
+    n_in = math.ceil(req.n_samples() / B)
+    n_total = n_in + math.ceil((L - 1) / B)
+    ks = change_blocks(req)
+    rng = np.random.default_rng(L)
+    irs = [rng.integers(-8, 9, L).astype(np.float32) for _ in range(len(ks) + 1)]
+    x = rng.integers(-8, 9, n_in * B).astype(np.float32)
+    whole = O.run_channel(x, irs, [(0, 0)] + [(k, v + 1) for v, k in enumerate(ks)], B, L, n_total)
+    head = O.run_channel(x, [h[:H] for h in irs], [(0, 0)] + [(k, v + 1) for v, k in enumerate(ks)], B, H, n_total)
+    r_in = -(-n_in * B // br)
+    r_total = max(r_in, -(-(n_total * B - H) // br))
+    xr = np.zeros(r_in * br, np.float32)
+    xr[:x.size] = x
+    rest_sched = [(0, 0)] + [(k * B // br, v + 1, k * B % br) for v, k in enumerate(ks)]
+    z = O.run_channel(xr, [h[H:] for h in irs], rest_sched, br, L - H, r_total)
+    y = head.copy()
+    y[H:] += z[:y.size - H]
+    assert np.array_equal(y, whole)
