@@ -255,8 +255,9 @@ int taches_tail_is_fp64(const taches_config* cfg);
 int taches_read_tail(taches_stream* s, int32_t channel, double* out, int32_t n);
 
 /* Return the stream to its state right after open (empty tail, no IR)
- * without freeing memory: a stream-ordered clear of the tail.  For reusing
- * a stream for a new input. */
+ * without freeing memory or enqueuing device work: the tail counts as empty
+ * (no slot is read before it is written again).  For reusing a stream for
+ * a new input. */
 int taches_reset(taches_stream* s);
 
 /* Force the gather tile shape (R outputs per lane in {4, 8, 12, 14, 16}, W waves
@@ -320,6 +321,14 @@ int taches_pool_step_strided(taches_pool* p, int32_t n, taches_stream* const* st
 /* HIP stream for the pool and its attached streams (NULL = HIP's null
  * stream).  Work already enqueued is first waited for. */
 int taches_pool_set_hip_stream(taches_pool* p, void* hip_stream);
+
+/* HIP stream for the host-to-device copy of each step's work table
+ * (nullptr, the default: the pool's stream, inside its captured graph).
+ * With a copy stream, the copy of step k + 1's table can run while step
+ * k's kernel does; the pool's stream waits for each copy through an event.
+ * The caller keeps the stream alive while it is set; setting another one
+ * first waits for the current one. */
+int taches_pool_set_copy_stream(taches_pool* p, void* hip_stream);
 
 /* Per-lane tile of the batched kernel (4, 8, 12, 16; 0 = automatic). */
 int taches_pool_set_tile(taches_pool* p, int32_t r);

@@ -1083,7 +1083,9 @@ int taches_read_tail(taches_stream* s, int32_t channel, double* out, int32_t n) 
                        hipMemcpyDeviceToHost));
   }
   for (int k = 0; k < n; ++k) {
-    if (s->tail_fp64) {
+    if (k >= s->live) {   // no pending sums past `live` (the slots may hold stale values)
+      out[k] = 0.0;
+    } else if (s->tail_fp64) {
       double v;
       std::memcpy(&v, buf.data() + (size_t)k * 8, 8);
       out[k] = v;
@@ -1098,8 +1100,9 @@ int taches_read_tail(taches_stream* s, int32_t channel, double* out, int32_t n) 
 
 int taches_reset(taches_stream* s) {
   if (!s) return fail(TACHES_EINVAL, "stream is NULL");
-  const size_t esz = s->tail_fp64 ? 8 : 4;
-  HIPCHK(hipMemsetAsync(s->ring, 0, (size_t)s->cpad * s->Rcap * esz, s->stream));
+  // The ring is not cleared: with live = 0 no kernel reads a slot before
+  // writing it (slots past `live` count as zero, and emitted slots are
+  // cleared as they are read), and taches_read_tail reports zeros there.
   for (auto& sl : s->slots) sl.L = 0;
   s->active = s->pending = -1;
   s->head = s->live = 0;
@@ -1144,7 +1147,11 @@ struct taches_pool {
   // Two pinned buffers are used in turn, so the host can build a step's
   // table while the previous step (and its copy) is still queued.
   unsigned char* tab_pin[2] = {nullptr, nullptr};
-  unsigned char* tab_dev = nullptr;
+  unsigned char* tab_dev[2] = {nullptr, nullptr};   // device copies, used in turn like the pinned ones
+  // stream of the table copies (nullptr: the pool's stream); the pool's
+  // stream waits for each copy through tab_copied
+  hipStream_t copy = nullptr;
+  hipEvent_t tab_copied = nullptr;
   size_t tab_cap = 0;
   hipEvent_t tab_free[2] = {nullptr, nullptr};
   bool tab_pending[2] = {false, false};
@@ -1162,7 +1169,7 @@ struct taches_pool {
     int nwg = 0;
     size_t cap = 0;
   };
-  static constexpr int kGraphs = 4 * 2 * 8;
+  static constexpr int kGraphs = 4 * 2 * 8 * 2 * 2;   // ... x table buffer x copy inside or outside
   Graph graphs[kGraphs];
   int64_t captures = 0;
   int64_t replays = 0;
@@ -1261,32 +1268,45 @@ int pool_reserve(taches_pool* p, size_t bytes) {
     (void)hipHostFree(p->tab_pin[k]);
     p->tab_pin[k] = nullptr;
   }
-  (void)hipFree(p->tab_dev);
-  p->tab_dev = nullptr;
+  for (int k = 0; k < 2; ++k) {
+    (void)hipFree(p->tab_dev[k]);
+    p->tab_dev[k] = nullptr;
+  }
   p->tab_cap = 0;
   const size_t cap = align256(bytes + bytes / 2);
   for (int k = 0; k < 2; ++k) {
     hipError_t e = hipHostMalloc((void**)&p->tab_pin[k], cap, hipHostMallocDefault);
     if (e != hipSuccess) return fail(TACHES_ENOMEM, "pool table (host): %s", hipGetErrorString(e));
   }
-  hipError_t e = hipMalloc((void**)&p->tab_dev, cap);
-  if (e != hipSuccess) return fail(TACHES_ENOMEM, "pool table (device): %s", hipGetErrorString(e));
+  for (int k = 0; k < 2; ++k) {
+    hipError_t e = hipMalloc((void**)&p->tab_dev[k], cap);
+    if (e != hipSuccess) return fail(TACHES_ENOMEM, "pool table (device): %s", hipGetErrorString(e));
+  }
   p->tab_cap = cap;
   return TACHES_OK;
 }
 
 // Tile shape of a batched launch: the same per-lane tile for every stream.
-// Longer tiles need fewer LDS reads per FMA; the largest one that still
-// leaves about four items per resident workgroup keeps the greedy balance
-// tight.
+// Longer tiles need fewer LDS reads per FMA and pay each tile's fixed costs
+// (descriptor, tail read and write) over more outputs.  The largest one is
+// taken that leaves about four items per resident workgroup, or at least
+// one when every tile is light (at most 4096 input samples reach a tile of
+// 1024 outputs: a few microseconds of one wave, so the work queue balances
+// the step whatever their number, as in serving steps); smaller tiles
+// otherwise keep steps of heavy tiles balanced.
 int pool_pick_r(const taches_pool* p, const std::vector<const GatherCall*>& calls, bool mixed) {
   if (p->force_r) return p->force_r;
   static const int rs[4] = {16, 12, 8, 4};
+  constexpr int64_t kLightTile = 1024LL * 4096;   // multiply-adds
   for (int r : rs) {
     const int64_t T = 64 * r;
-    int64_t items = 0;
-    for (const GatherCall* g : calls) items += (int64_t)g->channels * ((g->n_out + T - 1) / T);
-    if (items >= 4LL * 256 * taches::gather_batched_waves_per_cu(r, mixed)) return r;
+    const int64_t wg = 256LL * taches::gather_batched_waves_per_cu(r, mixed);
+    int64_t items = 0, heaviest = 0;
+    for (const GatherCall* g : calls) {
+      items += (int64_t)g->channels * ((g->n_out + T - 1) / T);
+      if (g->x) heaviest = std::max(heaviest, T * std::min<int64_t>(g->S, T + g->Lmax_call - 1));
+    }
+    if (items >= 4 * wg || (items >= wg && heaviest <= kLightTile)) return r;
   }
   return 4;
 }
@@ -1313,14 +1333,15 @@ taches_pool* taches_pool_create(int32_t max_streams, int64_t hbm_budget_bytes, i
             hipEventCreateWithFlags(&p->tab_free[0], hipEventDisableTiming) == hipSuccess &&
             hipEventCreateWithFlags(&p->tab_free[1], hipEventDisableTiming) == hipSuccess &&
             hipEventCreateWithFlags(&p->detach_ev, hipEventDisableTiming) == hipSuccess &&
-            hipEventCreateWithFlags(&p->attach_ev, hipEventDisableTiming) == hipSuccess;
+            hipEventCreateWithFlags(&p->attach_ev, hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&p->tab_copied, hipEventDisableTiming) == hipSuccess;
   for (int k = 0; ok && k < taches_pool::kRing; ++k)
     ok = hipEventCreate(&p->ev_beg[k]) == hipSuccess && hipEventCreate(&p->ev_end[k]) == hipSuccess;
   if (!ok) {
     fail(TACHES_EDEVICE, "pool stream/event creation failed");
     if (p->own) (void)hipStreamDestroy(p->own);
     if (p->capture) (void)hipStreamDestroy(p->capture);
-    for (hipEvent_t ev : {p->tab_free[0], p->tab_free[1], p->detach_ev, p->attach_ev})
+    for (hipEvent_t ev : {p->tab_free[0], p->tab_free[1], p->detach_ev, p->attach_ev, p->tab_copied})
       if (ev) (void)hipEventDestroy(ev);
     for (int k = 0; k < taches_pool::kRing; ++k) {
       if (p->ev_beg[k]) (void)hipEventDestroy(p->ev_beg[k]);
@@ -1339,8 +1360,8 @@ int taches_pool_destroy(taches_pool* p) {
   (void)hipStreamSynchronize(p->stream);
   pool_drop_graph(p);
   for (int k = 0; k < 2; ++k) (void)hipHostFree(p->tab_pin[k]);
-  (void)hipFree(p->tab_dev);
-  for (hipEvent_t ev : {p->tab_free[0], p->tab_free[1], p->detach_ev, p->attach_ev})
+  for (int k = 0; k < 2; ++k) (void)hipFree(p->tab_dev[k]);
+  for (hipEvent_t ev : {p->tab_free[0], p->tab_free[1], p->detach_ev, p->attach_ev, p->tab_copied})
     if (ev) (void)hipEventDestroy(ev);
   for (int k = 0; k < taches_pool::kRing; ++k) {
     (void)hipEventDestroy(p->ev_beg[k]);
@@ -1359,6 +1380,16 @@ int taches_pool_set_hip_stream(taches_pool* p, void* hip_stream) {
     HIPCHK(hipStreamSynchronize(p->stream));
     p->stream = next;
     for (taches_stream* s : p->attached) s->stream = next;
+  }
+  return TACHES_OK;
+}
+
+int taches_pool_set_copy_stream(taches_pool* p, void* hip_stream) {
+  if (!p) return fail(TACHES_EINVAL, "pool is NULL");
+  hipStream_t next = (hipStream_t)hip_stream;
+  if (next != p->copy) {
+    if (p->copy) HIPCHK(hipStreamSynchronize(p->copy));
+    p->copy = next;
   }
   return TACHES_OK;
 }
@@ -1748,16 +1779,18 @@ int taches_pool_step_strided(taches_pool* p, int32_t n, taches_stream* const* st
     int rc2 = pool_account(p, false);
     if (rc2 != TACHES_OK) return rc2;
   }
+  unsigned char* dev = p->tab_dev[cur];
+  const bool sep = p->copy != nullptr;   // table copy on the copy stream, outside the graph
   taches_pool::Graph* pg = nullptr;
   if (has_gather && p->use_graph) {
     int b = 0;
     while ((256 << b) < nwg && b < 7) ++b;
-    pg = &p->graphs[((r / 4 - 1) * 2 + (mixed ? 1 : 0)) * 8 + b];
+    pg = &p->graphs[(((((r / 4 - 1) * 2 + (mixed ? 1 : 0)) * 8 + b) * 2 + cur) * 2) + (sep ? 1 : 0)];
     if (!pg->exec || pg->nwg != nwg || pg->cap != p->tab_cap) {
       drop_graph(*pg);
       HIPCHK(hipStreamBeginCapture(p->capture, hipStreamCaptureModeThreadLocal));
-      hipError_t e1 = hipMemcpyAsync(p->tab_dev, pin, p->tab_cap, hipMemcpyHostToDevice, p->capture);
-      hipError_t e2 = taches::launch_gather_batched(p->tab_dev, nwg, r, mixed, p->capture);
+      hipError_t e1 = sep ? hipSuccess : hipMemcpyAsync(dev, pin, p->tab_cap, hipMemcpyHostToDevice, p->capture);
+      hipError_t e2 = taches::launch_gather_batched(dev, nwg, r, mixed, p->capture);
       hipError_t e3 = hipStreamEndCapture(p->capture, &pg->graph);
       if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess)
         return fail(TACHES_EDEVICE, "graph capture failed: %s", hipGetErrorString(e1 != hipSuccess ? e1 : e2 != hipSuccess ? e2 : e3));
@@ -1776,25 +1809,32 @@ int taches_pool_step_strided(taches_pool* p, int32_t n, taches_stream* const* st
       p->captures += 1;
     }
   }
-  const bool replay = pg && pg->copy_node &&
-                      hipGraphExecMemcpyNodeSetParams1D(pg->exec, pg->copy_node, p->tab_dev, pin, bytes,
-                                                        hipMemcpyHostToDevice) == hipSuccess;
+  bool replay = false;
+  if (pg && pg->exec)
+    replay = sep || (pg->copy_node && hipGraphExecMemcpyNodeSetParams1D(pg->exec, pg->copy_node, dev, pin, bytes,
+                                                                        hipMemcpyHostToDevice) == hipSuccess);
   // ---- enqueue: from here on, failures commit what was enqueued ----
-  hipError_t e = hipEventRecord(p->ev_beg[ev], p->stream);
+  hipError_t e = hipSuccess;
+  if (sep) {
+    e = hipMemcpyAsync(dev, pin, bytes, hipMemcpyHostToDevice, p->copy);
+    if (e == hipSuccess) e = hipEventRecord(p->tab_copied, p->copy);
+    if (e == hipSuccess) e = hipStreamWaitEvent(p->stream, p->tab_copied, 0);
+  }
+  if (e == hipSuccess) e = hipEventRecord(p->ev_beg[ev], p->stream);
   if (e == hipSuccess) {
     if (replay) {
       e = hipGraphLaunch(pg->exec, p->stream);
       if (e == hipSuccess) p->replays += 1;
     } else {
-      e = hipMemcpyAsync(p->tab_dev, pin, bytes, hipMemcpyHostToDevice, p->stream);
-      if (e == hipSuccess && has_gather) e = taches::launch_gather_batched(p->tab_dev, nwg, r, mixed, p->stream);
+      if (!sep) e = hipMemcpyAsync(dev, pin, bytes, hipMemcpyHostToDevice, p->stream);
+      if (e == hipSuccess && has_gather) e = taches::launch_gather_batched(dev, nwg, r, mixed, p->stream);
     }
   }
   if (e != hipSuccess) return finish(fail(TACHES_EDEVICE, "batched launch: %s", hipGetErrorString(e)));
   for (int i : gather_ids) enqueued[i] = 1;
   for (int k = 0; k < 4; ++k) {
     if (!sb[k].n_calls) continue;
-    e = taches::launch_toeplitz_batched(p->tab_dev, sb[k], (k & 2) != 0, (k & 1) != 0, p->stream);
+    e = taches::launch_toeplitz_batched(dev, sb[k], (k & 2) != 0, (k & 1) != 0, p->stream);
     if (e != hipSuccess) return finish(fail(TACHES_EDEVICE, "batched Toeplitz launch: %s", hipGetErrorString(e)));
     for (int i : split_ids[k]) {
       enqueued[i] = 1;

@@ -409,24 +409,33 @@ def segments_for(req, precision: int, fs: float = W.FS):
     L + B.  Br is the power of two nearest sqrt(24 L), within
     [max(B, 256), 2048]: with ticks about 0.5 ms apart (24 samples at
     48 kHz) it balances the head's traffic per tick, ~ H, against the
-    rest's, ~ L per Br samples.  Only FP32 requests whose IR is at least
-    four rest blocks long, and whose IR changes (the initial IR counting as
-    one at sample 0) apply in different rest blocks; Z (the rest outputs kept on the device) lets the rest stream
-    run up to 4 Br + 8 B samples ahead of the outputs the head has used."""
+    rest's, ~ L per Br samples.  A rest block takes at most one IR change
+    inside it (the initial IR counting as one at sample 0): Br is halved
+    until the request's changes fall in different rest blocks, down to
+    max(B, 256) (below 256 samples a rest block would need an FP64 tail).
+    Only FP32 requests whose IR is at least four rest blocks long; Z (the
+    rest outputs kept on the device) lets the rest stream run up to
+    4 Br + 8 B samples ahead of the outputs the head has used."""
     from . import taches as T
     if precision != T.TACHES_PREC_FP32:
         return None
     L, B = req.ir_len, req.block
     br = 1 << max(0, int(round(math.log2(math.sqrt(24.0 * L)))))
-    br = max(max(B, 256), min(2048, br))
-    if L < 4 * br:
+    lo = max(B, 256)
+    br = max(lo, min(2048, br))
+    samples = [k * B for k in change_blocks(req, fs)]
+
+    def separated(br):
+        prev = 0   # the initial IR applies from sample 0
+        for smp in samples:
+            if smp != prev and smp // br == prev // br:
+                return False
+            prev = smp
+        return True
+    while br > lo and not separated(br):
+        br //= 2
+    if L < 4 * br or not separated(br):
         return None
-    prev = 0   # the initial IR applies from sample 0
-    for k in change_blocks(req, fs):
-        smp = k * B
-        if smp != prev and smp // br == prev // br:
-            return None
-        prev = smp
     return br, br, 4 * br + 8 * B
 
 

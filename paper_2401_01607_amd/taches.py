@@ -106,6 +106,7 @@ _SIGS = {
     "taches_pool_step": (ctypes.c_int, [_vp, _i32, _vp, _vp, _vp, _vp]),
     "taches_pool_step_strided": (ctypes.c_int, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp]),
     "taches_pool_set_hip_stream": (ctypes.c_int, [_vp, _vp]),
+    "taches_pool_set_copy_stream": (ctypes.c_int, [_vp, _vp]),
     "taches_pool_set_tile": (ctypes.c_int, [_vp, _i32]),
     "taches_pool_use_graph": (ctypes.c_int, [_vp, _i32]),
     "taches_pool_synchronize": (ctypes.c_int, [_vp]),
@@ -385,6 +386,10 @@ def taches_fp32_fma_ceiling(device: int = 0) -> float:
 
 def taches_pool_set_hip_stream(p, stream: int) -> int:
     return lib.taches_pool_set_hip_stream(p, ctypes.c_void_p(stream) if stream else None)
+
+
+def taches_pool_set_copy_stream(p, stream: int) -> int:
+    return lib.taches_pool_set_copy_stream(p, ctypes.c_void_p(stream) if stream else None)
 
 
 def taches_pool_set_tile(p, r: int) -> int:

@@ -437,3 +437,37 @@ def test_sample_accurate_swap_errors():
     with pytest.raises(T.TachesError):
         sp.set_ir(h, 3)
     sp.close()
+
+
+@pytest.mark.parametrize("tail", ["fp32", "fp64"])
+def test_reset_stream_equals_fresh_stream(tail):
+    """A stream reset after use (no device clear: the tail counts as empty)
+    gives the same bits as a freshly opened one on a new input and IR, and
+    its tail reads back as zeros right after the reset."""
+    import torch
+    from tests.gpu_harness import binding
+    T = binding()
+    tail = T.TACHES_TAIL_FP32 if tail == "fp32" else T.TACHES_TAIL_FP64
+    B, L, C, nb = 64, 3000, 2, 40
+    x1 = np.stack([W.signal_gauss(nb * B, 900 + c) for c in range(C)])
+    x2 = np.stack([W.signal_gauss(nb * B, 910 + c) for c in range(C)])
+    h1, h2 = W.impulse_response(L, 920), W.impulse_response(L - 700, 921)
+
+    def run(s, x, h):
+        s.set_ir(h)
+        y = torch.empty((C, nb * B), device="cuda")
+        s.process_blocks(torch.from_numpy(x).cuda(), y, nb)
+        s.synchronize()
+        return y.cpu().numpy()
+    used = T.Stream(B, L, channels=C, max_blocks_per_call=nb, tail=tail)
+    run(used, x1, h1)
+    assert np.any(used.read_tail(0, L) != 0)
+    used.reset()
+    assert not np.any(used.read_tail(0, L))
+    assert not np.any(used.read_tail(C - 1, L))
+    fresh = T.Stream(B, L, channels=C, max_blocks_per_call=nb, tail=tail)
+    assert np.array_equal(run(used, x2, h2), run(fresh, x2, h2))
+    for c in range(C):
+        assert np.array_equal(used.read_tail(c, L), fresh.read_tail(c, L))
+    used.close()
+    fresh.close()

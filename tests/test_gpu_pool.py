@@ -41,13 +41,16 @@ def _alone(x, h, B, L, nb):
     return y
 
 
-def _pool_run(specs, steps, use_graph=False, tile=0, between=None):
+def _pool_run(specs, steps, use_graph=False, tile=0, between=None, copy_stream=None):
     """Run every stream through `steps` pool steps; specs: (x, h, B, L);
-    steps: list of per-step block counts (same for every stream)."""
+    steps: list of per-step block counts (same for every stream);
+    copy_stream: a torch stream for the work-table copies, or None."""
     import torch
     T = binding()
     total = sum(steps)
     pool = T.Pool(len(specs), 64 * GB, use_graph=use_graph, tile_r=tile)
+    if copy_stream is not None:
+        assert T.taches_pool_set_copy_stream(pool.h, copy_stream.cuda_stream) == T.TACHES_OK
     ss, xs = [], []
     for x, h, B, L in specs:
         s = T.Stream(B, L, max_blocks_per_call=max(steps))
@@ -71,6 +74,8 @@ def _pool_run(specs, steps, use_graph=False, tile=0, between=None):
     pool.synchronize()
     info = pool.info()
     res = [y.cpu().numpy() for y in ys]
+    if copy_stream is not None:
+        assert T.taches_pool_set_copy_stream(pool.h, 0) == T.TACHES_OK
     pool.close()
     for s in ss:
         s.close()
@@ -123,6 +128,31 @@ def test_graph_replays_equal_eager_steps():
     for a, b in zip(eager, graphed):
         assert np.array_equal(a, b)
     assert float(scratch[0]) == len(steps)
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_table_copy_stream_equals_default(use_graph):
+    """Work tables copied on a stream of their own (the pool's stream waits
+    for each copy; the two device tables are used in turn) give the same
+    bits as copies on the pool's stream, step after step, with eager work
+    and synchronisations between steps."""
+    import torch
+    specs = _streams(12, 17, 3000, lmax=2500, blocks=(32, 64, 128))
+    steps = [1, 3, 1, 2, 1, 1, 4, 1, 2, 1]
+    scratch = torch.zeros(1 << 20, device="cuda")
+
+    def eager_work(k):
+        scratch.add_(1.0)
+        if k % 3 == 0:
+            torch.cuda.synchronize()
+
+    base, _ = _pool_run(specs, steps, use_graph=use_graph)
+    cs = torch.cuda.Stream()
+    sep, info = _pool_run(specs, steps, use_graph=use_graph, between=eager_work, copy_stream=cs)
+    for a, b in zip(base, sep):
+        assert np.array_equal(a, b)
+    if use_graph:
+        assert info.graph_replays >= len(steps) - 4
 
 
 def test_admission_budget_and_slots():
