@@ -82,6 +82,8 @@ def parse():
     p.add_argument("--no-errors", action="store_true", help="skip the error figures (profiling runs)")
     p.add_argument("--only", type=str, default="",
                    help="run one extra section only (c1, c2, c3split, c4, c5, f2, f4, tail, f3)")
+    p.add_argument("--c5-seconds", type=float, default=30.0,
+                   help="real time of the full-load serving run (a third of it warm-up)")
     p.add_argument("--device-warmup-s", type=float, default=1.0,
                    help="seconds of untimed steps before the warm-up steps (device clock ramp)")
     return p.parse_args()
@@ -647,6 +649,7 @@ def extra_c5_serving(errors, duration_s=30.0, warmup_s=10.0):
     srv = RealtimeServer(reqs, max_streams=4096, hbm_budget_bytes=64 << 30, use_graph=True, keep_outputs=keep,
                          warmup_s=warmup_s)
     st = srv.run_realtime(duration_s)
+    print("bench: c5 full-load run done", file=sys.stderr, flush=True)
     info = srv.pool.info()
     if errors is not None:
         errors["c5_fp32"] = _serving_errors(srv, reqs, keep)
@@ -664,6 +667,7 @@ def extra_c5_serving(errors, duration_s=30.0, warmup_s=10.0):
         srv2 = RealtimeServer(r2, max_streams=4096, hbm_budget_bytes=64 << 30, use_graph=True, precision=prec,
                               keep_outputs=keep2, warmup_s=3.0)
         s2 = srv2.run_realtime(10.0)
+        print(f"bench: c5 run at 20 streams/s ({name}) done", file=sys.stderr, flush=True)
         if errors is not None:
             errors["c5_" + name + "_at_20_per_s"] = _serving_errors(srv2, r2, keep2)
         srv2.close()
@@ -949,7 +953,8 @@ def extras(args, errors):
     out = {}
     sections = {"c1": lambda: extra_c1(errors), "c2": lambda: extra_c2(errors),
                 "c3split": lambda: extra_c3_split(errors), "c4": lambda: extra_c4_batched(errors),
-                "c5": lambda: extra_c5_serving(errors), "f2": extra_f2_offline, "f4": extra_f4_zero_bypass,
+                "c5": lambda: extra_c5_serving(errors, args.c5_seconds, args.c5_seconds / 3),
+                "f2": extra_f2_offline, "f4": extra_f4_zero_bypass,
                 "tail": lambda: extra_tail_policy(errors), "f3": extra_f3_capacity}
     for name, fn in sections.items():
         if args.only and args.only != name:
