@@ -36,6 +36,7 @@ the device runs; a block still counts as done when wait() returns.
 """
 from __future__ import annotations
 
+import gc
 import math
 import sys
 import threading
@@ -966,6 +967,13 @@ class RealtimeServer:
         # long for it
         switch = sys.getswitchinterval()
         sys.setswitchinterval(1e-4)
+        # no cyclic garbage collection while serving: a full collection of a
+        # large heap stops both threads for tens of milliseconds (objects
+        # that exist now are frozen out of later collections)
+        gc_was_enabled = gc.isenabled()
+        gc.collect()
+        gc.freeze()
+        gc.disable()
         self._stop = False
         self._thread = threading.Thread(target=self._prepare_loop, name="taches-admission", daemon=True)
         self._thread.start()
@@ -976,6 +984,9 @@ class RealtimeServer:
             self._thread.join()
             self._thread = None
             sys.setswitchinterval(switch)
+            gc.unfreeze()
+            if gc_was_enabled:
+                gc.enable()
         T.taches_server_flush(sv)
         self._retire()
         wall = T.taches_server_clock(sv)
