@@ -361,3 +361,53 @@ def test_server_add_segmented_rejects_bad_shapes():
         pool.detach(s)
         s.close()
     pool.close()
+
+
+def test_server_tick_full_load_sampled_parity():
+    """The serving workload at full rate through the library tick, as the
+    benchmark runs it (Poisson 200 streams/s of 10-60 s, L log-uniform in
+    [512, 262 144], mono/stereo, B in {32..512}, IR changes at 0.5/s, real
+    time, long IRs in two segments): 14 s of real time, about 2 800
+    requests admitted.  Kept requests that finish in the run (the longest
+    IRs among the early ones, and the first ones) are checked on sampled
+    outputs, both sides of every applied IR change, against Eq. (4) in FP64."""
+    from oracle import oracle as O
+    from paper_2401_01607_amd.serving import RealtimeServer
+    horizon = 14.0
+    reqs = W.config5_requests(horizon_s=horizon)
+    done_by = [r for r in reqs if r.arrival_s < 2.0 and r.arrival_s + r.duration_s + r.ir_len / W.FS < horizon - 1.5]
+    keep = list(dict.fromkeys([r.rid for r in sorted(done_by, key=lambda r: -r.ir_len)[:3]] +
+                              [r.rid for r in done_by[:2]]))
+    srv = RealtimeServer(reqs, max_streams=4096, hbm_budget_bytes=64 << 30, keep_outputs=keep)
+    st = srv.run_realtime(horizon)
+    assert st["admitted"] >= 2000 and st["completed"] >= len(keep)
+    rng = np.random.default_rng(606)
+    checked = segmented = 0
+    for rid in keep:
+        req = next(r for r in reqs if r.rid == rid)
+        got = srv.kept_outputs(rid)
+        assert got is not None, f"request {rid} not admitted"
+        x, y, swaps = got
+        n_in = max(1, math.ceil(req.n_samples() / req.block))
+        n_total = n_in + math.ceil((req.ir_len - 1) / req.block)
+        assert y.shape[1] == n_total * req.block, f"request {rid} did not finish"
+        assert swaps == _swap_rule_blocks(req)
+        irs = [srv.ir(req, v).cpu().numpy() for v in range(len(swaps) + 1)]
+        sched = [(0, 0)] + [(b, v + 1) for v, b in enumerate(swaps)]
+        S = y.shape[1]
+        idx = set(rng.integers(0, S, 60).tolist()) | {0, x.shape[1] - 1, x.shape[1], S - 1}
+        for b in swaps:
+            idx.update([b * req.block - 1, b * req.block])
+        seg = srv.segments_for(req)
+        if seg is not None:   # both sides of where the rest segment starts to count, and of its blocks
+            H, br, _ = seg
+            idx.update([H - 1, H, H + br - 1, H + br])
+            segmented += 1
+        idx = np.array(sorted(j for j in idx if 0 <= j < S))
+        for c in range(req.channels):
+            ref = O.sampled_outputs(x[c], irs, sched, req.block, idx)
+            rms = rms_y64(x[c], irs, sched, req.block, S)
+            assert np.max(np.abs(y[c][idx].astype(np.float64) - ref)) <= 1e-5 * rms, f"request {rid} channel {c}"
+        checked += 1
+    assert checked == len(keep) and segmented >= 2
+    srv.close()
