@@ -721,6 +721,7 @@ class RealtimeServer:
         self._prepared: dict = {}    # rid -> (streams, keys, ring, irs, device bytes)
         self._thread = None
         self._stop = False
+        self._error = None           # an exception of the preparing thread
         self.live_bytes = self.reserved_bytes = self.idle_bytes = 0
         self.req_by_rid = {r.rid: r for r in requests}
         self.stats = Stats()
@@ -861,6 +862,9 @@ class RealtimeServer:
             except AdmissionRefused:
                 time.sleep(0.0005)   # wait for retirements to free budget
                 continue
+            except BaseException as e:   # handed to the tick loop, which raises it
+                self._error = e
+                return
             with self._lock:
                 self._to_prepare.popleft()
                 self._prepared[req.rid] = item
@@ -1000,6 +1004,8 @@ class RealtimeServer:
             now = T.taches_server_clock(sv)
             if now >= duration_s:
                 break
+            if self._error is not None:
+                raise RuntimeError("admission failed") from self._error
             t0 = clock()
             n_adm = self.stats.admitted
             self._admit(now)

@@ -411,3 +411,18 @@ def test_server_tick_full_load_sampled_parity():
         checked += 1
     assert checked == len(keep) and segmented >= 2
     srv.close()
+
+
+def test_server_admission_failure_is_raised():
+    """An error on the preparing thread (forced from the host) stops the
+    run with an exception instead of leaving requests unadmitted."""
+    from paper_2401_01607_amd.serving import RealtimeServer
+    reqs = W.config5_requests(horizon_s=0.2, rate_hz=20.0, seed=80, dur=(0.2, 0.3), lrange=(512, 2048))
+    srv = RealtimeServer(reqs, max_streams=8, hbm_budget_bytes=1 << 30)
+
+    def fail(req):
+        raise MemoryError("forced")
+    srv._prepare = fail
+    with pytest.raises(RuntimeError, match="admission failed"):
+        srv.run_realtime(2.0)
+    srv.close()
