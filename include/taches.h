@@ -414,6 +414,7 @@ typedef struct taches_server_stats {
   int64_t recorded;               /* blocks with a latency record, whose latencies split into: */
   double pickup_s;                /*   summed time from a block's arrival to the start of its tick */
   double service_s;               /*   summed time from the start of its tick to its outputs in host memory */
+  double device_s;                /* summed device time of the completed steps, input copy to output copy */
 } taches_server_stats;
 
 /* NULL on failure.  fs > 0 (samples per second), max_blocks_per_step >= 1

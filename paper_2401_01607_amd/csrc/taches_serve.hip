@@ -152,6 +152,7 @@ struct taches_server {
   // reference for the next), and the host time of the last completed one
   static constexpr int kEv = 4;
   hipEvent_t ev[kEv] = {};
+  hipEvent_t ev_beg[kEv] = {};   // a step's start on the device (before its input copy)
   int ev_next = 0;
   int ref_ev = -1;
   double ref_t = 0.0;
@@ -238,6 +239,7 @@ int complete_flight(taches_server* sv) {
     done = std::min(t1, sv->ref_t + (double)ms * 1e-3);
   sv->ref_ev = f.ev;
   sv->ref_t = done;
+  if (hipEventElapsedTime(&ms, sv->ev_beg[f.ev], sv->ev[f.ev]) == hipSuccess) sv->stats.device_s += (double)ms * 1e-3;
   const double fs = sv->fs;
   for (const FlightRange& q : f.ranges) {
     if (q.y) {
@@ -293,9 +295,11 @@ taches_server* taches_server_create(taches_pool* pool, double fs, int32_t max_bl
   sv->warmup_s = warmup_s;
   sv->t0 = std::chrono::steady_clock::now();
   for (int k = 0; k < taches_server::kEv; ++k) {
-    if (hipEventCreate(&sv->ev[k]) != hipSuccess) {
+    if (hipEventCreate(&sv->ev[k]) != hipSuccess || hipEventCreate(&sv->ev_beg[k]) != hipSuccess) {
       taches::set_error(TACHES_EDEVICE, "serving: event creation failed");
-      for (int j = 0; j < k; ++j) (void)hipEventDestroy(sv->ev[j]);
+      for (int j = 0; j <= k; ++j)
+        for (hipEvent_t e : {sv->ev[j], sv->ev_beg[j]})
+          if (e) (void)hipEventDestroy(e);
       delete sv;
       return nullptr;
     }
@@ -312,8 +316,9 @@ int taches_server_destroy(taches_server* sv) {
   }
   (void)hipFree(sv->x_dev);
   (void)hipFree(sv->y_dev);
-  for (hipEvent_t e : sv->ev)
-    if (e) (void)hipEventDestroy(e);
+  for (int k = 0; k < taches_server::kEv; ++k)
+    for (hipEvent_t e : {sv->ev[k], sv->ev_beg[k]})
+      if (e) (void)hipEventDestroy(e);
   delete sv;
   return TACHES_OK;
 }
@@ -620,8 +625,11 @@ int taches_server_tick(taches_server* sv, taches_server_tick_info* out) {
     if (rc != TACHES_OK) return rc;
   }
   const double t_launch = clock_s(sv);
-  if (x_floats > 0) {
-    const hipError_t e = hipMemcpyAsync(sv->x_dev, sv->x_pin[buf], x_floats * 4, hipMemcpyHostToDevice, hs);
+  const int evk = sv->ev_next;
+  {
+    hipError_t e = hipEventRecord(sv->ev_beg[evk], hs);
+    if (e == hipSuccess && x_floats > 0)
+      e = hipMemcpyAsync(sv->x_dev, sv->x_pin[buf], x_floats * 4, hipMemcpyHostToDevice, hs);
     if (e != hipSuccess) return taches::set_error(TACHES_EDEVICE, "serving: input copy: %s", hipGetErrorString(e));
   }
   rc = taches_pool_step(sv->pool, (int32_t)m, sv->a_s.data(), sv->a_x.data(), sv->a_y.data(), sv->a_n.data());
@@ -632,8 +640,7 @@ int taches_server_tick(taches_server* sv, taches_server_tick_info* out) {
     ServeStream& r = sv->st[sv->a_idx[j]];
     (sv->a_rest[j] ? r.r_next : r.next) = sv->a_k0[j] + sv->a_n[j];
   }
-  const int evk = sv->ev_next;
-  sv->ev_next = (sv->ev_next + 1) % taches_server::kEv;
+  sv->ev_next = (evk + 1) % taches_server::kEv;
   {
     hipError_t e = hipSuccess;
     if (n_ops) {

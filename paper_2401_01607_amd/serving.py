@@ -1048,6 +1048,8 @@ class RealtimeServer:
         out["bytes_h2d"] = int(st.bytes_in)
         out["bytes_d2h"] = int(st.bytes_out)
         out["gpu_busy_fraction"] = round(self.pool.info().device_ms_total / 1e3 / wall_s, 3) if wall_s > 0 else 0.0
+        # the whole step on the device: input copy, batched launch, ring kernels, output copy
+        out["device_step_busy_fraction"] = round(float(st.device_s) / wall_s, 3) if wall_s > 0 else 0.0
         if st.ticks:
             out["tick_ms_mean"] = {k: round(getattr(st, k + "_s") / st.ticks * 1e3, 4)
                                    for k in ("busy", "gather", "launch", "wait", "scatter")}

@@ -70,7 +70,7 @@ class taches_server_stats(ctypes.Structure):
                 ("bytes_out", ctypes.c_int64), ("busy_s", ctypes.c_double), ("gather_s", ctypes.c_double),
                 ("launch_s", ctypes.c_double), ("wait_s", ctypes.c_double), ("scatter_s", ctypes.c_double),
                 ("streams", ctypes.c_int32), ("pad_", ctypes.c_int32), ("recorded", ctypes.c_int64),
-                ("pickup_s", ctypes.c_double), ("service_s", ctypes.c_double)]
+                ("pickup_s", ctypes.c_double), ("service_s", ctypes.c_double), ("device_s", ctypes.c_double)]
 
 
 _vp, _i32, _i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
