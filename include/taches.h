@@ -131,6 +131,15 @@ int taches_set_ir_device(taches_stream* s, const float* h_dev, int32_t L);
  * before `offset`. */
 int taches_set_ir_at(taches_stream* s, const float* h, int32_t L, int32_t offset, int32_t h_on_device);
 
+/* As taches_set_ir_at with a device IR, without copying it: the stream reads
+ * h_dev[0..L) in place from sample `offset` of the next processed block on.
+ * The caller keeps those L floats unchanged and allocated until a later IR
+ * has taken over and every block enqueued with this one has completed (for
+ * a stream attached to a pool: until the pool's queued steps are done).
+ * TACHES_EINVAL on a SPLIT_BF16 stream (its MFMA path needs the BF16 split
+ * of a copy) and for the sizes taches_set_ir_at refuses. */
+int taches_set_ir_ref(taches_stream* s, const float* h_dev, int32_t L, int32_t offset);
+
 /* Load h[0..L) into IR slot `slot` (0 <= slot < ir_slots) for use by an IR
  * schedule of taches_process_blocks.  h_on_device selects host or device
  * memory for h.  Loading the active slot is allowed: the copy is ordered
@@ -437,7 +446,9 @@ double taches_server_clock(const taches_server* sv);
  * channel, or NULL to discard the outputs after their transfer.
  * n_swaps IR changes: ascending times swap_times_s (seconds from the
  * stream's start), device IRs swap_ir_dev[i] of swap_len[i] taps (alive
- * until applied).  TACHES_EINVAL for bad sizes or a duplicate tag. */
+ * until the stream is reported finished: an FP32 stream reads them in
+ * place, taches_set_ir_ref; a split-BF16 stream copies each when it
+ * applies).  TACHES_EINVAL for bad sizes or a duplicate tag. */
 int taches_server_add(taches_server* sv, taches_stream* s, int64_t tag, double start_s, int64_t n_in_blocks,
                       int64_t n_total_blocks, const float* x_host, int64_t x_cstride, float* y_host, int64_t y_cstride,
                       int32_t n_swaps, const double* swap_times_s, const float* const* swap_ir_dev,
@@ -456,7 +467,8 @@ int taches_server_add(taches_server* sv, taches_stream* s, int64_t tag, double s
  * max_blocks_per_step blocks per call, `rest` at least one.  The library
  * loads the two segments of ir_dev [ir_len] (H < ir_len <= H + rest
  * capacity) as the initial IR, and of each change's IR (swap_len[i] in the
- * same range) when it applies: the rest segment takes over at the same
+ * same range) when it applies, reading them in place (taches_set_ir_ref:
+ * ir_dev and the change IRs stay allocated until the stream finishes): the rest segment takes over at the same
  * input sample as the head (an IR change inside a rest block), so two
  * changes applying inside one rest block are refused, the initial IR
  * counting as a change at sample 0.  A tick runs a head

@@ -112,6 +112,7 @@ int validate(const taches_config* c) {
 
 struct IrSlot {
   float* h = nullptr;       // device, Lmax taps
+  const float* ref = nullptr;   // the caller's device IR, read in place instead of h (FP32 only)
   uint16_t* hi = nullptr;   // device BF16 hi copy (split precision)
   uint16_t* lo = nullptr;   // device BF16 lo copy
   int L = 0;
@@ -233,6 +234,7 @@ int stream_init(taches_stream* s) {
 
 int load_slot(taches_stream* s, int slot, const float* h, int L, bool on_device) {
   IrSlot& sl = s->slots[slot];
+  sl.ref = nullptr;
   if (on_device) {
     HIPCHK(hipMemcpyAsync(sl.h, h, (size_t)L * 4, hipMemcpyDeviceToDevice, s->stream));
   } else {
@@ -497,7 +499,7 @@ int plan_call(taches_stream* s, const float* x_dev, int64_t x_cstride, float* y_
   auto ir_of = [&](int k) {
     BlockIR ir{};
     if (k >= 0) {
-      ir.h = s->slots[k].h;
+      ir.h = s->slots[k].ref ? s->slots[k].ref : s->slots[k].h;
       ir.h_hi = s->slots[k].hi;
       ir.h_lo = s->slots[k].lo;
       ir.L = s->slots[k].L;
@@ -775,6 +777,31 @@ static int set_ir_common(taches_stream* s, const float* h, int32_t L, bool on_de
 }
 
 int taches_set_ir(taches_stream* s, const float* h, int32_t L) { return set_ir_common(s, h, L, false); }
+
+int taches_set_ir_ref(taches_stream* s, const float* h_dev, int32_t L, int32_t offset) {
+  if (!s) return fail(TACHES_EINVAL, "stream is NULL");
+  if (!h_dev) return fail(TACHES_EINVAL, "h is NULL");
+  if (is_split(s->cfg)) return fail(TACHES_EINVAL, "an IR read in place needs FP32 precision");
+  if (L < 1 || L > s->cfg.max_ir_len) return fail(TACHES_EINVAL, "L=%d outside [1, %d]", L, s->cfg.max_ir_len);
+  if (offset < 0 || offset >= s->cfg.block_size)
+    return fail(TACHES_EINVAL, "offset %d outside [0, %d)", offset, s->cfg.block_size);
+  // the same slot choice as a copy; only the pointer changes on the host,
+  // so calls already planned keep reading what they were planned with
+  int slot = s->pending;
+  if (slot < 0) {
+    for (int k = 0; k < (int)s->slots.size(); ++k)
+      if (k != s->active) {
+        slot = k;
+        break;
+      }
+  }
+  IrSlot& sl = s->slots[slot];
+  sl.ref = h_dev;
+  sl.L = L;
+  s->pending = slot;
+  s->pending_off = offset;
+  return TACHES_OK;
+}
 
 int taches_set_ir_at(taches_stream* s, const float* h, int32_t L, int32_t offset, int32_t h_on_device) {
   return set_ir_common(s, h, L, h_on_device != 0, offset);
@@ -1103,7 +1130,10 @@ int taches_reset(taches_stream* s) {
   // The ring is not cleared: with live = 0 no kernel reads a slot before
   // writing it (slots past `live` count as zero, and emitted slots are
   // cleared as they are read), and taches_read_tail reports zeros there.
-  for (auto& sl : s->slots) sl.L = 0;
+  for (auto& sl : s->slots) {
+    sl.L = 0;
+    sl.ref = nullptr;
+  }
   s->active = s->pending = -1;
   s->head = s->live = 0;
   s->blocks_done = 0;

@@ -62,6 +62,7 @@ struct ServeStream {
   std::vector<int32_t> swap_L;
   size_t swap_next = 0;
   std::vector<int64_t> swap_blocks;   // block index at which each applied swap took effect
+  bool in_place = false;              // FP32: IRs are read in place (taches_set_ir_ref), not copied
   // two-segment streams (rs != nullptr): the rest segment h[H, L)
   taches_stream* rs = nullptr;
   int32_t H = 0, Br = 0, r_cap = 1;
@@ -363,6 +364,7 @@ int fill_record(taches_server* sv, taches_stream* s, int64_t tag, double start_s
   }
   ServeStream& r = *out;
   r.s = s;
+  r.in_place = inf->precision == TACHES_PREC_FP32;
   r.tag = tag;
   r.start_s = start_s;
   r.B = inf->block_size;
@@ -438,8 +440,8 @@ int taches_server_add_segmented(taches_server* sv, taches_stream* head, taches_s
     ss.push_back(smp);
     prev = smp;
   }
-  rc = taches_set_ir_device(head, ir_dev, H);
-  if (rc == TACHES_OK) rc = taches_set_ir_device(rest, ir_dev + H, ir_len - H);
+  rc = taches_set_ir_ref(head, ir_dev, H, 0);
+  if (rc == TACHES_OK) rc = taches_set_ir_ref(rest, ir_dev + H, ir_len - H, 0);
   if (rc != TACHES_OK) return rc;
   r.rs = rest;
   r.H = H;
@@ -502,7 +504,7 @@ int taches_server_tick(taches_server* sv, taches_server_tick_info* out) {
               const int64_t off = std::max<int64_t>(0, r.swap_s[q] - j0 * r.Br);
               const float* h = r.swap_h[q] + r.H;
               const int32_t L = r.swap_L[q] - r.H;
-              int rc = off == 0 ? taches_set_ir_device(r.rs, h, L) : taches_set_ir_at(r.rs, h, L, (int32_t)off, 1);
+              int rc = taches_set_ir_ref(r.rs, h, L, (int32_t)off);
               if (rc != TACHES_OK) return rc;
               ++r.r_swap_next;
             }
@@ -525,7 +527,8 @@ int taches_server_tick(taches_server* sv, taches_server_tick_info* out) {
     if (is_in) {
       while (r.swap_next < r.swap_t.size() && r.swap_t[r.swap_next] <= (double)(k0 * r.B) / fs) {
         const int32_t L = r.rs ? r.H : r.swap_L[r.swap_next];
-        int rc = taches_set_ir_device(r.s, r.swap_h[r.swap_next], L);
+        int rc = r.in_place ? taches_set_ir_ref(r.s, r.swap_h[r.swap_next], L, 0)
+                            : taches_set_ir_device(r.s, r.swap_h[r.swap_next], L);
         if (rc != TACHES_OK) return rc;
         r.swap_blocks.push_back(k0);
         ++r.swap_next;

@@ -919,7 +919,10 @@ class RealtimeServer:
                 self.kept[req.rid] = y
             swaps = [self.ir(req, v + 1) for v in range(len(req.swap_times_s))]
             if ring is None:
-                streams[0].set_ir(self.ir(req, 0))
+                if self.precision == T.TACHES_PREC_FP32:   # read in place: the IRs live until retirement
+                    _ = T._check(T.taches_set_ir_ref(streams[0].h, self.ir(req, 0)), "taches_set_ir_ref")
+                else:
+                    streams[0].set_ir(self.ir(req, 0))
                 rc = T.taches_server_add(self.sv, streams[0].h, req.rid, now, n_in, n_total, self.input_signal(req),
                                          y, req.swap_times_s, swaps)
                 _ = T._check(rc, "taches_server_add")

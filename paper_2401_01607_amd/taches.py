@@ -114,6 +114,7 @@ _SIGS = {
     "taches_fp32_fma_ceiling": (ctypes.c_int, [_i32, _P(ctypes.c_double)]),
     "taches_convolve": (ctypes.c_int, [_vp, _i64, _i32, _vp, _i32, _vp, _i32, _i32, _i32, _vp]),
     "taches_convolve_noalloc": (ctypes.c_int, [_vp, _i64, _i32, _vp, _i32, _vp, _i32, _i32, _vp]),
+    "taches_set_ir_ref": (ctypes.c_int, [_vp, _vp, _i32, _i32]),
     "taches_server_create": (_vp, [_vp, ctypes.c_double, _i32, ctypes.c_double]),
     "taches_server_destroy": (ctypes.c_int, [_vp]),
     "taches_server_clock": (ctypes.c_double, [_vp]),
@@ -192,6 +193,12 @@ def taches_set_ir(s, h: np.ndarray) -> int:
 
 def taches_set_ir_device(s, h_dev) -> int:
     return lib.taches_set_ir_device(s, _dev_ptr(h_dev), int(h_dev.numel()))
+
+
+def taches_set_ir_ref(s, h_dev, offset: int = 0) -> int:
+    """h_dev: a contiguous float32 CUDA tensor the stream reads in place
+    (kept alive and unchanged by the caller until replaced and done)."""
+    return lib.taches_set_ir_ref(s, _dev_ptr(h_dev), int(h_dev.numel()), int(offset))
 
 
 def taches_set_ir_at(s, h, offset: int) -> int:

@@ -471,3 +471,51 @@ def test_reset_stream_equals_fresh_stream(tail):
         assert np.array_equal(used.read_tail(c, L), fresh.read_tail(c, L))
     used.close()
     fresh.close()
+
+
+def test_ir_read_in_place_equals_copied_ir():
+    """taches_set_ir_ref (the stream reads the caller's device IR without a
+    copy) gives the same bits as taches_set_ir / taches_set_ir_at, for swaps
+    at block starts and inside blocks, block by block and through a pool;
+    refused on a split-BF16 stream."""
+    import torch
+    from tests.gpu_harness import binding
+    T = binding()
+    B, L, C, nb = 128, 2500, 2, 30
+    x = np.stack([W.signal_gauss(nb * B, 930 + c) for c in range(C)])
+    hs = [torch.from_numpy(W.impulse_response(L - 300 * v, 940 + v)).cuda() for v in range(3)]
+    swaps = {0: (0, 0), 7: (1, 0), 12: (2, 37), 20: (0, 101)}   # block -> (IR, offset)
+
+    def run(ref, pool=None):
+        s = T.Stream(B, L, channels=C)
+        if pool is not None:
+            assert pool.attach(s) == T.TACHES_OK
+        ys = []
+        for k in range(nb):
+            if k in swaps:
+                v, off = swaps[k]
+                if ref:
+                    assert T.taches_set_ir_ref(s.h, hs[v], off) == T.TACHES_OK
+                else:
+                    s.set_ir(hs[v], offset=off)
+            xb = torch.from_numpy(np.ascontiguousarray(x[:, k * B:(k + 1) * B])).cuda()
+            y = torch.empty((C, B), device="cuda")
+            if pool is None:
+                s.process_async(xb, y)
+            else:
+                pool.step([s], [xb], [y], [1])
+            ys.append(y)
+        torch.cuda.synchronize()
+        out = torch.cat(ys, dim=1).cpu().numpy()
+        if pool is not None:
+            pool.detach(s)
+        s.close()
+        return out
+    base = run(False)
+    assert np.array_equal(run(True), base)
+    pool = T.Pool(4, 1 << 30, use_graph=True)
+    assert np.array_equal(run(True, pool), base)
+    pool.close()
+    sp = T.Stream(B, L, channels=C, precision=T.TACHES_PREC_SPLIT_BF16)
+    assert T.taches_set_ir_ref(sp.h, hs[0], 0) == T.TACHES_EINVAL
+    sp.close()
