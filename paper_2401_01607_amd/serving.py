@@ -897,7 +897,8 @@ class RealtimeServer:
         while self.queue and limit > 0:
             req = self.queue[0]
             if len(self.live) >= self.max_streams:
-                self.refused += 1
+                with self._lock:   # the preparing thread counts budget refusals
+                    self.refused += 1
                 return
             with self._lock:
                 item = self._prepared.pop(req.rid, None)
