@@ -1303,7 +1303,9 @@ int pool_reserve(taches_pool* p, size_t bytes) {
     p->tab_dev[k] = nullptr;
   }
   p->tab_cap = 0;
-  const size_t cap = align256(bytes + bytes / 2);
+  // grow by 2x, at least 4 MB: a reallocation waits for the pool's stream
+  // and drops the captured graphs, so a growing load should meet few of them
+  const size_t cap = align256(std::max<size_t>(2 * bytes, size_t(4) << 20));
   for (int k = 0; k < 2; ++k) {
     hipError_t e = hipHostMalloc((void**)&p->tab_pin[k], cap, hipHostMallocDefault);
     if (e != hipSuccess) return fail(TACHES_ENOMEM, "pool table (host): %s", hipGetErrorString(e));

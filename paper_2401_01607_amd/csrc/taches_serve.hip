@@ -194,9 +194,9 @@ ServeStream* find_tag(taches_server* sv, int64_t tag, bool with_done = false) {
 
 // Larger staging (called with no step in flight).
 int grow(taches_server* sv, size_t floats) {
-  // capacity grows in large steps (at least 8 M floats, then 4x): a larger
+  // capacity grows in large steps (at least 16 M floats, then 4x): a larger
   // staging costs pinned allocations and frees, which stall the tick
-  constexpr size_t kMinFloats = size_t(1) << 23;
+  constexpr size_t kMinFloats = size_t(1) << 24;
   if (floats > sv->pin_cap) {
     const size_t cap = std::max({floats, 4 * sv->pin_cap, kMinFloats});
     for (int k = 0; k < 2; ++k) {
