@@ -459,8 +459,9 @@ int taches_server_add(taches_server* sv, taches_stream* s, int64_t tag, double s
  * head_len, and is advanced every tick as in taches_server_add; `rest`
  * (block Br, a multiple of B with Br <= H) convolves with h[H, L) and is
  * advanced once per Br samples, its outputs z kept on the device in the
- * ring z_dev [C][z_len] (caller-owned, z_len >= Br + B, alive until the
- * stream finishes; contents need no initialisation); the result is
+ * ring z_dev [C][z_len] (caller-owned, z_len a multiple of Br and at least
+ * 2 Br, alive until the stream finishes; contents need no initialisation);
+ * the result is
  * y[n] = y_head[n] + z[n - H] (FP32 add), written to y_host as in
  * taches_server_add.  Both streams must be attached to the server's pool,
  * FP32 precision, with the same channel count; `head` must take

@@ -22,9 +22,9 @@
 // stream keeps the long tail and is advanced once per Br samples instead of
 // once per tick, so a tick reads and writes H + B tail slots of the stream
 // instead of L + B.  Its outputs stay on the device in a ring [C][Z] owned
-// by the caller; after the pool step, one launch stores them into the ring
-// and a second adds the ring into the head outputs before those are copied
-// back.  A head block is run only once the rest blocks it needs have been
+// by the caller (the pool step writes them there in place); after the pool
+// step, one launch adds the ring into the head outputs while it writes every
+// output block to the mapped host staging (the copy back).  A head block is run only once the rest blocks it needs have been
 // enqueued (by arrival they always have: their last sample comes no later
 // than the head block's, as Br <= H), and rest blocks wait while their
 // outputs would overwrite ring entries not yet added.
@@ -82,29 +82,33 @@ int64_t first_block_at(double t, int32_t B, double fs, int64_t k_min) {
   return k;
 }
 
-// One ring operation of a step: C rows of len outputs (row stride y_cs) in
-// the step's device staging, against ring positions p0, p0 + 1, ... (mod Z)
-// of the rows of z.
-struct ZOp {
-  float* y;
-  float* z;
-  int32_t y_cs, len, C, Z, p0, pad_;
+// The outputs of one range of a step, from the device staging (C rows of
+// len) to the host staging (the same layout, pinned and mapped for the
+// device); for a two-segment stream, ring entries p0, p0 + 1, ... (mod Z) of
+// the rows of z are added from output `skip` on (outputs before sample H
+// get nothing).
+struct OutOp {
+  const float* y;
+  float* out;
+  const float* z;   // nullptr: a stream served whole
+  int32_t len, C, Z, p0, skip, pad_;
 };
 
-// add == 0: store the outputs into the ring; add != 0: add the ring entries
-// into the outputs.  One workgroup per operation.
-__global__ __launch_bounds__(256) void k_zring(const ZOp* __restrict__ ops, int add) {
-  const ZOp o = ops[blockIdx.x];
+// One workgroup per range: the ring add and the copy back in one pass.
+__global__ __launch_bounds__(256) void k_out(const OutOp* __restrict__ ops) {
+  const OutOp o = ops[blockIdx.x];
   for (int c = 0; c < o.C; ++c) {
-    float* y = o.y + (int64_t)c * o.y_cs;
-    float* z = o.z + (int64_t)c * o.Z;
+    const float* y = o.y + (int64_t)c * o.len;
+    float* out = o.out + (int64_t)c * o.len;
+    const float* z = o.z ? o.z + (int64_t)c * o.Z : nullptr;
     for (int i = threadIdx.x; i < o.len; i += blockDim.x) {
-      int pos = o.p0 + i;
-      if (pos >= o.Z) pos -= o.Z;
-      if (add)
-        y[i] += z[pos];
-      else
-        z[pos] = y[i];
+      float v = y[i];
+      if (z && i >= o.skip) {
+        int pos = o.p0 + (i - o.skip);
+        if (pos >= o.Z) pos -= o.Z;
+        v += z[pos];
+      }
+      out[i] = v;
     }
   }
 }
@@ -144,7 +148,8 @@ struct taches_server {
   // its outputs are read after the next step is enqueued); one device pair
   // (copies and steps are ordered on the pool's stream)
   float* x_pin[2] = {nullptr, nullptr};
-  float* y_pin[2] = {nullptr, nullptr};
+  float* y_pin[2] = {nullptr, nullptr};      // mapped and coherent: written by k_out
+  float* y_pin_dev[2] = {nullptr, nullptr};  // their device addresses
   size_t pin_cap = 0;     // floats per buffer
   float* x_dev = nullptr;
   float* y_dev = nullptr;
@@ -164,6 +169,7 @@ struct taches_server {
   std::vector<taches_stream*> a_s;
   std::vector<const float*> a_x;
   std::vector<float*> a_y;
+  std::vector<int64_t> a_xcs, a_ycs;   // channel strides of the pool step's input and output
   std::vector<int32_t> a_n;
   std::vector<int32_t> a_idx;
   std::vector<int64_t> a_k0, a_xoff, a_yoff;
@@ -205,10 +211,13 @@ int grow(taches_server* sv, size_t floats) {
       sv->x_pin[k] = sv->y_pin[k] = nullptr;
     }
     sv->pin_cap = 0;
-    for (int k = 0; k < 2; ++k)
+    for (int k = 0; k < 2; ++k) {
+      sv->y_pin_dev[k] = nullptr;
       if (hipHostMalloc((void**)&sv->x_pin[k], cap * 4, hipHostMallocDefault) != hipSuccess ||
-          hipHostMalloc((void**)&sv->y_pin[k], cap * 4, hipHostMallocDefault) != hipSuccess)
+          hipHostMalloc((void**)&sv->y_pin[k], cap * 4, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+          hipHostGetDevicePointer((void**)&sv->y_pin_dev[k], sv->y_pin[k], 0) != hipSuccess)
         return taches::set_error(TACHES_ENOMEM, "serving: pinned staging of %zu floats", cap);
+    }
     sv->pin_cap = cap;
   }
   if (floats > sv->dev_cap) {
@@ -422,8 +431,9 @@ int taches_server_add_segmented(taches_server* sv, taches_stream* head, taches_s
     return taches::set_error(TACHES_EINVAL, "serving: segments need B | Br <= H <= head capacity (B %d, Br %d, H %d)",
                              hi.block_size, Br, H);
   if (ir_len < lmin || ir_len > lmax) return taches::set_error(TACHES_EINVAL, "serving: IR of %d taps for H = %d", ir_len, H);
-  if ((int64_t)z_len < (int64_t)Br + hi.block_size)
-    return taches::set_error(TACHES_EINVAL, "serving: ring of %d entries shorter than Br + B", z_len);
+  if (z_len < 2 * Br || z_len % Br != 0)
+    return taches::set_error(TACHES_EINVAL, "serving: ring of %d entries: not a multiple of Br = %d of at least 2 Br",
+                             z_len, Br);
   const int32_t B = hi.block_size;
   // input sample at which each change applies (the head's rule: the first
   // block starting at or after its time); changes after the input never apply
@@ -471,7 +481,7 @@ int taches_server_tick(taches_server* sv, taches_server_tick_info* out) {
   sv->a_yoff.clear();
   sv->a_rest.clear();
   sv->r_end.assign(sv->st.size(), 0);
-  size_t xf = 0, yf = 0, ryf = 0;   // input floats; head and rest output floats
+  size_t xf = 0, yf = 0;   // input floats; head output floats
   auto push_range = [&](taches_stream* s, int32_t n, size_t i, int64_t k0, bool in, size_t len, bool rest) {
     sv->a_s.push_back(s);
     sv->a_n.push_back(n);
@@ -479,8 +489,8 @@ int taches_server_tick(taches_server* sv, taches_server_tick_info* out) {
     sv->a_k0.push_back(k0);
     sv->a_xoff.push_back(in ? (int64_t)xf : -1);
     if (in) xf += len;
-    sv->a_yoff.push_back(rest ? (int64_t)ryf : (int64_t)yf);
-    (rest ? ryf : yf) += len;
+    sv->a_yoff.push_back(rest ? -1 : (int64_t)yf);   // rest outputs go straight into the ring
+    if (!rest) yf += len;
     sv->a_rest.push_back(rest ? 1 : 0);
   };
   for (size_t i = 0; i < sv->st.size(); ++i) {
@@ -495,6 +505,8 @@ int taches_server_tick(taches_server* sv, taches_server_tick_info* out) {
         const int64_t consumed = std::max<int64_t>(0, r.next * r.B - r.H);
         const int64_t j0 = r.r_next;
         int64_t end = std::min(std::min(arr, j0 + r.r_cap), (consumed + r.Z) / r.Br);
+        const int64_t zb = r.Z / r.Br;   // rest blocks per ring: a range is written in place, unwrapped
+        end = std::min(end, (j0 / zb + 1) * zb);
         if (end > j0) {
           const bool in = j0 < r.r_in;
           if (in) {
@@ -555,27 +567,13 @@ int taches_server_tick(taches_server* sv, taches_server_tick_info* out) {
     if (out) *out = info;
     return TACHES_OK;
   }
-  // rest outputs follow the head outputs in the staging; only the head
-  // outputs are copied back
-  for (size_t j = 0; j < m; ++j)
-    if (sv->a_rest[j]) sv->a_yoff[j] += (int64_t)yf;
-  // ring operations: stores of the rest outputs, then adds into the head
-  // outputs (a head range's outputs before sample H get nothing)
-  auto add_skip = [&](size_t j) -> int64_t {
-    const ServeStream& r = sv->st[sv->a_idx[j]];
-    return std::max<int64_t>(0, r.H - sv->a_k0[j] * r.B);
-  };
-  size_t n_store = 0, n_add = 0;
-  for (size_t j = 0; j < m; ++j) {
-    if (sv->a_rest[j])
-      ++n_store;
-    else if (sv->st[sv->a_idx[j]].rs && add_skip(j) < (int64_t)sv->a_n[j] * sv->st[sv->a_idx[j]].B)
-      ++n_add;
-  }
-  const size_t n_ops = n_store + n_add;
+  // one output operation per head range: the ring add (two-segment streams)
+  // and the copy into the mapped host staging
+  size_t n_ops = 0;
+  for (size_t j = 0; j < m; ++j) n_ops += sv->a_rest[j] ? 0 : 1;
   const size_t ops_off = (xf * 4 + 255) & ~(size_t)255;   // bytes: the ops follow the input
-  const size_t x_floats = n_ops ? (ops_off + n_ops * sizeof(ZOp) + 3) / 4 : xf;
-  const size_t y_floats = yf + ryf;
+  const size_t x_floats = n_ops ? (ops_off + n_ops * sizeof(OutOp) + 3) / 4 : xf;
+  const size_t y_floats = yf;
   const hipStream_t hs = taches::pool_stream(sv->pool);
   int rc = TACHES_OK;
   if (std::max(x_floats, y_floats) > std::min(sv->pin_cap, sv->dev_cap)) {
@@ -600,28 +598,44 @@ int taches_server_tick(taches_server* sv, taches_server_tick_info* out) {
     }
   }
   if (n_ops) {
-    ZOp* o = reinterpret_cast<ZOp*>(reinterpret_cast<unsigned char*>(sv->x_pin[buf]) + ops_off);
-    size_t qs = 0, qa = n_store;
+    OutOp* o = reinterpret_cast<OutOp*>(reinterpret_cast<unsigned char*>(sv->x_pin[buf]) + ops_off);
+    size_t q = 0;
     for (size_t j = 0; j < m; ++j) {
+      if (sv->a_rest[j]) continue;
       const ServeStream& r = sv->st[sv->a_idx[j]];
-      if (sv->a_rest[j]) {
-        const int32_t len = sv->a_n[j] * r.Br;
-        o[qs++] = ZOp{sv->y_dev + sv->a_yoff[j], r.z, len, len, r.C, r.Z, (int32_t)((sv->a_k0[j] * r.Br) % r.Z), 0};
-      } else if (r.rs) {
-        const int32_t len = sv->a_n[j] * r.B;
-        const int64_t skip = add_skip(j);
-        if (skip >= len) continue;
-        const int64_t m0 = sv->a_k0[j] * r.B + skip - r.H;   // ring index of the first output that gets one
-        o[qa++] = ZOp{sv->y_dev + sv->a_yoff[j] + skip, r.z, len, (int32_t)(len - skip), r.C, r.Z,
-                      (int32_t)(m0 % r.Z), 0};
+      const int32_t len = sv->a_n[j] * r.B;
+      OutOp op{sv->y_dev + sv->a_yoff[j], sv->y_pin_dev[buf] + sv->a_yoff[j], nullptr, len, r.C, 1, 0, len, 0};
+      if (r.rs) {
+        // ring index of the first output that gets a rest output (outputs
+        // before sample H get none)
+        const int64_t skip = std::min<int64_t>(len, std::max<int64_t>(0, r.H - sv->a_k0[j] * r.B));
+        if (skip < len) {
+          op.z = r.z;
+          op.Z = r.Z;
+          op.skip = (int32_t)skip;
+          op.p0 = (int32_t)((sv->a_k0[j] * r.B + skip - r.H) % r.Z);
+        }
       }
+      o[q++] = op;
     }
   }
+  // pool step arguments: head ranges read and write the staging (packed
+  // channels); rest ranges read the staging and write into the ring
   sv->a_x.resize(m);
   sv->a_y.resize(m);
+  sv->a_xcs.resize(m);
+  sv->a_ycs.resize(m);
   for (size_t j = 0; j < m; ++j) {
+    const ServeStream& r = sv->st[sv->a_idx[j]];
     sv->a_x[j] = sv->a_xoff[j] >= 0 ? sv->x_dev + sv->a_xoff[j] : nullptr;
-    sv->a_y[j] = sv->y_dev + sv->a_yoff[j];
+    sv->a_xcs[j] = 0;
+    if (sv->a_rest[j]) {
+      sv->a_y[j] = r.z + (sv->a_k0[j] * r.Br) % r.Z;
+      sv->a_ycs[j] = r.Z;
+    } else {
+      sv->a_y[j] = sv->y_dev + sv->a_yoff[j];
+      sv->a_ycs[j] = 0;
+    }
   }
   if (!sv->fl.active) {
     rc = anchor_clock(sv, hs);
@@ -635,7 +649,8 @@ int taches_server_tick(taches_server* sv, taches_server_tick_info* out) {
       e = hipMemcpyAsync(sv->x_dev, sv->x_pin[buf], x_floats * 4, hipMemcpyHostToDevice, hs);
     if (e != hipSuccess) return taches::set_error(TACHES_EDEVICE, "serving: input copy: %s", hipGetErrorString(e));
   }
-  rc = taches_pool_step(sv->pool, (int32_t)m, sv->a_s.data(), sv->a_x.data(), sv->a_y.data(), sv->a_n.data());
+  rc = taches_pool_step_strided(sv->pool, (int32_t)m, sv->a_s.data(), sv->a_x.data(), sv->a_xcs.data(),
+                                sv->a_y.data(), sv->a_ycs.data(), sv->a_n.data());
   if (rc != TACHES_OK) return rc;
   // the step is committed on the host: from here on, state advances even if
   // a later call reports an error
@@ -647,14 +662,12 @@ int taches_server_tick(taches_server* sv, taches_server_tick_info* out) {
   {
     hipError_t e = hipSuccess;
     if (n_ops) {
-      const ZOp* dops = reinterpret_cast<const ZOp*>(reinterpret_cast<unsigned char*>(sv->x_dev) + ops_off);
-      if (n_store) hipLaunchKernelGGL(k_zring, dim3((unsigned)n_store), dim3(256), 0, hs, dops, 0);
-      if (n_add) hipLaunchKernelGGL(k_zring, dim3((unsigned)n_add), dim3(256), 0, hs, dops + n_store, 1);
+      const OutOp* dops = reinterpret_cast<const OutOp*>(reinterpret_cast<unsigned char*>(sv->x_dev) + ops_off);
+      hipLaunchKernelGGL(k_out, dim3((unsigned)n_ops), dim3(256), 0, hs, dops);
       e = hipGetLastError();
     }
-    if (e == hipSuccess && yf > 0) e = hipMemcpyAsync(sv->y_pin[buf], sv->y_dev, yf * 4, hipMemcpyDeviceToHost, hs);
     if (e == hipSuccess) e = hipEventRecord(sv->ev[evk], hs);
-    if (e != hipSuccess) return taches::set_error(TACHES_EDEVICE, "serving: ring or output copy: %s", hipGetErrorString(e));
+    if (e != hipSuccess) return taches::set_error(TACHES_EDEVICE, "serving: output pass: %s", hipGetErrorString(e));
   }
   const double t_queued = clock_s(sv);
   // ---- the new step's book-keeping; finished streams leave the server ----

@@ -437,7 +437,7 @@ def segments_for(req, precision: int, fs: float = W.FS):
         br //= 2
     if L < 4 * br or not separated(br):
         return None
-    return br, br, 4 * br + 8 * B
+    return br, br, br * -(-(4 * br + 8 * B) // br)
 
 
 class GpuExecutor:

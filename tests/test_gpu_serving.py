@@ -323,7 +323,7 @@ def test_server_tick_small_budget_queues():
 def test_server_add_segmented_rejects_bad_shapes():
     """taches_server_add_segmented refuses (EINVAL, nothing registered)
     segments that break its rules: Br not a multiple of B, H < Br, a ring
-    shorter than Br + B, a split-BF16 stream, an IR no longer than H, and two
+    shorter than 2 Br or not a multiple of Br, a split-BF16 stream, an IR no longer than H, and two
     IR changes inside one rest block (the initial IR counting as one)."""
     import torch
     T = binding()
@@ -347,7 +347,8 @@ def test_server_add_segmented_rejects_bad_shapes():
     assert add(head, rest, 256, ring) == T.TACHES_EINVAL                     # H < Br
     odd = stream(96, 8192)
     assert add(head, odd, 1024, ring) == T.TACHES_EINVAL                     # Br not a multiple of B
-    assert add(head, rest, 1024, torch.empty((C, 512), device="cuda")) == T.TACHES_EINVAL   # ring < Br + B
+    assert add(head, rest, 1024, torch.empty((C, 512), device="cuda")) == T.TACHES_EINVAL   # ring < 2 Br
+    assert add(head, rest, 1024, torch.empty((C, 4000), device="cuda")) == T.TACHES_EINVAL  # not a multiple of Br
     assert add(head, rest, 1024, ring, ir=h[:1024]) == T.TACHES_EINVAL       # IR not longer than H
     split = stream(512, 8192, prec=T.TACHES_PREC_SPLIT_BF16)
     assert add(head, split, 1024, ring) == T.TACHES_EINVAL                   # rest segment not FP32

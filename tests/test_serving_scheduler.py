@@ -217,7 +217,7 @@ def test_segments_rule():
     for L, B in [(2048, 32), (41_940, 64), (262_144, 512), (8192, 512)]:
         H, br, Z = segments_for(_seg_request(L, B, []), fp32)
         assert br & (br - 1) == 0 and br % B == 0 and max(B, 256) <= br <= 2048 and H == br
-        assert L >= 4 * br and Z >= br + B
+        assert L >= 4 * br and Z % br == 0 and Z >= 4 * br + 8 * B
     # two changes inside one rest block: served whole
     H, br, _ = segments_for(_seg_request(65536, 32, []), fp32)
     assert segments_for(_seg_request(65536, 32, [br / W.FS + 32 / W.FS, br / W.FS + 96 / W.FS]), fp32) is None
