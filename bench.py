@@ -639,8 +639,8 @@ def extra_c5_serving(errors, duration_s=30.0, warmup_s=10.0):
     {32..512}, up to 4096 streams admitted by HBM budget, real-time paced at
     48 kHz.  Each tick is one library call: arrived input blocks gathered
     from host memory and copied to the device, one pool step (graph replay),
-    every output block copied back to host memory; latency ends when the
-    outputs are in host memory."""
+    every output block written to mapped host memory by one launch; latency
+    ends when the outputs are in host memory."""
     from paper_2401_01607_amd import workloads as W
     from paper_2401_01607_amd.serving import RealtimeServer
     from paper_2401_01607_amd import taches as T

@@ -380,14 +380,16 @@ int taches_pool_get_info(const taches_pool* p, taches_pool_info* out);
  * whose last sample has arrived by the server clock, over all registered
  * streams (at most max_blocks_per_step per stream), and runs them as one
  * pool step: the arrived input is gathered from each stream's host buffer
- * into pinned memory and copied to the device in one transfer; every output
- * block is copied back in one transfer and written to the stream's host
- * buffer (if any) when the step completes (during the next tick or flush).  An IR change scheduled at time
+ * into pinned memory and copied to the device in one transfer; after the
+ * pool step one launch writes every output block (for a two-segment stream,
+ * with the rest segment's ring added) to mapped, coherent pinned host
+ * memory, and the outputs are copied to the stream's host buffer (if any)
+ * when the step completes (during the next tick or flush).  An IR change scheduled at time
  * t (seconds from the stream's start) applies to the first block that
  * starts at or after t (the IR is replaced for the next samples, Abstract
- * and Section 6).  Latency of a block = the time its step's output copy
- * completed (outputs in host memory; a device event placed on the server
- * clock) minus the arrival time of its last sample; the deadline is one
+ * and Section 6).  Latency of a block = the time its step's output launch
+ * completed (outputs in host memory; a device event recorded after it,
+ * placed on the server clock) minus the arrival time of its last sample; the deadline is one
  * block period.  The server does not own streams: register an
  * attached stream, and detach it after its tag is reported finished.  A
  * server is not thread-safe.  After TACHES_EDEVICE from a tick, destroy the
@@ -412,18 +414,18 @@ typedef struct taches_server_stats {
   int64_t blocks;                 /* blocks processed */
   int64_t macs;                   /* direct-equivalent MACs of the input blocks */
   int64_t max_blocks_in_a_range;  /* most blocks of one stream in one step */
-  int64_t bytes_in, bytes_out;    /* host-to-device input and device-to-host output bytes */
+  int64_t bytes_in, bytes_out;    /* input bytes copied to the device, output bytes written to host memory */
   double busy_s;                  /* summed duration of the ticks that ran a step, split into: */
   double gather_s;                /*   ranges, IR changes and input gather on the host */
   double launch_s;                /*   input copy and pool step enqueued (step planning included) */
-  double wait_s;                  /*   waiting for the device (step and output copy) */
+  double wait_s;                  /*   waiting for the device (step and output launch) */
   double scatter_s;               /*   outputs to the streams' host buffers, latency records */
   int32_t streams;                /* streams registered and not finished */
   int32_t pad_;
   int64_t recorded;               /* blocks with a latency record, whose latencies split into: */
   double pickup_s;                /*   summed time from a block's arrival to the start of its tick */
   double service_s;               /*   summed time from the start of its tick to its outputs in host memory */
-  double device_s;                /* summed device time of the completed steps, input copy to output copy */
+  double device_s;                /* summed device time of the completed steps, input copy to output launch */
 } taches_server_stats;
 
 /* NULL on failure.  fs > 0 (samples per second), max_blocks_per_step >= 1
@@ -485,7 +487,7 @@ int taches_server_add_segmented(taches_server* sv, taches_stream* head, taches_s
                                 const double* swap_times_s, const float* const* swap_ir_dev, const int32_t* swap_len);
 
 /* One tick at the current server clock: if any block is due, enqueues its
- * step (input copy, pool step, output copy) on the pool's stream; then waits
+ * step (input copy, pool step, output launch) on the pool's stream; then waits
  * for the previous tick's step, hands its outputs to the host buffers and
  * records its latencies (so the host prepares step k + 1 while the device
  * runs step k).  Fills *out (may be NULL).  A stream whose last block has

@@ -8,8 +8,9 @@
 // last sample has arrived by the tick's clock reading, over all streams,
 // and runs them as one pool step: the arrived input is gathered from each
 // stream's host buffer into pinned memory, copied to the device in one
-// transfer, processed by the pool's batched launch, and every output block
-// is copied back in one transfer and handed to the stream's host buffer.
+// transfer and processed by the pool's batched launch; one more launch
+// writes every output block to mapped, coherent pinned host memory, from
+// where it is handed to the stream's host buffer.
 // An IR change scheduled at time t of a stream applies to its first block
 // that starts at or after t (the IR is replaced "for next samples",
 // Abstract and Section 6): a step's range of blocks ends before such a
@@ -24,17 +25,17 @@
 // instead of L + B.  Its outputs stay on the device in a ring [C][Z] owned
 // by the caller (the pool step writes them there in place); after the pool
 // step, one launch adds the ring into the head outputs while it writes every
-// output block to the mapped host staging (the copy back).  A head block is run only once the rest blocks it needs have been
-// enqueued (by arrival they always have: their last sample comes no later
+// output block to the mapped host staging.  A head block is run only once
+// the rest blocks it needs have been enqueued (by arrival they always have: their last sample comes no later
 // than the head block's, as Br <= H), and rest blocks wait while their
 // outputs would overwrite ring entries not yet added.
 //
 // Ticks overlap with the device: a tick enqueues its step (input copy, pool
-// step, output copy) and then waits for the previous tick's step, so the
+// step, output launch) and then waits for the previous tick's step, so the
 // host gathers and plans step k + 1 while the device runs step k, and the
 // device always has the next step queued.  Latency of a block = the time
-// its outputs are in host memory (the output copy's completion event,
-// placed on the host clock) minus the arrival time of the block's last
+// its outputs are in host memory (the completion event recorded after the
+// output launch, placed on the host clock) minus the arrival time of the block's last
 // sample; the deadline is one block period.
 #include <algorithm>
 #include <chrono>
@@ -94,7 +95,7 @@ struct OutOp {
   int32_t len, C, Z, p0, skip, pad_;
 };
 
-// One workgroup per range: the ring add and the copy back in one pass.
+// One workgroup per range: the ring add and the write to host memory in one pass.
 __global__ __launch_bounds__(256) void k_out(const OutOp* __restrict__ ops) {
   const OutOp o = ops[blockIdx.x];
   for (int c = 0; c < o.C; ++c) {
@@ -132,7 +133,7 @@ struct FlightRange {
 struct Flight {
   bool active = false;
   int buf = 0;        // pinned buffer pair used
-  int ev = 0;         // completion event (after the output copy)
+  int ev = 0;         // completion event (after the output launch)
   std::vector<FlightRange> ranges;
 };
 

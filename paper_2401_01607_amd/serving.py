@@ -666,7 +666,8 @@ class RealtimeServer:
     retirement of finished streams.  Everything per tick (which blocks
     have arrived, IR changes due, the ranges of blocks, gathering the
     arrived input into pinned memory, the host-to-device copy, the pool
-    step, the device-to-host copy of every output block, latency records)
+    step, one launch writing every output block to mapped host memory,
+    latency records)
     runs in one library call, which enqueues its step and then completes
     the previous one, so host and device work overlap.
 
@@ -677,7 +678,7 @@ class RealtimeServer:
     paper's IR shape, unit L2 norm, from a generator seeded by the request)
     and kept until the request finishes (the IRs of kept requests until
     close).  Outputs of requests listed in keep_outputs are written to host
-    arrays; the others are copied back and dropped."""
+    arrays; the others are written to host staging and dropped."""
 
     BANK_SECONDS = 70.0
 
@@ -1052,7 +1053,7 @@ class RealtimeServer:
         out["bytes_h2d"] = int(st.bytes_in)
         out["bytes_d2h"] = int(st.bytes_out)
         out["gpu_busy_fraction"] = round(self.pool.info().device_ms_total / 1e3 / wall_s, 3) if wall_s > 0 else 0.0
-        # the whole step on the device: input copy, batched launch, ring kernels, output copy
+        # the whole step on the device: input copy, batched launch, output launch
         out["device_step_busy_fraction"] = round(float(st.device_s) / wall_s, 3) if wall_s > 0 else 0.0
         if st.ticks:
             out["tick_ms_mean"] = {k: round(getattr(st, k + "_s") / st.ticks * 1e3, 4)
