@@ -660,6 +660,21 @@ def extra_c5_serving(errors, duration_s=30.0, warmup_s=10.0):
                "run_s": duration_s, "warmup_s": warmup_s, "last_step_items": info.last_items,
                "last_plan_ms": round(info.last_plan_ms, 3), "graph_replays": int(info.graph_replays),
                "graph_captures": int(info.graph_captures)})
+    # the same arrivals with admission held while more than 1 % of the blocks
+    # of >= 64 samples miss their deadline (queued requests wait instead)
+    from paper_2401_01607_amd.serving import MissGate
+    gate_s, gate_warm = 20.0, 5.0
+    rg = W.config5_requests(horizon_s=gate_s)
+    gate = MissGate(0.01, min_block=64)
+    srvg = RealtimeServer(rg, max_streams=4096, hbm_budget_bytes=64 << 30, use_graph=True, warmup_s=gate_warm,
+                          miss_gate=gate)
+    sg = srvg.run_realtime(gate_s)
+    srvg.close()
+    print("bench: c5 full-load run with the miss gate done", file=sys.stderr, flush=True)
+    st["with_miss_gate"] = {"run_s": gate_s, "warmup_s": gate_warm, **{
+        k: sg[k] for k in ("admitted", "max_active_streams", "latency_ms_p50", "latency_ms_p99", "latency_ms_max",
+                           "deadline_miss_fraction", "by_block_size", "queue_wait_s_p50", "queue_wait_s_p99",
+                           "gmacs", "device_step_busy_fraction", "miss_gate") if k in sg}}
     st["precision_at_20_per_s"] = {}
     for name, prec in (("fp32", T.TACHES_PREC_FP32), ("split_bf16", T.TACHES_PREC_SPLIT_BF16)):
         r2 = W.config5_requests(horizon_s=10.0, rate_hz=20.0, seed=502)

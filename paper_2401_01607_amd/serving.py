@@ -656,6 +656,37 @@ class GpuExecutor:
         self.pool.close()
 
 
+class MissGate:
+    """Admission gate fed by observed deadline misses: after each batch of
+    latency records it closes when more than `target` of the blocks of at
+    least `min_block` samples missed their deadline (one block period), and
+    reopens when the fraction falls to target / 2 or below.  While it is
+    closed, queued requests wait.  Blocks of fewer than min_block samples are
+    left out: at full load their period can be shorter than a step's service
+    time, so they would hold the gate closed at any load.  The server records
+    latencies only after its warm-up, so the gate acts from then on."""
+
+    def __init__(self, target: float, min_block: int = 64, fs: float = W.FS):
+        if not 0.0 < target < 1.0:
+            raise ValueError("target must be in (0, 1)")
+        self.target, self.min_block, self.fs = float(target), int(min_block), float(fs)
+        self.closed = False
+        self.checks = self.closed_checks = 0
+
+    def update(self, latency_s: np.ndarray, block: np.ndarray) -> None:
+        sel = np.asarray(block) >= self.min_block
+        if np.any(sel):
+            lat = np.asarray(latency_s, np.float64)[sel]
+            frac = float(np.mean(lat > np.asarray(block, np.float64)[sel] / self.fs))
+            self.closed = frac > (self.target / 2 if self.closed else self.target)
+        self.checks += 1
+        self.closed_checks += int(self.closed)
+
+    def summary(self) -> dict:
+        return {"target_miss_fraction": self.target, "min_block": self.min_block, "checks": self.checks,
+                "closed_fraction_of_checks": round(self.closed_checks / self.checks, 4) if self.checks else 0.0}
+
+
 class RealtimeServer:
     """Serving with one library call per tick (taches_server_tick).
 
@@ -688,7 +719,7 @@ class RealtimeServer:
     def __init__(self, requests, max_streams: int, hbm_budget_bytes: int, precision: int = 0,
                  use_graph: bool = True, max_ir_len: int = 262_144, seed: int = 9,
                  keep_outputs=(), max_blocks_per_step: int = 64, warmup_s: float = 0.0,
-                 segments: bool = True):
+                 segments: bool = True, miss_gate: MissGate = None):
         import torch
         from . import taches as T
         self.T, self.torch = T, torch
@@ -732,6 +763,7 @@ class RealtimeServer:
         self.n_segmented = 0
         self.slow_loops = []   # (clock, admit ms, tick ms, retire ms, admitted) of iterations over 5 ms
         self.admit_s = {"attach": 0.0, "register": 0.0}
+        self.gate = miss_gate        # optional admission gate on observed deadline misses
 
     # -- requests ------------------------------------------------------------
     def _draw_irs(self, req):
@@ -897,6 +929,8 @@ class RealtimeServer:
                 self._prepared[req.rid] = item
         while self.queue and limit > 0:
             req = self.queue[0]
+            if self.gate is not None and self.gate.closed:
+                return
             if len(self.live) >= self.max_streams:
                 with self._lock:   # the preparing thread counts budget refusals
                     self.refused += 1
@@ -964,6 +998,8 @@ class RealtimeServer:
         if lat.size:
             self.lat.append(lat)
             self.lat_b.append(bs)
+            if self.gate is not None:
+                self.gate.update(lat, bs)
 
     # -- driver ----------------------------------------------------------------
     def run_realtime(self, duration_s: float, sleep=time.sleep) -> dict:
@@ -1067,6 +1103,8 @@ class RealtimeServer:
         out["two_segment_requests"] = self.n_segmented
         if self.stats.admitted:
             out["admission_ms_mean"] = {k: round(v / self.stats.admitted * 1e3, 4) for k, v in self.admit_s.items()}
+        if self.gate is not None:
+            out["miss_gate"] = self.gate.summary()
         out["slow_loops"] = {"count": len(self.slow_loops),
                              "longest": sorted(self.slow_loops, key=lambda r: -(r[1] + r[2] + r[3]))[:8]}
         return out

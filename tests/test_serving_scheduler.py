@@ -7,7 +7,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_2401_01607_amd import workloads as W
-from paper_2401_01607_amd.serving import AdmissionRefused, Scheduler
+from paper_2401_01607_amd.serving import AdmissionRefused, MissGate, Scheduler
 
 
 class OracleExecutor:
@@ -258,3 +258,34 @@ def test_two_segments_equal_the_whole_ir(L, B, swaps):
     y = head.copy()
     y[H:] += z[:y.size - H]
     assert np.array_equal(y, whole)
+
+
+def test_miss_gate_closes_above_target_and_reopens_at_half():
+    """The admission gate: closes when more than the target fraction of the
+    blocks of at least min_block samples missed one block period, reopens at
+    half the target or below; shorter blocks do not count."""
+    g = MissGate(0.02, min_block=64)
+    dl = 64 / W.FS
+
+    def batch(n, late, b=64):
+        lat = np.full(n, 0.5 * dl)
+        lat[:late] = 1.5 * dl
+        return lat, np.full(n, b, np.int32)
+
+    g.update(*batch(100, 2))             # 2 % = target: stays open
+    assert not g.closed
+    g.update(*batch(100, 3))             # 3 % > 2 %: closes
+    assert g.closed
+    g.update(*batch(200, 3))             # 1.5 % > 1 %: stays closed
+    assert g.closed
+    g.update(*batch(200, 2))             # 1 % = half the target: reopens
+    assert not g.closed
+    g.update(*batch(50, 50, b=32))       # only short blocks, all late: no change
+    assert not g.closed
+    lat = np.full(10, dl)                # exactly one period is not a miss
+    g.update(lat, np.full(10, 64, np.int32))
+    assert not g.closed
+    s = g.summary()
+    assert s["checks"] == 6 and s["closed_fraction_of_checks"] == round(2 / 6, 4)
+    with pytest.raises(ValueError):
+        MissGate(0.0)
