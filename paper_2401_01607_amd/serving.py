@@ -719,7 +719,7 @@ class RealtimeServer:
     def __init__(self, requests, max_streams: int, hbm_budget_bytes: int, precision: int = 0,
                  use_graph: bool = True, max_ir_len: int = 262_144, seed: int = 9,
                  keep_outputs=(), max_blocks_per_step: int = 64, warmup_s: float = 0.0,
-                 segments: bool = True, miss_gate: MissGate = None):
+                 segments: bool = True, miss_gate: MissGate | None = None):
         import torch
         from . import taches as T
         self.T, self.torch = T, torch
